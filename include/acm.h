@@ -1,0 +1,184 @@
+/*
+ * acm.h - C ABI of the MI355X (gfx950) unit-cell solvers for periodic porous
+ * media, following Karimi & Bhattacharya, "Accelerated Computational
+ * Micromechanics for Reactive Flow in Porous Media" (arXiv 2312.15554).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Unit cell Y = [0,1)^d (Section 2), grid n[0] x n[1] (x n[2]) voxels,
+ *   h_j = 1/n_j.  Every n_j must be one of 8, 16, 24, 32, 48, 64, 96, 128,
+ *   192, 256, 512; nx = n[0] must also be at most 512.  dim is 2 or 3; for
+ *   dim 2 set n[2] = 1.
+ * - Real fields are structure-of-arrays [component][z][y][x], x fastest, in
+ *   the precision selected by `precision` (ACM_FP32: float, ACM_FP64: double).
+ *   Half spectra are [field][z][y][x_half] of interleaved complex values with
+ *   x_half = nx/2 + 1.
+ * - H is the solid indicator of Section 3 (eq. Heaviside): one uint8 per
+ *   voxel, 1 = solid, 0 = pore, same [z][y][x] order.
+ * - ALL array arguments except the small double arrays (g, B0, K, D, mass,
+ *   history) are DEVICE pointers on the current HIP device.  The caller owns
+ *   every buffer; the library owns only its internal workspace and tables.
+ * - `stream` is a hipStream_t (NULL = default stream).  Every call is ordered
+ *   after prior work on `stream` and returns only when its results are
+ *   complete (the call synchronises).
+ * - Derivatives use the central-difference symbol s_j = sin(2 pi m_j/n_j)/h_j
+ *   for first derivatives and the compact symbol 4 sin^2(pi m_j/n_j)/h_j^2 for
+ *   second derivatives (Section 3.2, eq. fft_app), for both problems.
+ * - No exception or abort crosses the ABI.  On a negative status, outputs are
+ *   left untouched and acm_last_error() describes the failure.
+ */
+#ifndef ACM_H_
+#define ACM_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ACM_OK = 0,
+  ACM_NOT_CONVERGED = 1,       /* max_iter reached; outputs hold the last iterate */
+  ACM_E_INVALID = -1,          /* bad argument (null pointer, bad dim, all-pore H, ...) */
+  ACM_E_UNSUPPORTED_SIZE = -2, /* grid length not in the supported set */
+  ACM_E_NOMEM = -3,            /* device allocation failed */
+  ACM_E_HIP = -4,              /* a HIP runtime call failed */
+  ACM_E_DIVERGED = -5          /* a residual became non-finite */
+} acm_status;
+
+enum { ACM_FP32 = 0, ACM_FP64 = 1 };
+
+typedef struct {
+  int32_t dim;  /* 2 or 3 */
+  int32_t n[3]; /* nx, ny, nz (nz = 1 when dim = 2) */
+} acm_grid;
+
+/* ADMM penalties (Section 3.1, eq. Lagrangian with auxiliary variable) and
+ * their adaptive update (Section 4.1, eq. varying algorithm).  Order of every
+ * triple: {alpha, beta, b}; alpha pairs with constraint 1 (ut = 0 in the
+ * solid), beta with constraint 2 (div u = 0), b with constraint 3 (u = ut). */
+typedef struct {
+  double alpha, beta, b;  /* initial penalties; <= 0 selects nu * max(n) */
+  double phi[3];          /* growth factors (paper: 1.1) */
+  double tau[3];          /* ratio thresholds (paper: {20,10,30} model cell, {5,10,5} random) */
+  double psi_min[3];      /* floors; <= 0 selects 1e-3 * initial value */
+  int32_t adaptive;       /* 0: fixed penalties */
+} acm_penalty;
+
+typedef struct {
+  double eps;           /* epsilon = eps_abs = eps_rel of the stopping test (Section 3.1, Step 4) */
+  int64_t max_iter;     /* iteration cap (per time step for transport) */
+  int32_t precision;    /* ACM_FP32 or ACM_FP64: field and transform precision */
+  int32_t check_every;  /* iterations between host convergence checks; 0 = automatic */
+  int32_t warm_start;   /* Stokes only: 1 = u (and q if non-NULL) hold an initial guess */
+  int32_t use_graph;    /* 1 = replay the iterations as a captured HIP graph */
+  int32_t profile;      /* 1 = launch eagerly and time every kernel kind with HIP events */
+  int32_t history_cap;  /* > 0: keep the residuals of the last history_cap iterations */
+} acm_opts;
+
+/* Kernel kinds reported in acm_stats.kernel_ms (with opts.profile = 1). */
+enum {
+  ACM_K_GREEN = 0,   /* Stokes: last-axis FFT pair + Step 1 + q update */
+  ACM_K_LOCAL = 1,   /* Stokes: x inverse transform + Steps 2-3 (+ Step 4) */
+  ACM_K_RHS = 2,     /* Stokes: right-hand side of Step 1 + x forward transform */
+  ACM_K_YINV = 3,    /* y inverse transform (3D) */
+  ACM_K_YFWD = 4,    /* y forward transform (3D) */
+  ACM_K_T_GREEN = 5, /* transport: last-axis FFT pair + LS update */
+  ACM_K_T_LOCAL = 6, /* transport: x transforms + local residual F */
+  ACM_K_OTHER = 7
+};
+
+typedef struct {
+  int64_t iters;        /* iterations performed (summed over time steps for transport) */
+  double r_p[3], r_d[3];        /* last primal/dual residuals (transport: r_1, r_2 in r_p[0..1]) */
+  double tol_p[3], tol_d[3];    /* their tolerances */
+  double psi[3];                /* penalties after the last iteration */
+  double seconds;               /* wall time of the iteration loop */
+  int32_t converged;
+  int32_t status;
+  double kernel_ms[8];          /* opts.profile: summed kernel time per kind */
+  int64_t kernel_calls[8];
+} acm_stats;
+
+/* Fill *p / *o with the defaults (adaptive, phi = 1.1, tau = {5,10,5},
+ * eps = 1e-6, FP32, HIP graph on). */
+void acm_default_penalty(acm_penalty* p);
+void acm_default_opts(acm_opts* o);
+
+/* Message of the last failing call on this thread ("" if none).  Valid until
+ * the next call on the same thread. */
+const char* acm_last_error(void);
+
+/* ABI version (incremented on any signature change). */
+int32_t acm_version(void);
+
+/*
+ * Unit-cell Stokes flow (Section 2, eq. unit cell, first two lines) solved on
+ * the extended domain by ADMM (Section 3.1: Steps 1-4, eq. FFT step1,
+ * eq. u_tilde, eq. Lagrange-multipliers, eq. constrains) with adaptive
+ * penalties (Section 4.1, eq. varying algorithm).
+ *   grid   cell size; H   solid indicator (device, ntot bytes, needs >= 1 solid voxel)
+ *   g_p    body force / imposed pressure gradient, dim entries used
+ *   nu     viscosity (> 0)
+ *   pen    penalties (NULL = defaults); opts (NULL = defaults)
+ *   u      inout device field, dim components: on entry the initial guess if
+ *          opts->warm_start, otherwise ignored; on exit the velocity.
+ *   q      out device scalar field (may be NULL): the pressure multiplier q.
+ *          With warm_start it is also read as the initial guess.
+ *   stats  out (may be NULL); history: host array of history_cap*15 doubles
+ *          (may be NULL): per iteration r_p[3], r_d[3], tol_p[3], tol_d[3],
+ *          psi[3], oldest first.
+ * Convergence: every residual within its tolerance (all six, Step 4).
+ * Returns ACM_OK, ACM_NOT_CONVERGED (outputs valid), or a negative status.
+ */
+acm_status acm_stokes_solve(const acm_grid* grid, const uint8_t* H, const double* g_p, double nu,
+                            const acm_penalty* pen, const acm_opts* opts, void* u, void* q,
+                            acm_stats* stats, double* history, void* stream);
+
+/*
+ * Penalised advection-diffusion (Section 3.2, eq. penalization) by the
+ * Lippmann-Schwinger iteration (eq. iter solved by eq. fft_solute, stopping
+ * test eq. tol_solute):
+ *   A = diffusivity (1-H) + eta H,  B = Pe (1-H) u,  calF = Pe (1-H) ubar . g_chi.
+ *   dt = +INFINITY: the steady cell problem (mean-zero chi); n_steps must be 1.
+ *   dt finite: n_steps backward-Euler steps of d chi/dt + operator = calF,
+ *   each converged by the LS iteration with comparison symbol
+ *   1/dt + A0 L + i B0 . s.
+ *   u    device flow field (dim components, as passed: no normalisation)
+ *   chi  inout device scalar field: initial value on entry, result on exit.
+ *   A0 > 0; B0: dim entries (host).
+ */
+acm_status acm_transport_step(const acm_grid* grid, const uint8_t* H, const void* u,
+                              const double* g_chi, double Pe, double diffusivity, double eta,
+                              double A0, const double* B0, double dt, int32_t n_steps,
+                              const acm_opts* opts, void* chi, acm_stats* stats, void* stream);
+
+/*
+ * Effective properties (Section 2, eq. K and eq. D), FP64 reductions.
+ *   K (host, n_flow x dim, row i = flow i):  K_ij = (1/nu) h^d sum_Y u^i_j
+ *     (equals the integral of grad u^i . grad u^j at a converged solution).
+ *   D (host, dim x n_chi, column j = chi^j):
+ *     D_ij = porosity delta_ij + Pe h^d sum_pore (ubar_i - u_i) chi^j
+ *            + h^d sum_pore (grad_c chi^j)_i
+ *     with u = u_transport (the flow used for chi) and grad_c the central
+ *     difference.  mass (host, n_chi): h^d sum_Y chi^j.
+ *   Any of K / D / mass may be NULL to skip it.
+ */
+acm_status acm_effective_props(const acm_grid* grid, int32_t precision, const uint8_t* H,
+                               int32_t n_flow, const void* const* u, int32_t n_chi,
+                               const void* const* chi, const void* u_transport, double nu,
+                               double Pe, double* K, double* D, double* mass, void* stream);
+
+/* Multi-dimensional real FFT of nfields fields (forward unnormalised /
+ * inverse normalised by 1/ntot), half spectra as described above.  These are
+ * the transforms every solver pass is built from. */
+acm_status acm_fft_r2c(const acm_grid* grid, int32_t precision, int32_t nfields, const void* in,
+                       void* out, void* stream);
+acm_status acm_fft_c2r(const acm_grid* grid, int32_t precision, int32_t nfields, const void* in,
+                       void* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACM_H_ */

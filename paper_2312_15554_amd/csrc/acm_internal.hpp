@@ -1,0 +1,134 @@
+// Internal declarations shared by the HIP kernels and the host runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace acm {
+
+// Geometry of one periodic cell.  Real fields: [comp][z][y][x], x fastest.
+// Half spectra (after the x real-to-complex pass): [comp][z][y][xh] with
+// xh = nx/2 + 1.  For dim == 2, nz == 1 and the "last axis" is y.
+struct Geom {
+  int dim;
+  int nx, ny, nz;
+  int xh;            // nx/2 + 1
+  int64_t ntot;      // nx*ny*nz
+  int64_t nrows;     // ny*nz  (x rows per component)
+  int64_t nspec;     // nz*ny*xh complex values per component
+  int last_n;        // length of the last axis (nz in 3D, ny in 2D)
+  int64_t plane;     // complex values per index of the last axis (ny*xh in 3D, xh in 2D)
+};
+
+// Per-cell device tables (working precision T): FFT twiddles for the three
+// lengths used (nx/2, ny, nz), the real-transform twiddles W^k = exp(-2 pi i k/nx)
+// for k in [0, nx/2], and the per-axis derivative symbols
+// s(m) = sin(2 pi m/n)/h and l(m) = 4 sin^2(pi m/n)/h^2.
+struct TableOffsets {
+  int tw_x;    // complex offsets into the complex table
+  int tw_y;
+  int tw_z;
+  int rtw;
+  int ncomplex;
+  int sx, lx, sy, ly, sz, lz;  // real offsets into the real table
+  int nreal;
+};
+
+// Device control block for one ADMM solve.  Written by the host before the
+// first iteration; afterwards only the finalize step (last workgroup of the
+// local pass) changes it.
+struct StokesCtl {
+  double psi[3];      // alpha, beta, b of the current iteration
+  double c_prev;      // b/(b+alpha) of the previous iteration
+  double phi[3], tau[3], psi_min[3];
+  double eps;
+  double sqrt_n[3];   // sqrt(d N), sqrt(N), sqrt(d N)
+  double nu;
+  double g[3];
+  double rp[3], rd[3], tp[3], td[3], mu[3];
+  int64_t iter;
+  int64_t max_iter;
+  int32_t done;
+  int32_t status;     // 0 ok, 1 not converged, -5 diverged
+  int32_t adaptive;
+  uint32_t counter;   // workgroups of the local pass that have finished
+  int32_t hist_cap;   // capacity of the residual history ring (entries)
+  int32_t pad_;
+};
+
+// One history record per iteration: rp[3], rd[3], tp[3], td[3], psi[3].
+constexpr int kHistDoubles = 15;
+
+// Control block for one Lippmann-Schwinger solve (one time step at a time).
+struct TransportCtl {
+  double eps;
+  double sqrt_n1, sqrt_n2;
+  double inv_dt;        // 0 for the steady cell problem
+  double A0, B0[3];
+  double g[3];
+  double Pe, eta, diff;
+  double calF;          // Pe * ubar . g  (multiplied by (1-H) per voxel)
+  double r1, r2;
+  int64_t iter;         // iterations in the current time step
+  int64_t total_iter;
+  int64_t max_iter;
+  int32_t done;
+  int32_t status;
+  uint32_t counter;
+  int32_t steady;
+};
+
+enum KernelKind {
+  KK_GREEN = 0,
+  KK_LOCAL = 1,
+  KK_RHS = 2,
+  KK_YINV = 3,
+  KK_YFWD = 4,
+  KK_T_GREEN = 5,
+  KK_T_LOCAL = 6,
+  KK_OTHER = 7,
+  KK_COUNT = 8
+};
+
+// ----------------------------------------------------------------- launchers
+// All return hipSuccess or an error; an unsupported length returns
+// hipErrorInvalidValue.
+
+template <typename T>
+struct DevTables {
+  const void* ctab;  // cplx<T>[ncomplex]
+  const T* rtab;     // T[nreal]
+  TableOffsets off;
+};
+
+bool fft_length_supported(int n);
+
+// Plain transforms (utility; init and readout).
+template <typename T>
+hipError_t launch_rows_r2c(const Geom& g, const DevTables<T>& tb, int nfields, const T* in,
+                           void* out, hipStream_t s);
+template <typename T>
+hipError_t launch_rows_c2r(const Geom& g, const DevTables<T>& tb, int nfields, const void* in,
+                           T* out, double scale, hipStream_t s);
+// Complex transform along y (axis 1) or z (axis 2) of nfields half spectra, in place.
+template <typename T>
+hipError_t launch_cols(const Geom& g, const DevTables<T>& tb, int axis, int sign, int nfields,
+                       void* data, hipStream_t s);
+
+// Stokes ADMM passes.
+template <typename T>
+hipError_t launch_stokes_green(const Geom& g, const DevTables<T>& tb, void* spec, void* qhat,
+                               void* dhat, double* partials, StokesCtl* ctl, int* nblocks,
+                               hipStream_t s);
+template <typename T>
+hipError_t launch_stokes_local(const Geom& g, const DevTables<T>& tb, const void* spec, T* u,
+                               T* a, const uint8_t* H, double* partials, int green_blocks,
+                               StokesCtl* ctl, double* hist, int* nblocks, hipStream_t s);
+template <typename T>
+hipError_t launch_stokes_rhs(const Geom& g, const DevTables<T>& tb, void* spec, const T* u,
+                             const T* a, const uint8_t* H, StokesCtl* ctl, hipStream_t s);
+
+// Grid-size helpers used by the host to size partial-sum buffers.
+int stokes_green_blocks(const Geom& g, int precision_bytes);
+int stokes_local_blocks(const Geom& g, int precision_bytes);
+
+}  // namespace acm

@@ -1,0 +1,194 @@
+// Plain multi-dimensional FFT passes (no physics): real x rows <-> half
+// spectra, and complex transforms along y or z.  Used to set up and read out
+// the solvers and exposed through the C ABI for testing.
+#include "pass_common.hpp"
+
+namespace acm {
+
+bool fft_length_supported(int n) {
+  switch (n) {
+#define CASE(L) case L:
+    ACM_COL_LENGTHS(CASE)
+#undef CASE
+    return true;
+    default:
+      return false;
+  }
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_rows_r2c(const T* __restrict__ in,
+                                                               cplx<T>* __restrict__ out,
+                                                               int nrows, int64_t ntot,
+                                                               int64_t nspec,
+                                                               const cplx<T>* __restrict__ tw,
+                                                               const cplx<T>* __restrict__ rtw) {
+  using C = RowCfg<T, M>;
+  extern __shared__ __align__(16) char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  T* ldsr = reinterpret_cast<T*>(smem_raw);
+  const int field = blockIdx.y;
+  const int row0 = blockIdx.x * C::RB;
+  const int nr = min(C::RB, nrows - row0);
+  const T* src = in + field * ntot + (int64_t)row0 * (2 * M);
+  for (int v = threadIdx.x; v < nr * 2 * M; v += C::NT) {
+    const int r = v / (2 * M), x = v - r * (2 * M);
+    ldsr[r * 2 * C::RP + x] = src[v];
+  }
+  __syncthreads();
+  const int row = threadIdx.x / C::TPP, t = threadIdx.x % C::TPP;
+  rows_r2c_lds<T, M>(lds, row, t, row < nr, tw, rtw);
+  cplx<T>* dst = out + field * nspec + (int64_t)row0 * (M + 1);
+  for (int v = threadIdx.x; v < nr * (M + 1); v += C::NT) dst[v] = lds[v];
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_rows_c2r(const cplx<T>* __restrict__ in,
+                                                               T* __restrict__ out, int nrows,
+                                                               int64_t ntot, int64_t nspec,
+                                                               T scale,
+                                                               const cplx<T>* __restrict__ tw,
+                                                               const cplx<T>* __restrict__ rtw) {
+  using C = RowCfg<T, M>;
+  extern __shared__ __align__(16) char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  T* ldsr = reinterpret_cast<T*>(smem_raw);
+  const int field = blockIdx.y;
+  const int row0 = blockIdx.x * C::RB;
+  const int nr = min(C::RB, nrows - row0);
+  const cplx<T>* src = in + field * nspec + (int64_t)row0 * (M + 1);
+  for (int v = threadIdx.x; v < nr * (M + 1); v += C::NT) lds[v] = src[v];
+  __syncthreads();
+  const int row = threadIdx.x / C::TPP, t = threadIdx.x % C::TPP;
+  rows_c2r_lds<T, M>(lds, row, t, row < nr, tw, rtw);
+  T* dst = out + field * ntot + (int64_t)row0 * (2 * M);
+  for (int v = threadIdx.x; v < nr * 2 * M; v += C::NT) {
+    const int r = v / (2 * M), x = v - r * (2 * M);
+    dst[v] = ldsr[r * 2 * C::RP + x] * scale;
+  }
+}
+
+template <typename T, int L, int SIGN>
+__global__ __launch_bounds__((ColCfg<T, L, 1>::NT)) void k_cols(cplx<T>* __restrict__ data,
+                                                              int64_t field_stride, ColMap m,
+                                                              const cplx<T>* __restrict__ tw) {
+  using C = ColCfg<T, L, 1>;
+  extern __shared__ __align__(16) char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* base = data + blockIdx.y * field_stride;
+  const int f0 = blockIdx.x * C::TX;
+  for (int e = threadIdx.x; e < L * C::TX; e += C::NT) {
+    const int i = e / C::TX, col = e - i * C::TX;
+    const int f = f0 + col;
+    if (f < m.ncols) lds[e] = base[col_base(m, f) + i * m.as];
+  }
+  __syncthreads();
+  const int t = threadIdx.x / C::TX, col = threadIdx.x % C::TX;
+  PencilFFT<T, L, 1, SIGN>::run_lds(t, t < C::TPP && f0 + col < m.ncols, lds + col, 0, C::TX, tw);
+  __syncthreads();
+  for (int e = threadIdx.x; e < L * C::TX; e += C::NT) {
+    const int i = e / C::TX, col = e - i * C::TX;
+    const int f = f0 + col;
+    if (f < m.ncols) base[col_base(m, f) + i * m.as] = lds[e];
+  }
+}
+
+template <typename T>
+hipError_t launch_rows_r2c(const Geom& g, const DevTables<T>& tb, int nfields, const T* in,
+                           void* out, hipStream_t s) {
+  const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
+  switch (g.nx / 2) {
+#define CASE(M)                                                                            \
+  case M: {                                                                                \
+    using C = RowCfg<T, M>;                                                                \
+    dim3 grid((unsigned)((g.nrows + C::RB - 1) / C::RB), (unsigned)nfields);               \
+    hipLaunchKernelGGL((k_rows_r2c<T, M>), grid, dim3(C::NT), C::LDS_BYTES, s, in,          \
+                       reinterpret_cast<cplx<T>*>(out), (int)g.nrows, g.ntot, g.nspec,      \
+                       ct + tb.off.tw_x, ct + tb.off.rtw);                                  \
+    return hipGetLastError();                                                              \
+  }
+    ACM_ROW_LENGTHS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_rows_c2r(const Geom& g, const DevTables<T>& tb, int nfields, const void* in,
+                           T* out, double scale, hipStream_t s) {
+  const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
+  switch (g.nx / 2) {
+#define CASE(M)                                                                            \
+  case M: {                                                                                \
+    using C = RowCfg<T, M>;                                                                \
+    dim3 grid((unsigned)((g.nrows + C::RB - 1) / C::RB), (unsigned)nfields);               \
+    hipLaunchKernelGGL((k_rows_c2r<T, M>), grid, dim3(C::NT), C::LDS_BYTES, s,              \
+                       reinterpret_cast<const cplx<T>*>(in), out, (int)g.nrows, g.ntot,     \
+                       g.nspec, (T)scale, ct + tb.off.tw_x, ct + tb.off.rtw);               \
+    return hipGetLastError();                                                              \
+  }
+    ACM_ROW_LENGTHS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_cols(const Geom& g, const DevTables<T>& tb, int axis, int sign, int nfields,
+                       void* data, hipStream_t s) {
+  const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
+  ColMap m;
+  int L;
+  const cplx<T>* tw;
+  if (axis == 1) {
+    L = g.ny;
+    m.inner = g.xh;
+    m.outer = g.ny * g.xh;
+    m.as = g.xh;
+    m.ncols = g.nz * g.xh;
+    tw = ct + tb.off.tw_y;
+  } else if (axis == 2 && g.dim == 3) {
+    L = g.nz;
+    m.inner = g.ny * g.xh;
+    m.outer = 0;
+    m.as = g.ny * g.xh;
+    m.ncols = g.ny * g.xh;
+    tw = ct + tb.off.tw_z;
+  } else {
+    return hipErrorInvalidValue;
+  }
+  cplx<T>* d = reinterpret_cast<cplx<T>*>(data);
+  switch (L) {
+#define CASE(LL)                                                                            \
+  case LL: {                                                                                \
+    using C = ColCfg<T, LL, 1>;                                                             \
+    dim3 grid((unsigned)((m.ncols + C::TX - 1) / C::TX), (unsigned)nfields);                \
+    if (sign < 0)                                                                           \
+      hipLaunchKernelGGL((k_cols<T, LL, -1>), grid, dim3(C::NT), C::LDS_BYTES, s, d,         \
+                         g.nspec, m, tw);                                                   \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_cols<T, LL, 1>), grid, dim3(C::NT), C::LDS_BYTES, s, d, g.nspec, \
+                         m, tw);                                                            \
+    return hipGetLastError();                                                               \
+  }
+    ACM_COL_LENGTHS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+#define INST(T)                                                                              \
+  template hipError_t launch_rows_r2c<T>(const Geom&, const DevTables<T>&, int, const T*,    \
+                                         void*, hipStream_t);                                \
+  template hipError_t launch_rows_c2r<T>(const Geom&, const DevTables<T>&, int, const void*, \
+                                         T*, double, hipStream_t);                           \
+  template hipError_t launch_cols<T>(const Geom&, const DevTables<T>&, int, int, int, void*, \
+                                     hipStream_t);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace acm

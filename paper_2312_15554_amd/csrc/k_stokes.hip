@@ -1,0 +1,454 @@
+// Fused passes of the ADMM iteration for unit-cell Stokes flow (Section 3.1,
+// Steps 1-4, with the adaptive penalties of Section 4.1).
+//
+// State kept on the device per voxel: u (= u^n, the previous velocity) and a.
+// Steps 2 and 3 imply, exactly, that after one iteration a = 0 and ut = u in
+// the pore while a = lambda and ut = b/(b+alpha) u in the solid (given
+// a^0 = lambda^0 supported in the solid and u^0 = 0 there).  So ut and lambda
+// are never stored; q lives only as its spectrum q-hat.
+//
+// One iteration n:
+//   green  (last axis): r-hat + N g delta_k0 - i s q-hat -> Step 1 solved per
+//           mode with M = (nu L + b) I + beta s s^T (Sherman-Morrison), Step 3
+//           for q-hat, Parseval sums for |div u|, |div u - div u_prev|, |q|.
+//   [y inverse in 3D]
+//   local  (x rows): inverse x transform gives u^{n+1}; Steps 2-3 pointwise;
+//           sums for the residuals; the last workgroup runs Step 4 and the
+//           penalty update (eq. varying algorithm).
+//   rhs    (x rows): r = b^{n+1} ut^{n+1} - a^{n+1}, forward x transform.
+//   [y forward in 3D]
+#include "pass_common.hpp"
+
+namespace acm {
+
+struct GreenGeom {
+  int dim;
+  int nx, xh;
+  int plane;   // pencils along the last axis
+  int64_t nspec;
+  int64_t ntot;
+};
+
+template <typename T, int L, int NC>
+__global__ __launch_bounds__((ColCfg<T, L, NC>::NT)) void k_stokes_green(
+    cplx<T>* __restrict__ spec, cplx<T>* __restrict__ qhat, cplx<T>* __restrict__ dhat,
+    double* __restrict__ partials, const StokesCtl* __restrict__ ctl, GreenGeom gg,
+    const cplx<T>* __restrict__ tw, const T* __restrict__ sx, const T* __restrict__ lx,
+    const T* __restrict__ sy, const T* __restrict__ ly, const T* __restrict__ sz,
+    const T* __restrict__ lz) {
+  using C = ColCfg<T, L, NC>;
+  constexpr int PS = L * C::TX;  // LDS pencil-set stride per field
+  extern __shared__ __align__(16) char smem_raw[];
+  __shared__ double red[3 * 16];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  if (ctl->done) return;
+  const T beta = (T)ctl->psi[1];
+  const T bpen = (T)ctl->psi[2];
+  const T nu = (T)ctl->nu;
+  const int P = gg.plane;
+  const int f0 = blockIdx.x * C::TX;
+
+  for (int e = threadIdx.x; e < NC * PS; e += C::NT) {
+    const int c = e / PS, rem = e - c * PS;
+    const int i = rem / C::TX, col = rem - i * C::TX;
+    const int f = f0 + col;
+    cplx<T> v = cmake<T>(T(0), T(0));
+    if (f < P) v = spec[c * gg.nspec + (int64_t)i * P + f];
+    lds[e] = v;
+  }
+  __syncthreads();
+  const int t = threadIdx.x / C::TX, colt = threadIdx.x % C::TX;
+  const bool act = t < C::TPP && f0 + colt < P;
+  PencilFFT<T, L, NC, -1>::run_lds(t, act, lds + colt, PS, C::TX, tw);
+  __syncthreads();
+
+  double acc[3] = {0.0, 0.0, 0.0};
+  const T inv_ntot = T(1.0 / (double)gg.ntot);
+  for (int e = threadIdx.x; e < PS; e += C::NT) {
+    const int i = e / C::TX, col = e - i * C::TX;
+    const int f = f0 + col;
+    if (f >= P) continue;
+    int kx, ky, kz;
+    if (NC == 3) {
+      kx = f % gg.xh;
+      ky = f / gg.xh;
+      kz = i;
+    } else {
+      kx = f;
+      ky = i;
+      kz = 0;
+    }
+    T s[NC];
+    s[0] = sx[kx];
+    s[1] = sy[ky];
+    T Lk = lx[kx] + ly[ky];
+    if constexpr (NC == 3) {
+      s[2] = sz[kz];
+      Lk += lz[kz];
+    }
+    const double w = (kx == 0 || 2 * kx == gg.nx) ? 1.0 : 2.0;
+    const int64_t mi = (int64_t)i * P + f;
+    const cplx<T> q = qhat[mi];
+    const cplx<T> dp = dhat[mi];
+    cplx<T> R[NC];
+    const bool k0 = (kx == 0 && ky == 0 && kz == 0);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      cplx<T> r = lds[c * PS + e];
+      // - i s_c q
+      r.x += s[c] * q.y;
+      r.y -= s[c] * q.x;
+      if (k0) r.x += (T)((double)gg.ntot * ctl->g[c]);
+      R[c] = r;
+    }
+    const T c0 = nu * Lk + bpen;
+    cplx<T> sr = cmake<T>(T(0), T(0));
+    T ss = T(0);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      sr.x += s[c] * R[c].x;
+      sr.y += s[c] * R[c].y;
+      ss += s[c] * s[c];
+    }
+    const T den = c0 + beta * ss;
+    const T inv_den = T(1) / den;
+    const cplx<T> coef = cscale(sr, beta * inv_den);
+    const T inv_c0 = T(1) / c0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      cplx<T> uc = cmake<T>((R[c].x - s[c] * coef.x) * inv_c0, (R[c].y - s[c] * coef.y) * inv_c0);
+      lds[c * PS + e] = cscale(uc, inv_ntot);
+    }
+    // div u-hat = i s . u-hat = i (s . R) / den
+    const cplx<T> dl = cmake<T>(-sr.y * inv_den, sr.x * inv_den);
+    const cplx<T> qn = cmake<T>(q.x - beta * dl.x, q.y - beta * dl.y);
+    qhat[mi] = qn;
+    dhat[mi] = dl;
+    const double ddx = (double)dl.x - (double)dp.x, ddy = (double)dl.y - (double)dp.y;
+    acc[0] += w * ((double)dl.x * dl.x + (double)dl.y * dl.y);
+    acc[1] += w * (ddx * ddx + ddy * ddy);
+    acc[2] += w * ((double)qn.x * qn.x + (double)qn.y * qn.y);
+  }
+  __syncthreads();
+  PencilFFT<T, L, NC, 1>::run_lds(t, act, lds + colt, PS, C::TX, tw);
+  __syncthreads();
+  for (int e = threadIdx.x; e < NC * PS; e += C::NT) {
+    const int c = e / PS, rem = e - c * PS;
+    const int i = rem / C::TX, col = rem - i * C::TX;
+    const int f = f0 + col;
+    if (f < P) spec[c * gg.nspec + (int64_t)i * P + f] = lds[e];
+  }
+  block_sum<3>(acc, red);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x * 3 + 0] = acc[0];
+    partials[blockIdx.x * 3 + 1] = acc[1];
+    partials[blockIdx.x * 3 + 2] = acc[2];
+  }
+}
+
+// Step 4 and the penalty update, run by the last workgroup of the local pass.
+__device__ void stokes_finalize(StokesCtl* ctl, const double* __restrict__ gpart, int ngreen,
+                                const double* __restrict__ lpart, int nlocal, int64_t ntot,
+                                double* hist, double* red) {
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int j = threadIdx.x; j < ngreen; j += blockDim.x) {
+    acc[0] += gpart[j * 3 + 0];
+    acc[1] += gpart[j * 3 + 1];
+    acc[2] += gpart[j * 3 + 2];
+  }
+  for (int j = threadIdx.x; j < nlocal; j += blockDim.x) {
+    acc[3] += lpart[j * 4 + 0];
+    acc[4] += lpart[j * 4 + 1];
+    acc[5] += lpart[j * 4 + 2];
+    acc[6] += lpart[j * 4 + 3];
+  }
+  block_sum<7>(acc, red);
+  if (threadIdx.x != 0) return;
+  const double inv_n = 1.0 / (double)ntot;
+  const double s_div = acc[0] * inv_n, s_ddiv = acc[1] * inv_n, s_q = acc[2] * inv_n;
+  const double s_su2 = acc[3], s_sd = acc[4], s_a2 = acc[5], s_du = acc[6];
+  const double al = ctl->psi[0], be = ctl->psi[1], bb = ctl->psi[2];
+  const double cc = bb / (bb + al);
+  const double one_m_cc = al / (bb + al);
+  const double nsu = sqrt(s_su2);
+  double rp[3] = {cc * nsu, sqrt(s_div), one_m_cc * nsu};
+  double rd[3] = {al * sqrt(s_sd), be * sqrt(s_ddiv), bb * sqrt(s_du)};
+  double mu[3] = {sqrt(s_a2), sqrt(s_q), sqrt(s_a2)};
+  const double eps = ctl->eps;
+  bool ok = true, finite = true;
+  for (int k = 0; k < 3; ++k) {
+    const double tp = ctl->sqrt_n[k] * eps + eps * fmax(rp[k], mu[k]);
+    const double td = ctl->sqrt_n[k] * eps + eps * mu[k];
+    ctl->rp[k] = rp[k];
+    ctl->rd[k] = rd[k];
+    ctl->tp[k] = tp;
+    ctl->td[k] = td;
+    ctl->mu[k] = mu[k];
+    if (!(rp[k] <= tp && rd[k] <= td)) ok = false;
+    if (!isfinite(rp[k]) || !isfinite(rd[k])) finite = false;
+  }
+  const int64_t it = ctl->iter + 1;
+  ctl->iter = it;
+  if (hist != nullptr && ctl->hist_cap > 0) {
+    double* hrec = hist + ((it - 1) % ctl->hist_cap) * kHistDoubles;
+    for (int k = 0; k < 3; ++k) {
+      hrec[k] = rp[k];
+      hrec[3 + k] = rd[k];
+      hrec[6 + k] = ctl->tp[k];
+      hrec[9 + k] = ctl->td[k];
+      hrec[12 + k] = ctl->psi[k];
+    }
+  }
+  ctl->c_prev = cc;
+  if (!finite) {
+    ctl->done = 1;
+    ctl->status = -5;
+  } else if (ok) {
+    ctl->done = 1;
+    ctl->status = 0;
+  } else if (it >= ctl->max_iter) {
+    ctl->done = 1;
+    ctl->status = 1;
+  } else if (ctl->adaptive) {
+    for (int k = 0; k < 3; ++k) {
+      if (rp[k] > ctl->tau[k] * rd[k])
+        ctl->psi[k] = ctl->phi[k] * ctl->psi[k];
+      else if (rd[k] > ctl->tau[k] * rp[k])
+        ctl->psi[k] = fmax(ctl->psi[k] / ctl->phi[k], ctl->psi_min[k]);
+    }
+  }
+  ctl->counter = 0u;
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_stokes_local(
+    const cplx<T>* __restrict__ spec, T* __restrict__ u, T* __restrict__ a,
+    const uint8_t* __restrict__ H, double* __restrict__ lpart, const double* __restrict__ gpart,
+    int ngreen, StokesCtl* ctl, double* hist, int nrows, int64_t ntot, int64_t nspec,
+    const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ rtw) {
+  using C = RowCfg<T, M>;
+  constexpr int NX = 2 * M;
+  extern __shared__ __align__(16) char smem_raw[];
+  __shared__ double red[7 * 16];
+  __shared__ int s_last;
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  T* ldsr = reinterpret_cast<T*>(smem_raw);
+  if (ctl->done) return;
+  const double al = ctl->psi[0], bb = ctl->psi[2];
+  const T cc = (T)(bb / (bb + al));
+  const T cp = (T)ctl->c_prev;
+  const T ka = (T)(bb * al / (bb + al));
+  const int field = blockIdx.y;
+  const int row0 = blockIdx.x * C::RB;
+  const int nr = min(C::RB, nrows - row0);
+  const cplx<T>* src = spec + field * nspec + (int64_t)row0 * (M + 1);
+  for (int v = threadIdx.x; v < nr * (M + 1); v += C::NT) lds[v] = src[v];
+  __syncthreads();
+  const int row = threadIdx.x / C::TPP, t = threadIdx.x % C::TPP;
+  rows_c2r_lds<T, M>(lds, row, t, row < nr, tw, rtw);
+
+  const int64_t off = field * ntot + (int64_t)row0 * NX;
+  T* ur = u + off;
+  T* ar = a + off;
+  const uint8_t* hr = H + (int64_t)row0 * NX;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int v = threadIdx.x; v < nr * NX; v += C::NT) {
+    const int r = v / NX, x = v - r * NX;
+    const T un = ldsr[r * 2 * C::RP + x];
+    const T up = ur[v];
+    const T du = un - up;
+    acc[3] += (double)du * du;
+    ur[v] = un;
+    if (hr[v]) {
+      const T an = ar[v] + ka * un;
+      ar[v] = an;
+      const T dd = cc * un - cp * up;
+      acc[0] += (double)un * un;
+      acc[1] += (double)dd * dd;
+      acc[2] += (double)an * an;
+    }
+  }
+  block_sum<4>(acc, red);
+  const int nblk = gridDim.x * gridDim.y;
+  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+  if (threadIdx.x == 0) {
+    lpart[bid * 4 + 0] = acc[0];
+    lpart[bid * 4 + 1] = acc[1];
+    lpart[bid * 4 + 2] = acc[2];
+    lpart[bid * 4 + 3] = acc[3];
+    __threadfence();
+    const unsigned prev = atomicAdd(&ctl->counter, 1u);
+    s_last = (prev == (unsigned)(nblk - 1)) ? 1 : 0;
+  }
+  __syncthreads();
+  if (s_last) {
+    __threadfence();
+    stokes_finalize(ctl, gpart, ngreen, lpart, nblk, ntot, hist, red);
+  }
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_stokes_rhs(
+    cplx<T>* __restrict__ spec, const T* __restrict__ u, const T* __restrict__ a,
+    const uint8_t* __restrict__ H, const StokesCtl* __restrict__ ctl, int nrows, int64_t ntot,
+    int64_t nspec, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ rtw) {
+  using C = RowCfg<T, M>;
+  constexpr int NX = 2 * M;
+  extern __shared__ __align__(16) char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  T* ldsr = reinterpret_cast<T*>(smem_raw);
+  if (ctl->done) return;
+  const T bb = (T)ctl->psi[2];
+  const T bcp = (T)(ctl->psi[2] * ctl->c_prev);
+  const int field = blockIdx.y;
+  const int row0 = blockIdx.x * C::RB;
+  const int nr = min(C::RB, nrows - row0);
+  const int64_t off = field * ntot + (int64_t)row0 * NX;
+  const T* ur = u + off;
+  const T* ar = a + off;
+  const uint8_t* hr = H + (int64_t)row0 * NX;
+  for (int v = threadIdx.x; v < nr * NX; v += C::NT) {
+    const int r = v / NX, x = v - r * NX;
+    const T un = ur[v];
+    ldsr[r * 2 * C::RP + x] = hr[v] ? (bcp * un - ar[v]) : (bb * un);
+  }
+  __syncthreads();
+  const int row = threadIdx.x / C::TPP, t = threadIdx.x % C::TPP;
+  rows_r2c_lds<T, M>(lds, row, t, row < nr, tw, rtw);
+  cplx<T>* dst = spec + field * nspec + (int64_t)row0 * (M + 1);
+  for (int v = threadIdx.x; v < nr * (M + 1); v += C::NT) dst[v] = lds[v];
+}
+
+// ------------------------------------------------------------------ launchers
+template <int L, typename T>
+static int green_blocks_for(const Geom& g) {
+  if (g.dim == 3) return (int)((g.plane + ColCfg<T, L, 3>::TX - 1) / ColCfg<T, L, 3>::TX);
+  return (int)((g.plane + ColCfg<T, L, 2>::TX - 1) / ColCfg<T, L, 2>::TX);
+}
+
+int stokes_green_blocks(const Geom& g, int prec_bytes) {
+  switch (g.last_n) {
+#define CASE(LL) \
+  case LL:       \
+    return prec_bytes == 8 ? green_blocks_for<LL, double>(g) : green_blocks_for<LL, float>(g);
+    ACM_COL_LENGTHS(CASE)
+#undef CASE
+    default:
+      return -1;
+  }
+}
+
+int stokes_local_blocks(const Geom& g, int prec_bytes) {
+  switch (g.nx / 2) {
+#define CASE(M)                                                                               \
+  case M: {                                                                                   \
+    const int rb = prec_bytes == 8 ? RowCfg<double, M>::RB : RowCfg<float, M>::RB;            \
+    return (int)((g.nrows + rb - 1) / rb) * g.dim;                                            \
+  }
+    ACM_ROW_LENGTHS(CASE)
+#undef CASE
+    default:
+      return -1;
+  }
+}
+
+template <typename T>
+hipError_t launch_stokes_green(const Geom& g, const DevTables<T>& tb, void* spec, void* qhat,
+                               void* dhat, double* partials, StokesCtl* ctl, int* nblocks,
+                               hipStream_t s) {
+  const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
+  const T* rt = tb.rtab;
+  GreenGeom gg{g.dim, g.nx, g.xh, (int)g.plane, g.nspec, g.ntot};
+  const cplx<T>* tw = ct + (g.dim == 3 ? tb.off.tw_z : tb.off.tw_y);
+  const T* szp = rt + tb.off.sz;
+  const T* lzp = rt + tb.off.lz;
+  auto* sp = reinterpret_cast<cplx<T>*>(spec);
+  auto* qp = reinterpret_cast<cplx<T>*>(qhat);
+  auto* dp = reinterpret_cast<cplx<T>*>(dhat);
+  switch (g.last_n) {
+#define CASE(LL)                                                                              \
+  case LL: {                                                                                  \
+    if (g.dim == 3) {                                                                         \
+      using C = ColCfg<T, LL, 3>;                                                             \
+      const int nb = (int)((g.plane + C::TX - 1) / C::TX);                                    \
+      if (nblocks) *nblocks = nb;                                                             \
+      hipLaunchKernelGGL((k_stokes_green<T, LL, 3>), dim3(nb), dim3(C::NT), C::LDS_BYTES, s,   \
+                         sp, qp, dp, partials, ctl, gg, tw, rt + tb.off.sx, rt + tb.off.lx,     \
+                         rt + tb.off.sy, rt + tb.off.ly, szp, lzp);                           \
+    } else {                                                                                  \
+      using C = ColCfg<T, LL, 2>;                                                             \
+      const int nb = (int)((g.plane + C::TX - 1) / C::TX);                                    \
+      if (nblocks) *nblocks = nb;                                                             \
+      hipLaunchKernelGGL((k_stokes_green<T, LL, 2>), dim3(nb), dim3(C::NT), C::LDS_BYTES, s,   \
+                         sp, qp, dp, partials, ctl, gg, tw, rt + tb.off.sx, rt + tb.off.lx,     \
+                         rt + tb.off.sy, rt + tb.off.ly, szp, lzp);                           \
+    }                                                                                         \
+    return hipGetLastError();                                                                 \
+  }
+    ACM_COL_LENGTHS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_stokes_local(const Geom& g, const DevTables<T>& tb, const void* spec, T* u,
+                               T* a, const uint8_t* H, double* partials, int green_blocks,
+                               StokesCtl* ctl, double* hist, int* nblocks, hipStream_t s) {
+  const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
+  const double* gpart = partials;
+  double* lpart = partials + 3 * (int64_t)green_blocks;
+  switch (g.nx / 2) {
+#define CASE(M)                                                                               \
+  case M: {                                                                                   \
+    using C = RowCfg<T, M>;                                                                   \
+    dim3 grid((unsigned)((g.nrows + C::RB - 1) / C::RB), (unsigned)g.dim);                    \
+    if (nblocks) *nblocks = (int)(grid.x * grid.y);                                           \
+    hipLaunchKernelGGL((k_stokes_local<T, M>), grid, dim3(C::NT), C::LDS_BYTES, s,             \
+                       reinterpret_cast<const cplx<T>*>(spec), u, a, H, lpart, gpart,         \
+                       green_blocks, ctl, hist, (int)g.nrows, g.ntot, g.nspec,                \
+                       ct + tb.off.tw_x, ct + tb.off.rtw);                                    \
+    return hipGetLastError();                                                                 \
+  }
+    ACM_ROW_LENGTHS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_stokes_rhs(const Geom& g, const DevTables<T>& tb, void* spec, const T* u,
+                             const T* a, const uint8_t* H, StokesCtl* ctl, hipStream_t s) {
+  const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
+  switch (g.nx / 2) {
+#define CASE(M)                                                                               \
+  case M: {                                                                                   \
+    using C = RowCfg<T, M>;                                                                   \
+    dim3 grid((unsigned)((g.nrows + C::RB - 1) / C::RB), (unsigned)g.dim);                    \
+    hipLaunchKernelGGL((k_stokes_rhs<T, M>), grid, dim3(C::NT), C::LDS_BYTES, s,               \
+                       reinterpret_cast<cplx<T>*>(spec), u, a, H, ctl, (int)g.nrows, g.ntot,  \
+                       g.nspec, ct + tb.off.tw_x, ct + tb.off.rtw);                           \
+    return hipGetLastError();                                                                 \
+  }
+    ACM_ROW_LENGTHS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+#define INST(T)                                                                                \
+  template hipError_t launch_stokes_green<T>(const Geom&, const DevTables<T>&, void*, void*,   \
+                                             void*, double*, StokesCtl*, int*, hipStream_t);   \
+  template hipError_t launch_stokes_local<T>(const Geom&, const DevTables<T>&, const void*, T*, \
+                                             T*, const uint8_t*, double*, int, StokesCtl*,     \
+                                             double*, int*, hipStream_t);                      \
+  template hipError_t launch_stokes_rhs<T>(const Geom&, const DevTables<T>&, void*, const T*,  \
+                                           const T*, const uint8_t*, StokesCtl*, hipStream_t);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace acm

@@ -1,0 +1,124 @@
+// Device helpers shared by every pass kernel: real<->half-complex transforms of
+// x rows held in LDS, and the column (strided pencil) tile mapping used by the
+// y and z passes.
+#pragma once
+#include "acm_internal.hpp"
+#include "fft_core.hpp"
+
+namespace acm {
+
+// Supported lengths.  Row kernels take the complex half length M = nx/2,
+// column kernels the full axis length.
+#define ACM_ROW_LENGTHS(X) X(4) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(256)
+#define ACM_COL_LENGTHS(X) X(8) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(512)
+
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+// --------------------------------------------------------------------- rows
+// A workgroup holds RB consecutive x rows of one field, each with pitch RP
+// complex values.  TPP threads cooperate on one row.
+template <typename T, int M>
+struct RowCfg {
+  static constexpr int TPP = Plan<M>::TPP;
+  static constexpr int RP = M + 1;
+  static constexpr int RB_THREADS = cmax(1, 256 / TPP);
+  static constexpr int RB_LDS = cmax(1, (40 * 1024) / (RP * (int)sizeof(cplx<T>)));
+  static constexpr int RB = cmin(RB_THREADS, RB_LDS);
+  // block size padded to whole wavefronts; threads past TPP*RB stay idle
+  static constexpr int NT = ((TPP * RB + 63) / 64) * 64;
+  static constexpr int LDS_BYTES = RB * RP * (int)sizeof(cplx<T>);
+};
+
+// Turn half spectra X[0..M] of every row into real rows x[0..2M) in place
+// (the row then reads as T[2M]).  The inverse is unnormalised along x, so the
+// real row equals nx * (inverse DFT of X).  Ends with a barrier.
+template <typename T, int M>
+__device__ __forceinline__ void rows_c2r_lds(cplx<T>* lds, int row, int t, bool active,
+                                             const cplx<T>* __restrict__ tw,
+                                             const cplx<T>* __restrict__ rtw) {
+  using C = RowCfg<T, M>;
+  cplx<T>* r = lds + row * C::RP;
+  if (active) {
+    for (int k = t; k <= M / 2; k += C::TPP) {
+      if (k == 0) {
+        cplx<T> x0 = r[0], xm = r[M];
+        cplx<T> S = cadd(x0, cconj(xm));
+        cplx<T> D = csub(x0, cconj(xm));
+        r[0] = cmake<T>(S.x - D.y, S.y + D.x);
+      } else if (2 * k == M) {
+        r[k] = cscale(cconj(r[k]), T(2));
+      } else {
+        cplx<T> xk = r[k], xm = r[M - k];
+        cplx<T> S = cadd(xk, cconj(xm));
+        cplx<T> D = csub(xk, cconj(xm));
+        cplx<T> P = cmulc(D, rtw[k]);  // D * conj(W^k)
+        r[k] = cmake<T>(S.x - P.y, S.y + P.x);
+        r[M - k] = cmake<T>(S.x + P.y, P.x - S.y);  // conj(S) + i conj(P)
+      }
+    }
+  }
+  __syncthreads();
+  PencilFFT<T, M, 1, +1>::run_lds(t, active, r, 0, 1, tw);
+  __syncthreads();
+}
+
+// Turn real rows x[0..2M) (stored as M complex) into half spectra X[0..M] in
+// place (forward, unnormalised).  Ends with a barrier.
+template <typename T, int M>
+__device__ __forceinline__ void rows_r2c_lds(cplx<T>* lds, int row, int t, bool active,
+                                             const cplx<T>* __restrict__ tw,
+                                             const cplx<T>* __restrict__ rtw) {
+  using C = RowCfg<T, M>;
+  cplx<T>* r = lds + row * C::RP;
+  PencilFFT<T, M, 1, -1>::run_lds(t, active, r, 0, 1, tw);
+  __syncthreads();
+  if (active) {
+    for (int k = t; k <= M / 2; k += C::TPP) {
+      if (k == 0) {
+        cplx<T> z = r[0];
+        r[0] = cmake<T>(z.x + z.y, T(0));
+        r[M] = cmake<T>(z.x - z.y, T(0));
+      } else if (2 * k == M) {
+        r[k] = cconj(r[k]);
+      } else {
+        cplx<T> zk = r[k], zm = r[M - k];
+        cplx<T> E = cscale(cadd(zk, cconj(zm)), T(0.5));
+        cplx<T> D = csub(zk, cconj(zm));
+        cplx<T> O = cmake<T>(T(0.5) * D.y, T(-0.5) * D.x);
+        cplx<T> WO = cmul(rtw[k], O);
+        r[k] = cadd(E, WO);
+        r[M - k] = cconj(csub(E, WO));
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ columns
+// Pencils along an axis of stride `as`; pencil f in [0, ncols) starts at
+// (f / inner) * outer + (f % inner).  A workgroup holds TX consecutive pencils
+// of NCOMP fields in LDS as [field][i][col] (col fastest).
+struct ColMap {
+  int inner;
+  int outer;
+  int as;
+  int ncols;
+};
+
+__device__ __forceinline__ int col_base(const ColMap& m, int f) {
+  return (f / m.inner) * m.outer + (f % m.inner);
+}
+
+template <typename T, int L, int NCOMP>
+struct ColCfg {
+  static constexpr int TPP = Plan<L>::TPP;
+  static constexpr int TX_THREADS = cmax(1, 256 / TPP);
+  static constexpr int TX_LDS = cmax(1, (56 * 1024) / (NCOMP * L * (int)sizeof(cplx<T>)));
+  static constexpr int TX = cmin(TX_THREADS, TX_LDS);
+  // block size padded to whole wavefronts; threads with t >= TPP stay idle
+  static constexpr int NT = ((TPP * TX + 63) / 64) * 64;
+  static constexpr int LDS_BYTES = NCOMP * L * TX * (int)sizeof(cplx<T>);
+};
+
+}  // namespace acm

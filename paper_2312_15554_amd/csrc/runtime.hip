@@ -1,0 +1,616 @@
+// Host runtime behind the C ABI: argument checks, per-cell plans (twiddle and
+// symbol tables computed in FP64), workspace, the graph-replayed iteration
+// loops and the read-out transforms.
+#include <math.h>
+#include <string.h>
+
+#include <chrono>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/acm.h"
+#include "acm_internal.hpp"
+#include "fft_core.hpp"
+
+namespace acm {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static acm_status fail(acm_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(e_ == hipErrorOutOfMemory ? ACM_E_NOMEM : ACM_E_HIP,                 \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+  } while (0)
+
+// ------------------------------------------------------------------- plans
+struct CellPlan {
+  Geom g;
+  int prec;  // bytes per real
+  int device;
+  void* ctab = nullptr;
+  void* rtab = nullptr;
+  TableOffsets off{};
+  int green_blocks = 0;
+  int local_blocks = 0;
+  ~CellPlan() {
+    if (ctab) (void)hipFree(ctab);
+    if (rtab) (void)hipFree(rtab);
+  }
+};
+
+static std::mutex g_mu;
+static std::map<std::tuple<int, int, int, int, int, int>, std::unique_ptr<CellPlan>> g_plans;
+
+static bool make_geom(const acm_grid* grid, Geom* g, std::string* why) {
+  if (!grid) {
+    *why = "grid is NULL";
+    return false;
+  }
+  if (grid->dim != 2 && grid->dim != 3) {
+    *why = "dim must be 2 or 3";
+    return false;
+  }
+  g->dim = grid->dim;
+  g->nx = grid->n[0];
+  g->ny = grid->n[1];
+  g->nz = grid->dim == 3 ? grid->n[2] : 1;
+  if (grid->dim == 2 && grid->n[2] != 1) {
+    *why = "n[2] must be 1 when dim = 2";
+    return false;
+  }
+  g->xh = g->nx / 2 + 1;
+  g->ntot = (int64_t)g->nx * g->ny * g->nz;
+  g->nrows = (int64_t)g->ny * g->nz;
+  g->nspec = (int64_t)g->nz * g->ny * g->xh;
+  g->last_n = g->dim == 3 ? g->nz : g->ny;
+  g->plane = g->dim == 3 ? (int64_t)g->ny * g->xh : g->xh;
+  return true;
+}
+
+static bool size_supported(const Geom& g) {
+  auto ok = [](int n) { return fft_length_supported(n); };
+  if (!ok(g.nx) || g.nx > 512 || !ok(g.ny)) return false;
+  if (g.dim == 3 && !ok(g.nz)) return false;
+  return true;
+}
+
+static void push_twiddles(std::vector<double>& c, int L) {
+  RadixPlan p = make_plan(L);
+  for (int s = 0; s < p.nst; ++s) {
+    const int R = p.r[s], NS = p.ns[s];
+    for (int k = 0; k < NS; ++k)
+      for (int r = 1; r < R; ++r) {
+        const double ang = -2.0 * M_PI * (double)(k * r) / (double)(NS * R);
+        c.push_back(cos(ang));
+        c.push_back(sin(ang));
+      }
+  }
+}
+
+static void push_symbols(std::vector<double>& rv, int n, int count, int* s_off, int* l_off) {
+  *s_off = (int)rv.size();
+  for (int k = 0; k < count; ++k) {
+    double v = (2 * k == n || n == 1) ? 0.0 : sin(2.0 * M_PI * k / n) * n;
+    rv.push_back(v);
+  }
+  *l_off = (int)rv.size();
+  for (int k = 0; k < count; ++k) {
+    const double sn = sin(M_PI * k / n);
+    rv.push_back(n == 1 ? 0.0 : 4.0 * sn * sn * n * n);
+  }
+}
+
+template <typename T>
+static hipError_t upload(const std::vector<double>& v, void** dst) {
+  std::vector<T> tmp(v.size());
+  for (size_t i = 0; i < v.size(); ++i) tmp[i] = (T)v[i];
+  size_t bytes = std::max<size_t>(tmp.size(), 2) * sizeof(T);
+  hipError_t e = hipMalloc(dst, bytes);
+  if (e != hipSuccess) return e;
+  if (!tmp.empty()) e = hipMemcpy(*dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+static acm_status get_plan(const acm_grid* grid, int precision, CellPlan** out) {
+  Geom g;
+  std::string why;
+  if (!make_geom(grid, &g, &why)) return fail(ACM_E_INVALID, why);
+  if (!size_supported(g))
+    return fail(ACM_E_UNSUPPORTED_SIZE,
+                "grid lengths must be in {8,16,24,32,48,64,96,128,192,256,512} (nx <= 512)");
+  if (precision != ACM_FP32 && precision != ACM_FP64)
+    return fail(ACM_E_INVALID, "precision must be ACM_FP32 or ACM_FP64");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_tuple(dev, precision, g.dim, g.nx, g.ny, g.nz);
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) {
+    *out = it->second.get();
+    return ACM_OK;
+  }
+  auto p = std::make_unique<CellPlan>();
+  p->g = g;
+  p->prec = precision == ACM_FP64 ? 8 : 4;
+  p->device = dev;
+  std::vector<double> c, r;
+  p->off.tw_x = 0;
+  push_twiddles(c, g.nx / 2);
+  p->off.tw_y = (int)(c.size() / 2);
+  push_twiddles(c, g.ny);
+  p->off.tw_z = (int)(c.size() / 2);
+  if (g.dim == 3) push_twiddles(c, g.nz);
+  p->off.rtw = (int)(c.size() / 2);
+  for (int k = 0; k <= g.nx / 2; ++k) {
+    const double ang = -2.0 * M_PI * k / g.nx;
+    c.push_back(cos(ang));
+    c.push_back(sin(ang));
+  }
+  p->off.ncomplex = (int)(c.size() / 2);
+  push_symbols(r, g.nx, g.xh, &p->off.sx, &p->off.lx);
+  push_symbols(r, g.ny, g.ny, &p->off.sy, &p->off.ly);
+  push_symbols(r, g.nz, g.nz, &p->off.sz, &p->off.lz);
+  p->off.nreal = (int)r.size();
+  hipError_t e;
+  if (precision == ACM_FP64) {
+    e = upload<double>(c, &p->ctab);
+    if (e == hipSuccess) e = upload<double>(r, &p->rtab);
+  } else {
+    e = upload<float>(c, &p->ctab);
+    if (e == hipSuccess) e = upload<float>(r, &p->rtab);
+  }
+  if (e != hipSuccess) return fail(ACM_E_HIP, std::string("table upload: ") + hipGetErrorString(e));
+  p->green_blocks = stokes_green_blocks(g, p->prec);
+  p->local_blocks = stokes_local_blocks(g, p->prec);
+  *out = p.get();
+  g_plans[key] = std::move(p);
+  return ACM_OK;
+}
+
+template <typename T>
+static DevTables<T> tables_of(const CellPlan* p) {
+  DevTables<T> tb;
+  tb.ctab = p->ctab;
+  tb.rtab = reinterpret_cast<const T*>(p->rtab);
+  tb.off = p->off;
+  return tb;
+}
+
+// A scoped device allocation.
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+// Timing of eager launches with HIP events, per kernel kind.
+struct Profiler {
+  bool on = false;
+  hipStream_t s = nullptr;
+  double ms[KK_COUNT] = {0};
+  int64_t calls[KK_COUNT] = {0};
+  std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> ev;
+  void begin(int kind, hipEvent_t* a) {
+    if (!on) return;
+    (void)hipEventCreate(a);
+    (void)hipEventRecord(*a, s);
+    (void)kind;
+  }
+  void end(int kind, hipEvent_t a) {
+    if (!on) return;
+    hipEvent_t b;
+    (void)hipEventCreate(&b);
+    (void)hipEventRecord(b, s);
+    ev.emplace_back(kind, a, b);
+  }
+  void collect() {
+    for (auto& x : ev) {
+      float t = 0.f;
+      (void)hipEventSynchronize(std::get<2>(x));
+      (void)hipEventElapsedTime(&t, std::get<1>(x), std::get<2>(x));
+      ms[std::get<0>(x)] += t;
+      calls[std::get<0>(x)] += 1;
+      (void)hipEventDestroy(std::get<1>(x));
+      (void)hipEventDestroy(std::get<2>(x));
+    }
+    ev.clear();
+  }
+};
+
+// Streams owned by the library (default priority), one per device.
+static hipStream_t work_stream(int dev) {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = streams.find(dev);
+  if (it != streams.end()) return it->second;
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  streams[dev] = s;
+  return s;
+}
+
+// Order `ws` after the caller's stream.
+static hipError_t join_from(hipStream_t caller, hipStream_t ws) {
+  hipEvent_t e;
+  hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+  if (r != hipSuccess) return r;
+  r = hipEventRecord(e, caller);
+  if (r == hipSuccess) r = hipStreamWaitEvent(ws, e, 0);
+  (void)hipEventDestroy(e);
+  return r;
+}
+
+// ------------------------------------------------------------------ Stokes
+template <typename T>
+static acm_status stokes_impl(CellPlan* pl, const uint8_t* H, const double* gp, double nu,
+                              const acm_penalty& pen, const acm_opts& o, void* u, void* q,
+                              acm_stats* st, double* history, hipStream_t caller) {
+  const Geom& g = pl->g;
+  const int d = g.dim;
+  DevTables<T> tb = tables_of<T>(pl);
+  hipStream_t s = work_stream(pl->device);
+  if (!s) return fail(ACM_E_HIP, "cannot create work stream");
+  HIP_TRY(join_from(caller, s));
+
+  const size_t cbytes = sizeof(T) * 2;
+  const size_t spec_b = cbytes * (size_t)g.nspec * d;
+  const size_t one_b = cbytes * (size_t)g.nspec;
+  const size_t a_b = sizeof(T) * (size_t)g.ntot * d;
+  const int ngreen = pl->green_blocks, nlocal = pl->local_blocks;
+  const size_t part_b = sizeof(double) * (size_t)(3 * ngreen + 4 * nlocal);
+  const int hist_cap = o.history_cap > 0 ? o.history_cap : 0;
+  const size_t hist_b = sizeof(double) * kHistDoubles * (size_t)std::max(hist_cap, 1);
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t total = al(spec_b) + 2 * al(one_b) + al(a_b) + al(part_b) + al(sizeof(StokesCtl)) +
+                       al(hist_b);
+  DevBuf ws;
+  HIP_TRY(hipMalloc(&ws.p, total));
+  char* cur = (char*)ws.p;
+  auto take = [&](size_t b) {
+    void* r = cur;
+    cur += al(b);
+    return r;
+  };
+  void* spec = take(spec_b);
+  void* qhat = take(one_b);
+  void* dhat = take(one_b);
+  T* a = (T*)take(a_b);
+  double* part = (double*)take(part_b);
+  StokesCtl* dctl = (StokesCtl*)take(sizeof(StokesCtl));
+  double* dhist = hist_cap > 0 ? (double*)take(hist_b) : nullptr;
+  T* uu = (T*)u;
+
+  // ---- initial state X^0 (zero start): u = ut = q = a = lambda = 0
+  if (o.warm_start) return fail(ACM_E_INVALID, "warm_start is not available in this build");
+  HIP_TRY(hipMemsetAsync(spec, 0, spec_b, s));
+  HIP_TRY(hipMemsetAsync(qhat, 0, one_b, s));
+  HIP_TRY(hipMemsetAsync(dhat, 0, one_b, s));
+  HIP_TRY(hipMemsetAsync(a, 0, a_b, s));
+  HIP_TRY(hipMemsetAsync(uu, 0, a_b, s));
+  HIP_TRY(hipMemsetAsync(part, 0, part_b, s));
+
+  StokesCtl c{};
+  const double p0 = nu * (double)std::max(g.nx, std::max(g.ny, g.nz));
+  c.psi[0] = pen.alpha > 0 ? pen.alpha : p0;
+  c.psi[1] = pen.beta > 0 ? pen.beta : p0;
+  c.psi[2] = pen.b > 0 ? pen.b : p0;
+  for (int k = 0; k < 3; ++k) {
+    c.phi[k] = pen.phi[k];
+    c.tau[k] = pen.tau[k];
+    c.psi_min[k] = pen.psi_min[k] > 0 ? pen.psi_min[k] : 1e-3 * c.psi[k];
+    c.g[k] = k < d ? gp[k] : 0.0;
+  }
+  c.c_prev = 0.0;
+  c.eps = o.eps;
+  c.sqrt_n[0] = sqrt((double)d * (double)g.ntot);
+  c.sqrt_n[1] = sqrt((double)g.ntot);
+  c.sqrt_n[2] = c.sqrt_n[0];
+  c.nu = nu;
+  c.iter = 0;
+  c.max_iter = o.max_iter;
+  c.done = 0;
+  c.status = 1;
+  c.adaptive = pen.adaptive;
+  c.counter = 0;
+  c.hist_cap = hist_cap;
+  HIP_TRY(hipMemcpyAsync(dctl, &c, sizeof(c), hipMemcpyHostToDevice, s));
+
+  Profiler prof;
+  prof.on = o.profile != 0;
+  prof.s = s;
+  auto one_iter = [&]() -> hipError_t {
+    hipError_t e;
+    hipEvent_t ev0 = nullptr;
+    prof.begin(KK_GREEN, &ev0);
+    e = launch_stokes_green<T>(g, tb, spec, qhat, dhat, part, dctl, nullptr, s);
+    if (e != hipSuccess) return e;
+    prof.end(KK_GREEN, ev0);
+    if (d == 3) {
+      prof.begin(KK_YINV, &ev0);
+      e = launch_cols<T>(g, tb, 1, +1, d, spec, s);
+      if (e != hipSuccess) return e;
+      prof.end(KK_YINV, ev0);
+    }
+    prof.begin(KK_LOCAL, &ev0);
+    e = launch_stokes_local<T>(g, tb, spec, uu, a, H, part, ngreen, dctl, dhist, nullptr, s);
+    if (e != hipSuccess) return e;
+    prof.end(KK_LOCAL, ev0);
+    prof.begin(KK_RHS, &ev0);
+    e = launch_stokes_rhs<T>(g, tb, spec, uu, a, H, dctl, s);
+    if (e != hipSuccess) return e;
+    prof.end(KK_RHS, ev0);
+    if (d == 3) {
+      prof.begin(KK_YFWD, &ev0);
+      e = launch_cols<T>(g, tb, 1, -1, d, spec, s);
+      if (e != hipSuccess) return e;
+      prof.end(KK_YFWD, ev0);
+    }
+    return hipSuccess;
+  };
+
+  int K = o.check_every;
+  if (K <= 0) {
+    const double work = (double)g.ntot * d;
+    K = (int)std::min(200.0, std::max(8.0, 3.0e8 / work));
+  }
+  if (o.max_iter < K) K = (int)std::max<int64_t>(1, o.max_iter);
+
+  StokesCtl* hctl = nullptr;
+  HIP_TRY(hipHostMalloc((void**)&hctl, sizeof(StokesCtl), hipHostMallocDefault));
+  struct HostFree {
+    void* p;
+    ~HostFree() {
+      if (p) (void)hipHostFree(p);
+    }
+  } hf{hctl};
+
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  const bool use_graph = o.use_graph && !prof.on;
+  if (use_graph) {
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < K && e == hipSuccess; ++k) e = one_iter();
+    hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return fail(ACM_E_HIP, std::string("kernel launch during capture: ") + hipGetErrorString(e));
+    }
+    HIP_TRY(e2);
+    HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  }
+  struct GraphFree {
+    hipGraph_t g;
+    hipGraphExec_t x;
+    ~GraphFree() {
+      if (x) (void)hipGraphExecDestroy(x);
+      if (g) (void)hipGraphDestroy(g);
+    }
+  } gf{graph, exec};
+
+  auto t0 = std::chrono::steady_clock::now();
+  int64_t launched = 0;
+  for (;;) {
+    if (use_graph) {
+      HIP_TRY(hipGraphLaunch(exec, s));
+    } else {
+      for (int k = 0; k < K; ++k) {
+        hipError_t e = one_iter();
+        if (e != hipSuccess) return fail(ACM_E_HIP, std::string("launch: ") + hipGetErrorString(e));
+      }
+    }
+    launched += K;
+    HIP_TRY(hipMemcpyAsync(hctl, dctl, sizeof(StokesCtl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    prof.collect();
+    if (hctl->done) break;
+    if (launched > o.max_iter + 2LL * K) break;  // safety net: the device caps iterations itself
+  }
+  auto t1 = std::chrono::steady_clock::now();
+
+  // ---- read-out of q: inverse transform of q-hat
+  if (q) {
+    HIP_TRY(hipMemcpyAsync(spec, qhat, one_b, hipMemcpyDeviceToDevice, s));
+    if (d == 3) {
+      hipError_t e = launch_cols<T>(g, tb, 2, +1, 1, spec, s);
+      if (e == hipSuccess) e = launch_cols<T>(g, tb, 1, +1, 1, spec, s);
+      if (e != hipSuccess) return fail(ACM_E_HIP, hipGetErrorString(e));
+    } else {
+      hipError_t e = launch_cols<T>(g, tb, 1, +1, 1, spec, s);
+      if (e != hipSuccess) return fail(ACM_E_HIP, hipGetErrorString(e));
+    }
+    hipError_t e = launch_rows_c2r<T>(g, tb, 1, spec, (T*)q, 1.0 / (double)g.ntot, s);
+    if (e != hipSuccess) return fail(ACM_E_HIP, hipGetErrorString(e));
+  }
+  if (history && hist_cap > 0) {
+    std::vector<double> h((size_t)hist_cap * kHistDoubles);
+    HIP_TRY(hipMemcpyAsync(h.data(), dhist, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const int64_t n = hctl->iter;
+    const int64_t keep = std::min<int64_t>(n, hist_cap);
+    for (int64_t i = 0; i < keep; ++i) {
+      const int64_t it = n - keep + i;  // 0-based iteration index
+      memcpy(history + i * kHistDoubles, h.data() + (it % hist_cap) * kHistDoubles,
+             sizeof(double) * kHistDoubles);
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  if (st) {
+    memset(st, 0, sizeof(*st));
+    st->iters = hctl->iter;
+    for (int k = 0; k < 3; ++k) {
+      st->r_p[k] = hctl->rp[k];
+      st->r_d[k] = hctl->rd[k];
+      st->tol_p[k] = hctl->tp[k];
+      st->tol_d[k] = hctl->td[k];
+      st->psi[k] = hctl->psi[k];
+    }
+    st->seconds = std::chrono::duration<double>(t1 - t0).count();
+    st->converged = hctl->status == 0;
+    st->status = hctl->status;
+    for (int k = 0; k < KK_COUNT; ++k) {
+      st->kernel_ms[k] = prof.ms[k];
+      st->kernel_calls[k] = prof.calls[k];
+    }
+  }
+  if (hctl->status == -5) return fail(ACM_E_DIVERGED, "a residual became non-finite");
+  return hctl->status == 0 ? ACM_OK : ACM_NOT_CONVERGED;
+}
+
+// --------------------------------------------------------------------- FFT
+template <typename T>
+static acm_status fft_impl(CellPlan* pl, int nfields, const void* in, void* out, bool forward,
+                           hipStream_t caller) {
+  const Geom& g = pl->g;
+  DevTables<T> tb = tables_of<T>(pl);
+  hipStream_t s = work_stream(pl->device);
+  if (!s) return fail(ACM_E_HIP, "cannot create work stream");
+  HIP_TRY(join_from(caller, s));
+  hipError_t e;
+  if (forward) {
+    e = launch_rows_r2c<T>(g, tb, nfields, (const T*)in, out, s);
+    if (e == hipSuccess) e = launch_cols<T>(g, tb, 1, -1, nfields, out, s);
+    if (e == hipSuccess && g.dim == 3) e = launch_cols<T>(g, tb, 2, -1, nfields, out, s);
+    if (e != hipSuccess) return fail(ACM_E_HIP, hipGetErrorString(e));
+  } else {
+    DevBuf tmp;
+    const size_t b = sizeof(T) * 2 * (size_t)g.nspec * nfields;
+    HIP_TRY(hipMalloc(&tmp.p, b));
+    HIP_TRY(hipMemcpyAsync(tmp.p, in, b, hipMemcpyDeviceToDevice, s));
+    e = hipSuccess;
+    if (g.dim == 3) e = launch_cols<T>(g, tb, 2, +1, nfields, tmp.p, s);
+    if (e == hipSuccess) e = launch_cols<T>(g, tb, 1, +1, nfields, tmp.p, s);
+    if (e == hipSuccess) e = launch_rows_c2r<T>(g, tb, nfields, tmp.p, (T*)out, 1.0 / (double)g.ntot, s);
+    if (e != hipSuccess) return fail(ACM_E_HIP, hipGetErrorString(e));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  return ACM_OK;
+}
+
+}  // namespace acm
+
+// ===================================================================== C ABI
+using namespace acm;
+
+extern "C" {
+
+void acm_default_penalty(acm_penalty* p) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  for (int k = 0; k < 3; ++k) p->phi[k] = 1.1;
+  p->tau[0] = 5.0;
+  p->tau[1] = 10.0;
+  p->tau[2] = 5.0;
+  p->adaptive = 1;
+}
+
+void acm_default_opts(acm_opts* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->eps = 1e-6;
+  o->max_iter = 1000000;
+  o->precision = ACM_FP32;
+  o->use_graph = 1;
+}
+
+const char* acm_last_error(void) { return g_err.c_str(); }
+
+int32_t acm_version(void) { return 1; }
+
+acm_status acm_stokes_solve(const acm_grid* grid, const uint8_t* H, const double* g_p, double nu,
+                            const acm_penalty* pen, const acm_opts* opts, void* u, void* q,
+                            acm_stats* stats, double* history, void* stream) {
+  g_err.clear();
+  acm_penalty P;
+  acm_opts O;
+  acm_default_penalty(&P);
+  acm_default_opts(&O);
+  if (pen) P = *pen;
+  if (opts) O = *opts;
+  if (!H || !g_p || !u) return fail(ACM_E_INVALID, "H, g_p and u must be non-NULL");
+  if (!(nu > 0.0) || !isfinite(nu)) return fail(ACM_E_INVALID, "nu must be positive");
+  if (!(O.eps >= 0.0) || O.max_iter < 1) return fail(ACM_E_INVALID, "eps >= 0 and max_iter >= 1 required");
+  for (int k = 0; k < 3; ++k)
+    if (!(P.phi[k] >= 1.0) || !(P.tau[k] > 0.0))
+      return fail(ACM_E_INVALID, "phi >= 1 and tau > 0 required");
+  CellPlan* pl = nullptr;
+  acm_status r = get_plan(grid, O.precision, &pl);
+  if (r != ACM_OK) return r;
+  for (int k = 0; k < grid->dim; ++k)
+    if (!isfinite(g_p[k])) return fail(ACM_E_INVALID, "g_p must be finite");
+  // H must contain a solid voxel: with no solid the mean of a grows without
+  // bound under a body force and no steady flow exists.
+  {
+    hipStream_t cs = (hipStream_t)stream;
+    std::vector<uint8_t> hh((size_t)pl->g.ntot);
+    hipError_t e = hipMemcpyAsync(hh.data(), H, hh.size(), hipMemcpyDeviceToHost, cs);
+    if (e == hipSuccess) e = hipStreamSynchronize(cs);
+    if (e != hipSuccess) return fail(ACM_E_HIP, std::string("reading H: ") + hipGetErrorString(e));
+    bool any = false;
+    for (uint8_t v : hh) {
+      if (v > 1) return fail(ACM_E_INVALID, "H must hold 0 or 1");
+      any |= v == 1;
+    }
+    if (!any) return fail(ACM_E_INVALID, "H has no solid voxel: no steady flow under a body force");
+  }
+  if (O.precision == ACM_FP64)
+    return stokes_impl<double>(pl, H, g_p, nu, P, O, u, q, stats, history, (hipStream_t)stream);
+  return stokes_impl<float>(pl, H, g_p, nu, P, O, u, q, stats, history, (hipStream_t)stream);
+}
+
+acm_status acm_fft_r2c(const acm_grid* grid, int32_t precision, int32_t nfields, const void* in,
+                       void* out, void* stream) {
+  g_err.clear();
+  if (!in || !out || nfields < 1) return fail(ACM_E_INVALID, "in/out non-NULL and nfields >= 1 required");
+  CellPlan* pl = nullptr;
+  acm_status r = get_plan(grid, precision, &pl);
+  if (r != ACM_OK) return r;
+  if (precision == ACM_FP64) return fft_impl<double>(pl, nfields, in, out, true, (hipStream_t)stream);
+  return fft_impl<float>(pl, nfields, in, out, true, (hipStream_t)stream);
+}
+
+acm_status acm_fft_c2r(const acm_grid* grid, int32_t precision, int32_t nfields, const void* in,
+                       void* out, void* stream) {
+  g_err.clear();
+  if (!in || !out || nfields < 1) return fail(ACM_E_INVALID, "in/out non-NULL and nfields >= 1 required");
+  CellPlan* pl = nullptr;
+  acm_status r = get_plan(grid, precision, &pl);
+  if (r != ACM_OK) return r;
+  if (precision == ACM_FP64) return fft_impl<double>(pl, nfields, in, out, false, (hipStream_t)stream);
+  return fft_impl<float>(pl, nfields, in, out, false, (hipStream_t)stream);
+}
+
+acm_status acm_transport_step(const acm_grid* grid, const uint8_t* H, const void* u,
+                              const double* g_chi, double Pe, double diffusivity, double eta,
+                              double A0, const double* B0, double dt, int32_t n_steps,
+                              const acm_opts* opts, void* chi, acm_stats* stats, void* stream) {
+  (void)grid; (void)H; (void)u; (void)g_chi; (void)Pe; (void)diffusivity; (void)eta; (void)A0;
+  (void)B0; (void)dt; (void)n_steps; (void)opts; (void)chi; (void)stats; (void)stream;
+  return fail(ACM_E_INVALID, "acm_transport_step: not available in this build");
+}
+
+acm_status acm_effective_props(const acm_grid* grid, int32_t precision, const uint8_t* H,
+                               int32_t n_flow, const void* const* u, int32_t n_chi,
+                               const void* const* chi, const void* u_transport, double nu,
+                               double Pe, double* K, double* D, double* mass, void* stream) {
+  (void)grid; (void)precision; (void)H; (void)n_flow; (void)u; (void)n_chi; (void)chi;
+  (void)u_transport; (void)nu; (void)Pe; (void)K; (void)D; (void)mass; (void)stream;
+  return fail(ACM_E_INVALID, "acm_effective_props: not available in this build");
+}
+
+}  // extern "C"
