@@ -74,6 +74,9 @@ typedef struct {
   int32_t use_graph;    /* 1 = replay the iterations as a captured HIP graph */
   int32_t profile;      /* 1 = launch eagerly and time every kernel kind with HIP events */
   int32_t history_cap;  /* > 0: keep the residuals of the last history_cap iterations */
+  int32_t pass_mode;    /* Stokes 3D: 0 automatic, 1 separate x and y passes,
+                           2 fused xy-slab passes (needs nx == ny <= 128 and
+                           16-byte aligned u and H; otherwise ACM_E_INVALID) */
 } acm_opts;
 
 /* Kernel kinds reported in acm_stats.kernel_ms (with opts.profile = 1). */
@@ -109,7 +112,7 @@ void acm_default_opts(acm_opts* o);
  * the next call on the same thread. */
 const char* acm_last_error(void);
 
-/* ABI version (incremented on any signature change). */
+/* ABI version (incremented on any signature or struct change): 2. */
 int32_t acm_version(void);
 
 /*

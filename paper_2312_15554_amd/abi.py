@@ -30,7 +30,7 @@ class acm_penalty(C.Structure):
 class acm_opts(C.Structure):
     _fields_ = [("eps", C.c_double), ("max_iter", C.c_int64), ("precision", C.c_int32),
                 ("check_every", C.c_int32), ("warm_start", C.c_int32), ("use_graph", C.c_int32),
-                ("profile", C.c_int32), ("history_cap", C.c_int32)]
+                ("profile", C.c_int32), ("history_cap", C.c_int32), ("pass_mode", C.c_int32)]
 
 
 class acm_stats(C.Structure):

@@ -45,6 +45,25 @@ def _dev(t: torch.Tensor, what: str):
     return C.c_void_p(t.data_ptr())
 
 
+def _expect(t: torch.Tensor, shape, dtype, what: str):
+    """Buffers the library writes or reads must match exactly: a wrong dtype or
+    shape would make the kernels run past the end of the allocation."""
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if t.dtype != dtype:
+        raise ValueError(f"{what} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous device tensor")
+    if t.device != torch.device("cuda", torch.cuda.current_device()):
+        raise ValueError(f"{what} must live on the current device")
+
+
+def _check_H(H: torch.Tensor):
+    if H.dtype != torch.uint8:
+        raise ValueError("H must be uint8")
+    _expect(H, H.shape, torch.uint8, "H")
+
+
 def _dvec(vals, n=3):
     arr = (C.c_double * n)()
     for i, v in enumerate(vals):
@@ -86,23 +105,25 @@ def acm_stokes_solve(H: torch.Tensor, g, nu: float = 1.0, *, dtype=torch.float32
                      check_every: int = 0, use_graph: bool = True, profile: bool = False,
                      history_cap: int = 0, u: torch.Tensor | None = None,
                      q: torch.Tensor | None = None, want_q: bool = True, warm_start: bool = False,
-                     stream=None) -> dict:
+                     pass_mode: int = 0, stream=None) -> dict:
     """Stokes cell problem by ADMM (acm_stokes_solve).  H: uint8 device tensor
     in numpy order.  Returns dict(u, q, status, stats, history)."""
     lib = abi.load()
+    _check_H(H)
     shape = tuple(H.shape)
     d = len(shape)
-    if H.dtype != torch.uint8:
-        raise ValueError("H must be uint8")
     dev = H.device
     if u is None:
         u = torch.empty((d,) + shape, dtype=dtype, device=dev)
     if q is None and want_q:
         q = torch.empty(shape, dtype=dtype, device=dev)
+    _expect(u, (d,) + shape, dtype, "u")
+    if q is not None:
+        _expect(q, shape, dtype, "q")
     pen = default_penalty(**(penalty or {}))
     opts = default_opts(eps=eps, max_iter=max_iter, precision=_prec(dtype), check_every=check_every,
                         use_graph=int(use_graph), profile=int(profile), history_cap=history_cap,
-                        warm_start=int(warm_start))
+                        warm_start=int(warm_start), pass_mode=int(pass_mode))
     st = abi.acm_stats()
     hist = (C.c_double * (max(history_cap, 1) * abi.HIST_DOUBLES))() if history_cap > 0 else None
     gr = _grid(shape)
@@ -124,6 +145,7 @@ def acm_fft_r2c(x: torch.Tensor, cell_shape, stream=None) -> torch.Tensor:
     (nfields, *cell_shape[:-1], nx//2+1) complex."""
     lib = abi.load()
     nf = x.shape[0]
+    _expect(x, (nf,) + tuple(cell_shape), x.dtype, "x")
     cdt = torch.complex64 if x.dtype == torch.float32 else torch.complex128
     out = torch.empty((nf,) + tuple(cell_shape[:-1]) + (cell_shape[-1] // 2 + 1,), dtype=cdt,
                       device=x.device)
@@ -136,9 +158,78 @@ def acm_fft_r2c(x: torch.Tensor, cell_shape, stream=None) -> torch.Tensor:
 def acm_fft_c2r(X: torch.Tensor, cell_shape, stream=None) -> torch.Tensor:
     lib = abi.load()
     nf = X.shape[0]
+    if X.dtype not in (torch.complex64, torch.complex128):
+        raise ValueError("X must be complex64 or complex128")
+    _expect(X, (nf,) + tuple(cell_shape[:-1]) + (cell_shape[-1] // 2 + 1,), X.dtype, "X")
     rdt = torch.float32 if X.dtype == torch.complex64 else torch.float64
     out = torch.empty((nf,) + tuple(cell_shape), dtype=rdt, device=X.device)
     gr = _grid(cell_shape)
     abi.check(lib.acm_fft_c2r(C.byref(gr), _prec(rdt), nf, _dev(X, "X"), _dev(out, "out"),
                               _stream(stream)))
     return out
+
+
+def acm_transport_step(H: torch.Tensor, u: torch.Tensor, g_chi, Pe: float, *,
+                       diffusivity: float = 1.0, eta: float = 0.01, A0: float = 0.55,
+                       B0=(0.0, 0.0, 0.0), dt: float = math.inf, n_steps: int = 1,
+                       eps: float = 1e-6, max_iter: int = 1_000_000, chi: torch.Tensor | None = None,
+                       check_every: int = 0, use_graph: bool = True, profile: bool = False,
+                       stream=None) -> dict:
+    """Penalised advection-diffusion by the LS iteration (acm_transport_step).
+    u: flow field (d, *shape) in the working precision.  chi (optional) holds
+    the initial value and receives the result.  Returns dict(chi, status, stats)."""
+    lib = abi.load()
+    _check_H(H)
+    shape = tuple(H.shape)
+    _prec(u.dtype)
+    _expect(u, (len(shape),) + shape, u.dtype, "u")
+    if chi is None:
+        chi = torch.zeros(shape, dtype=u.dtype, device=u.device)
+    _expect(chi, shape, u.dtype, "chi")
+    opts = default_opts(eps=eps, max_iter=max_iter, precision=_prec(u.dtype),
+                        check_every=check_every, use_graph=int(use_graph), profile=int(profile))
+    st = abi.acm_stats()
+    gr = _grid(shape)
+    d = len(shape)
+    status = lib.acm_transport_step(C.byref(gr), _dev(H, "H"), _dev(u, "u"),
+                                    _dvec(list(g_chi) + [0.0] * (3 - len(g_chi))), float(Pe),
+                                    float(diffusivity), float(eta), float(A0),
+                                    _dvec(list(B0)[:d] + [0.0] * (3 - d)), float(dt), int(n_steps),
+                                    C.byref(opts), _dev(chi, "chi"), C.byref(st), _stream(stream))
+    abi.check(status)
+    return dict(chi=chi, status=status, stats=stats_dict(st))
+
+
+def acm_effective_props(H: torch.Tensor, us=(), chis=(), u_transport: torch.Tensor | None = None,
+                        nu: float = 1.0, Pe: float = 0.0, stream=None) -> dict:
+    """Effective permeability rows K[i] (flow i) and diffusivity columns D[:, j]
+    (chi j) with solute masses (acm_effective_props)."""
+    import numpy as np
+    lib = abi.load()
+    shape = tuple(H.shape)
+    d = len(shape)
+    ref = us[0] if len(us) else (chis[0] if len(chis) else None)
+    if ref is None:
+        raise ValueError("nothing to compute")
+    prec = _prec(ref.dtype)
+    _check_H(H)
+    for x in us:
+        _expect(x, (d,) + shape, ref.dtype, "u")
+    for x in chis:
+        _expect(x, shape, ref.dtype, "chi")
+    if u_transport is not None:
+        _expect(u_transport, (d,) + shape, ref.dtype, "u_transport")
+    nf, nc = len(us), len(chis)
+    up = (C.c_void_p * max(nf, 1))(*[_dev(x, "u").value for x in us])
+    cp = (C.c_void_p * max(nc, 1))(*[_dev(x, "chi").value for x in chis])
+    K = (C.c_double * max(nf * d, 1))()
+    D = (C.c_double * max(d * nc, 1))()
+    mass = (C.c_double * max(nc, 1))()
+    gr = _grid(shape)
+    abi.check(lib.acm_effective_props(C.byref(gr), prec, _dev(H, "H"), nf, up, nc, cp,
+                                      _dev(u_transport, "u_transport") if u_transport is not None else None,
+                                      float(nu), float(Pe), K if nf else None, D if nc else None,
+                                      mass if nc else None, _stream(stream)))
+    return dict(K=np.array(K[: nf * d]).reshape(nf, d) if nf else None,
+                D=np.array(D[: d * nc]).reshape(d, nc) if nc else None,
+                mass=np.array(mass[:nc]) if nc else None)

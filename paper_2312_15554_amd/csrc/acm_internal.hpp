@@ -110,9 +110,10 @@ template <typename T>
 hipError_t launch_rows_c2r(const Geom& g, const DevTables<T>& tb, int nfields, const void* in,
                            T* out, double scale, hipStream_t s);
 // Complex transform along y (axis 1) or z (axis 2) of nfields half spectra, in place.
+// `skip` (may be null): device flag; when non-zero the launch does nothing.
 template <typename T>
 hipError_t launch_cols(const Geom& g, const DevTables<T>& tb, int axis, int sign, int nfields,
-                       void* data, hipStream_t s);
+                       void* data, hipStream_t s, const int32_t* skip = nullptr);
 
 // Stokes ADMM passes.
 template <typename T>
@@ -126,6 +127,38 @@ hipError_t launch_stokes_local(const Geom& g, const DevTables<T>& tb, const void
 template <typename T>
 hipError_t launch_stokes_rhs(const Geom& g, const DevTables<T>& tb, void* spec, const T* u,
                              const T* a, const uint8_t* H, StokesCtl* ctl, hipStream_t s);
+
+// Lippmann-Schwinger passes.  mode 0: LS update; mode 1: grad chi-hat only.
+template <typename T>
+hipError_t launch_transport_green(const Geom& g, const DevTables<T>& tb, int mode, void* spec,
+                                  void* chat, const void* chat_m, double* partials,
+                                  TransportCtl* ctl, hipStream_t s);
+template <typename T>
+hipError_t launch_transport_local(const Geom& g, const DevTables<T>& tb, void* spec, const T* u,
+                                  const uint8_t* H, const TransportCtl* ctl, hipStream_t s);
+int transport_green_blocks(const Geom& g, int precision_bytes);
+
+// FP64 reductions (per-block partials; the host adds them in order).
+template <typename T>
+hipError_t launch_flow_sums(const Geom& g, const T* u, const uint8_t* H, double* part, int* nsums,
+                            hipStream_t s);
+template <typename T>
+hipError_t launch_chi_sums(const Geom& g, const T* chi, const T* u, const uint8_t* H,
+                           double* part, int* nsums, hipStream_t s);
+int reduction_blocks(const Geom& g);
+
+// Fused xy-slab Stokes passes (3D, nx == ny, slab of one field in LDS).
+template <typename T>
+bool slab_supported(const Geom& g);
+template <typename T>
+int slab_local_blocks(const Geom& g);
+template <typename T>
+hipError_t launch_slab_local(const Geom& g, const DevTables<T>& tb, const void* spec, T* u, T* a,
+                             const uint8_t* H, double* partials, int green_blocks,
+                             StokesCtl* ctl, double* hist, hipStream_t s);
+template <typename T>
+hipError_t launch_slab_rhs(const Geom& g, const DevTables<T>& tb, void* spec, const T* u,
+                           const T* a, const uint8_t* H, StokesCtl* ctl, hipStream_t s);
 
 // Grid-size helpers used by the host to size partial-sum buffers.
 int stokes_green_blocks(const Geom& g, int precision_bytes);

@@ -37,7 +37,7 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_rows_r2c(const T* __rest
   }
   __syncthreads();
   const int row = threadIdx.x / C::TPP, t = threadIdx.x % C::TPP;
-  rows_r2c_lds<T, M>(lds, row, t, row < nr, tw, rtw);
+  rows_r2c_lds<T, M>(lds, 0, row, t, row < nr, tw, rtw);
   cplx<T>* dst = out + field * nspec + (int64_t)row0 * (M + 1);
   for (int v = threadIdx.x; v < nr * (M + 1); v += C::NT) dst[v] = lds[v];
 }
@@ -60,7 +60,7 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_rows_c2r(const cplx<T>* 
   for (int v = threadIdx.x; v < nr * (M + 1); v += C::NT) lds[v] = src[v];
   __syncthreads();
   const int row = threadIdx.x / C::TPP, t = threadIdx.x % C::TPP;
-  rows_c2r_lds<T, M>(lds, row, t, row < nr, tw, rtw);
+  rows_c2r_lds<T, M>(lds, 0, row, t, row < nr, tw, rtw);
   T* dst = out + field * ntot + (int64_t)row0 * (2 * M);
   for (int v = threadIdx.x; v < nr * 2 * M; v += C::NT) {
     const int r = v / (2 * M), x = v - r * (2 * M);
@@ -71,8 +71,10 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_rows_c2r(const cplx<T>* 
 template <typename T, int L, int SIGN>
 __global__ __launch_bounds__((ColCfg<T, L, 1>::NT)) void k_cols(cplx<T>* __restrict__ data,
                                                               int64_t field_stride, ColMap m,
-                                                              const cplx<T>* __restrict__ tw) {
+                                                              const cplx<T>* __restrict__ tw,
+                                                              const int32_t* __restrict__ skip) {
   using C = ColCfg<T, L, 1>;
+  if (skip != nullptr && *skip) return;
   extern __shared__ __align__(16) char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* base = data + blockIdx.y * field_stride;
@@ -137,7 +139,7 @@ hipError_t launch_rows_c2r(const Geom& g, const DevTables<T>& tb, int nfields, c
 
 template <typename T>
 hipError_t launch_cols(const Geom& g, const DevTables<T>& tb, int axis, int sign, int nfields,
-                       void* data, hipStream_t s) {
+                       void* data, hipStream_t s, const int32_t* skip) {
   const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
   ColMap m;
   int L;
@@ -167,10 +169,10 @@ hipError_t launch_cols(const Geom& g, const DevTables<T>& tb, int axis, int sign
     dim3 grid((unsigned)((m.ncols + C::TX - 1) / C::TX), (unsigned)nfields);                \
     if (sign < 0)                                                                           \
       hipLaunchKernelGGL((k_cols<T, LL, -1>), grid, dim3(C::NT), C::LDS_BYTES, s, d,         \
-                         g.nspec, m, tw);                                                   \
+                         g.nspec, m, tw, skip);                                             \
     else                                                                                    \
       hipLaunchKernelGGL((k_cols<T, LL, 1>), grid, dim3(C::NT), C::LDS_BYTES, s, d, g.nspec, \
-                         m, tw);                                                            \
+                         m, tw, skip);                                                      \
     return hipGetLastError();                                                               \
   }
     ACM_COL_LENGTHS(CASE)
@@ -186,7 +188,7 @@ hipError_t launch_cols(const Geom& g, const DevTables<T>& tb, int axis, int sign
   template hipError_t launch_rows_c2r<T>(const Geom&, const DevTables<T>&, int, const void*, \
                                          T*, double, hipStream_t);                           \
   template hipError_t launch_cols<T>(const Geom&, const DevTables<T>&, int, int, int, void*, \
-                                     hipStream_t);
+                                     hipStream_t, const int32_t*);
 INST(float)
 INST(double)
 #undef INST

@@ -1,0 +1,335 @@
+// Fused xy-slab passes of the ADMM iteration for 3D cells whose z-slab of one
+// field fits in LDS (ny * (nx/2 + 2) complex values, up to 150 KB).  One
+// workgroup owns one (field, z) slab:
+//   slab_local: load the half-spectrum slab, inverse y transform (columns),
+//               inverse x transform (rows) -> u^{n+1}, Steps 2-3 pointwise
+//               (Section 3.1), FP64 partial sums; the last workgroup runs
+//               Step 4 and the penalty update (shared with the row path).
+//   slab_rhs:   r = b^{n+1} ut^{n+1} - a^{n+1}, forward x transform (rows),
+//               forward y transform (columns), store the slab.
+// This replaces the separate x-row and y-column passes of the general path
+// and saves one HBM round trip of the spectra per direction of transform.
+#include "pass_common.hpp"
+#include "stokes_finalize.hpp"
+
+namespace acm {
+
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  using type = float4;
+};
+template <>
+struct Vec4<double> {
+  using type = double4;
+};
+
+template <typename T, int NX, int NY>
+struct SlabCfg {
+  static constexpr int M = NX / 2;
+  static constexpr int XH = M + 1;
+  static constexpr int P2 = XH + 1;  // row pitch in complex values (even: rows 16B-aligned)
+  static constexpr int TPPY = Plan<NY>::TPP;
+  static constexpr int TPPX = Plan<M>::TPP;
+  static constexpr int NT = 512;
+  static constexpr int GY = NT / TPPY;  // column groups per round
+  static constexpr int GX = NT / TPPX;  // row groups per round
+  static constexpr int LDS_BYTES = NY * P2 * (int)sizeof(cplx<T>);
+  static constexpr int NV = NX * NY;                     // voxels per slab
+  static constexpr int NQ = NV / 4;                       // quads per slab
+  static constexpr int QPT = (NQ + NT - 1) / NT;          // quads per thread
+  static constexpr bool FULL = (NQ % NT) == 0;
+};
+
+// y transform of all XH columns of the slab held in LDS ([y][k], pitch P2).
+template <typename T, int NX, int NY, int SIGN>
+__device__ __forceinline__ void slab_cols(cplx<T>* lds, const cplx<T>* __restrict__ tw) {
+  using S = SlabCfg<T, NX, NY>;
+  const int grp = threadIdx.x / S::TPPY, t = threadIdx.x % S::TPPY;
+#pragma unroll 1
+  for (int c0 = 0; c0 < S::XH; c0 += S::GY) {
+    const int col = c0 + grp;
+    const bool act = grp < S::GY && col < S::XH;
+    PencilFFT<T, NY, 1, SIGN>::run_lds(t, act, lds + (act ? col : 0), 0, S::P2, tw);
+    __syncthreads();
+  }
+}
+
+template <typename T, int NX, int NY>
+__global__ __launch_bounds__(512) void k_slab_local(
+    const cplx<T>* __restrict__ spec, T* __restrict__ u, T* __restrict__ a,
+    const uint8_t* __restrict__ H, double* __restrict__ lpart, const double* __restrict__ gpart,
+    int ngreen, StokesCtl* ctl, double* hist, int64_t ntot, int64_t nspec,
+    const cplx<T>* __restrict__ twx, const cplx<T>* __restrict__ twy,
+    const cplx<T>* __restrict__ rtw) {
+  using S = SlabCfg<T, NX, NY>;
+  using V = typename Vec4<T>::type;
+  extern __shared__ __align__(32) char smem_raw[];
+  __shared__ double red[4 * 8];
+  __shared__ double red7[7 * 8];
+  __shared__ int s_last;
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  T* ldsr = reinterpret_cast<T*>(smem_raw);
+  if (ctl->done) return;
+  const double al = ctl->psi[0], bb = ctl->psi[2];
+  const T cc = (T)(bb / (bb + al));
+  const T cp = (T)ctl->c_prev;
+  const T ka = (T)(bb * al / (bb + al));
+  const int z = blockIdx.x, field = blockIdx.y;
+
+  const cplx<T>* src = spec + field * nspec + (int64_t)z * NY * S::XH;
+  for (int v = threadIdx.x; v < NY * S::XH; v += S::NT) {
+    const int y = v / S::XH, k = v - y * S::XH;
+    lds[y * S::P2 + k] = src[v];
+  }
+  __syncthreads();
+  slab_cols<T, NX, NY, +1>(lds, twy);
+  {
+    const int grp = threadIdx.x / S::TPPX, t = threadIdx.x % S::TPPX;
+#pragma unroll 1
+    for (int r0 = 0; r0 < NY; r0 += S::GX) {
+      const int row = r0 + grp;
+      const bool act = grp < S::GX && row < NY;
+      rows_c2r_lds<T, S::M, 1, S::P2>(lds, 0, act ? row : 0, t, act, twx, rtw);
+    }
+  }
+
+  // Steps 2-3 on 4 consecutive voxels per quad; all loads issued up front.
+  const int64_t off = field * ntot + (int64_t)z * S::NV;
+  V* uq = reinterpret_cast<V*>(u + off);
+  V* aq = reinterpret_cast<V*>(a + off);
+  const uint32_t* hq = reinterpret_cast<const uint32_t*>(H + (int64_t)z * S::NV);
+  V up[S::QPT];
+  uint32_t hw[S::QPT];
+#pragma unroll
+  for (int j = 0; j < S::QPT; ++j) {
+    const int q = threadIdx.x + j * S::NT;
+    hw[j] = 0u;
+    if (S::FULL || q < S::NQ) {
+      up[j] = uq[q];
+      hw[j] = hq[q];
+    }
+  }
+  V ao[S::QPT];
+#pragma unroll
+  for (int j = 0; j < S::QPT; ++j) {
+    const int q = threadIdx.x + j * S::NT;
+    if (hw[j]) ao[j] = aq[q];
+  }
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < S::QPT; ++j) {
+    const int q = threadIdx.x + j * S::NT;
+    if (!S::FULL && q >= S::NQ) continue;
+    const int v = 4 * q;
+    const int y = v / NX, x = v - y * NX;
+    const V un = *reinterpret_cast<const V*>(ldsr + y * 2 * S::P2 + x);
+    const T unv[4] = {un.x, un.y, un.z, un.w};
+    const T upv[4] = {up[j].x, up[j].y, up[j].z, up[j].w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const double du = (double)unv[e] - (double)upv[e];
+      acc[3] += du * du;
+    }
+    uq[q] = un;
+    if (hw[j]) {
+      T aov[4] = {ao[j].x, ao[j].y, ao[j].z, ao[j].w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if ((hw[j] >> (8 * e)) & 0xffu) {
+          const T an = aov[e] + ka * unv[e];
+          aov[e] = an;
+          const T dd = cc * unv[e] - cp * upv[e];
+          acc[0] += (double)unv[e] * unv[e];
+          acc[1] += (double)dd * dd;
+          acc[2] += (double)an * an;
+        }
+      }
+      V w;
+      w.x = aov[0];
+      w.y = aov[1];
+      w.z = aov[2];
+      w.w = aov[3];
+      aq[q] = w;
+    }
+  }
+  block_sum<4>(acc, red);
+  const int nblk = gridDim.x * gridDim.y;
+  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+  if (threadIdx.x == 0) {
+    lpart[bid * 4 + 0] = acc[0];
+    lpart[bid * 4 + 1] = acc[1];
+    lpart[bid * 4 + 2] = acc[2];
+    lpart[bid * 4 + 3] = acc[3];
+    __threadfence();
+    const unsigned prev = atomicAdd(&ctl->counter, 1u);
+    s_last = (prev == (unsigned)(nblk - 1)) ? 1 : 0;
+  }
+  __syncthreads();
+  if (s_last) {
+    __threadfence();
+    stokes_finalize(ctl, gpart, ngreen, lpart, nblk, ntot, hist, red7);
+  }
+}
+
+template <typename T, int NX, int NY>
+__global__ __launch_bounds__(512) void k_slab_rhs(cplx<T>* __restrict__ spec,
+                                                  const T* __restrict__ u,
+                                                  const T* __restrict__ a,
+                                                  const uint8_t* __restrict__ H,
+                                                  const StokesCtl* __restrict__ ctl,
+                                                  int64_t ntot, int64_t nspec,
+                                                  const cplx<T>* __restrict__ twx,
+                                                  const cplx<T>* __restrict__ twy,
+                                                  const cplx<T>* __restrict__ rtw) {
+  using S = SlabCfg<T, NX, NY>;
+  using V = typename Vec4<T>::type;
+  extern __shared__ __align__(32) char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  T* ldsr = reinterpret_cast<T*>(smem_raw);
+  if (ctl->done) return;
+  const T bb = (T)ctl->psi[2];
+  const T bcp = (T)(ctl->psi[2] * ctl->c_prev);
+  const int z = blockIdx.x, field = blockIdx.y;
+  const int64_t off = field * ntot + (int64_t)z * S::NV;
+  const V* uq = reinterpret_cast<const V*>(u + off);
+  const V* aq = reinterpret_cast<const V*>(a + off);
+  const uint32_t* hq = reinterpret_cast<const uint32_t*>(H + (int64_t)z * S::NV);
+  V uv[S::QPT];
+  uint32_t hw[S::QPT];
+#pragma unroll
+  for (int j = 0; j < S::QPT; ++j) {
+    const int q = threadIdx.x + j * S::NT;
+    hw[j] = 0u;
+    if (S::FULL || q < S::NQ) {
+      uv[j] = uq[q];
+      hw[j] = hq[q];
+    }
+  }
+  V av[S::QPT];
+#pragma unroll
+  for (int j = 0; j < S::QPT; ++j) {
+    const int q = threadIdx.x + j * S::NT;
+    if (hw[j]) av[j] = aq[q];
+  }
+#pragma unroll
+  for (int j = 0; j < S::QPT; ++j) {
+    const int q = threadIdx.x + j * S::NT;
+    if (!S::FULL && q >= S::NQ) continue;
+    const int v = 4 * q;
+    const int y = v / NX, x = v - y * NX;
+    V r;
+    if (hw[j]) {
+      r.x = (hw[j] & 0xffu) ? bcp * uv[j].x - av[j].x : bb * uv[j].x;
+      r.y = (hw[j] & 0xff00u) ? bcp * uv[j].y - av[j].y : bb * uv[j].y;
+      r.z = (hw[j] & 0xff0000u) ? bcp * uv[j].z - av[j].z : bb * uv[j].z;
+      r.w = (hw[j] & 0xff000000u) ? bcp * uv[j].w - av[j].w : bb * uv[j].w;
+    } else {
+      r.x = bb * uv[j].x;
+      r.y = bb * uv[j].y;
+      r.z = bb * uv[j].z;
+      r.w = bb * uv[j].w;
+    }
+    *reinterpret_cast<V*>(ldsr + y * 2 * S::P2 + x) = r;
+  }
+  __syncthreads();
+  {
+    const int grp = threadIdx.x / S::TPPX, t = threadIdx.x % S::TPPX;
+#pragma unroll 1
+    for (int r0 = 0; r0 < NY; r0 += S::GX) {
+      const int row = r0 + grp;
+      const bool act = grp < S::GX && row < NY;
+      rows_r2c_lds<T, S::M, 1, S::P2>(lds, 0, act ? row : 0, t, act, twx, rtw);
+    }
+  }
+  slab_cols<T, NX, NY, -1>(lds, twy);
+  cplx<T>* dst = spec + field * nspec + (int64_t)z * NY * S::XH;
+  for (int v = threadIdx.x; v < NY * S::XH; v += S::NT) {
+    const int y = v / S::XH, k = v - y * S::XH;
+    dst[v] = lds[y * S::P2 + k];
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+// Slab sizes compiled: square slabs (nx == ny) of these lengths.
+#define ACM_SLAB_LENGTHS(X) X(32) X(48) X(64) X(96) X(128)
+
+template <typename T>
+bool slab_supported(const Geom& g) {
+  if (g.dim != 3 || g.nx != g.ny) return false;
+  switch (g.nx) {
+#define CASE(N) \
+  case N:       \
+    return SlabCfg<T, N, N>::LDS_BYTES <= 150 * 1024;
+    ACM_SLAB_LENGTHS(CASE)
+#undef CASE
+    default:
+      return false;
+  }
+}
+
+template <typename T>
+int slab_local_blocks(const Geom& g) {
+  return g.nz * g.dim;
+}
+
+template <typename T>
+hipError_t launch_slab_local(const Geom& g, const DevTables<T>& tb, const void* spec, T* u, T* a,
+                             const uint8_t* H, double* partials, int green_blocks,
+                             StokesCtl* ctl, double* hist, hipStream_t s) {
+  const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
+  const double* gpart = partials;
+  double* lpart = partials + 3 * (int64_t)green_blocks;
+  dim3 grid((unsigned)g.nz, (unsigned)g.dim);
+  switch (g.nx) {
+#define CASE(N)                                                                                \
+  case N: {                                                                                    \
+    using S = SlabCfg<T, N, N>;                                                                \
+    hipLaunchKernelGGL((k_slab_local<T, N, N>), grid, dim3(S::NT), S::LDS_BYTES, s,             \
+                       reinterpret_cast<const cplx<T>*>(spec), u, a, H, lpart, gpart,          \
+                       green_blocks, ctl, hist, g.ntot, g.nspec, ct + tb.off.tw_x,             \
+                       ct + tb.off.tw_y, ct + tb.off.rtw);                                     \
+    return hipGetLastError();                                                                  \
+  }
+    ACM_SLAB_LENGTHS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_slab_rhs(const Geom& g, const DevTables<T>& tb, void* spec, const T* u,
+                           const T* a, const uint8_t* H, StokesCtl* ctl, hipStream_t s) {
+  const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
+  dim3 grid((unsigned)g.nz, (unsigned)g.dim);
+  switch (g.nx) {
+#define CASE(N)                                                                                \
+  case N: {                                                                                    \
+    using S = SlabCfg<T, N, N>;                                                                \
+    hipLaunchKernelGGL((k_slab_rhs<T, N, N>), grid, dim3(S::NT), S::LDS_BYTES, s,               \
+                       reinterpret_cast<cplx<T>*>(spec), u, a, H, ctl, g.ntot, g.nspec,        \
+                       ct + tb.off.tw_x, ct + tb.off.tw_y, ct + tb.off.rtw);                   \
+    return hipGetLastError();                                                                  \
+  }
+    ACM_SLAB_LENGTHS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+#define INST(T)                                                                                \
+  template bool slab_supported<T>(const Geom&);                                                \
+  template int slab_local_blocks<T>(const Geom&);                                              \
+  template hipError_t launch_slab_local<T>(const Geom&, const DevTables<T>&, const void*, T*,  \
+                                           T*, const uint8_t*, double*, int, StokesCtl*,       \
+                                           double*, hipStream_t);                              \
+  template hipError_t launch_slab_rhs<T>(const Geom&, const DevTables<T>&, void*, const T*,    \
+                                         const T*, const uint8_t*, StokesCtl*, hipStream_t);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace acm

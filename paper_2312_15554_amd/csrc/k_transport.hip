@@ -1,0 +1,335 @@
+// Fused passes of the Lippmann-Schwinger iteration for the penalised
+// advection-diffusion cell problem (Section 3.2: eq. penalization, eq. iter,
+// eq. fft_solute, eq. tol_solute; symbols of eq. fft_app).
+//
+// One iteration n (3D; in 2D the y passes disappear and "last axis" is y):
+//   [y inverse of grad chi-hat]
+//   local  (x rows, all fields of a row at once): grad chi^n in real space,
+//           e = grad chi + g, tau = (A - A0) e, f = calF (1-H) - (B - B0) . e,
+//           forward x transform of (tau, f).
+//   [y forward of (tau, f)]
+//   green  (last axis): F-hat = f-hat + i s . tau-hat, chi-hat update by the
+//           comparison-medium symbol (plus 1/dt for a time step), Parseval
+//           sums for r_1 = |chi^{n+1} - chi^n| and r_2 = |grad chi^{n+1} -
+//           grad chi^n|, the last workgroup applies the stopping test, and
+//           grad chi-hat = i s chi-hat is transformed back along the last axis.
+#include "pass_common.hpp"
+
+namespace acm {
+
+struct TGreenGeom {
+  int dim;
+  int nx, xh;
+  int plane;
+  int64_t nspec;
+  int64_t ntot;
+};
+
+// MODE 0: LS update.  MODE 1: only form grad chi-hat from chi-hat (set-up).
+template <typename T, int L, int D, int MODE>
+__global__ __launch_bounds__((ColCfg<T, L, D + 1>::NT)) void k_transport_green(
+    cplx<T>* __restrict__ spec, cplx<T>* __restrict__ chat, const cplx<T>* __restrict__ chat_m,
+    double* __restrict__ partials, TransportCtl* ctl, TGreenGeom gg,
+    const cplx<T>* __restrict__ tw, const T* __restrict__ sx, const T* __restrict__ lx,
+    const T* __restrict__ sy, const T* __restrict__ ly, const T* __restrict__ sz,
+    const T* __restrict__ lz) {
+  using C = ColCfg<T, L, D + 1>;
+  constexpr int PS = L * C::TX;
+  constexpr int NIN = D + 1;
+  extern __shared__ __align__(16) char smem_raw[];
+  __shared__ double red[2 * 16];
+  __shared__ int s_last;
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  if (MODE == 0 && ctl->done) return;
+  const int P = gg.plane;
+  const int f0 = blockIdx.x * C::TX;
+  const int t = threadIdx.x / C::TX, colt = threadIdx.x % C::TX;
+  const bool act = t < C::TPP && f0 + colt < P;
+
+  if constexpr (MODE == 0) {
+    for (int e = threadIdx.x; e < NIN * PS; e += C::NT) {
+      const int c = e / PS, rem = e - c * PS;
+      const int i = rem / C::TX, col = rem - i * C::TX;
+      const int f = f0 + col;
+      cplx<T> v = cmake<T>(T(0), T(0));
+      if (f < P) v = spec[c * gg.nspec + (int64_t)i * P + f];
+      lds[e] = v;
+    }
+    __syncthreads();
+    PencilFFT<T, L, NIN, -1>::run_lds(t, act, lds + colt, PS, C::TX, tw);
+    __syncthreads();
+  }
+
+  double acc[2] = {0.0, 0.0};
+  const T inv_ntot = T(1.0 / (double)gg.ntot);
+  const T A0 = (T)ctl->A0;
+  const T inv_dt = (T)ctl->inv_dt;
+  const int steady = ctl->steady;
+  T B0[3] = {(T)ctl->B0[0], (T)ctl->B0[1], (T)ctl->B0[2]};
+  for (int e = threadIdx.x; e < PS; e += C::NT) {
+    const int i = e / C::TX, col = e - i * C::TX;
+    const int f = f0 + col;
+    if (f >= P) continue;
+    int kx, ky, kz;
+    if (D == 3) {
+      kx = f % gg.xh;
+      ky = f / gg.xh;
+      kz = i;
+    } else {
+      kx = f;
+      ky = i;
+      kz = 0;
+    }
+    T s[D];
+    s[0] = sx[kx];
+    s[1] = sy[ky];
+    T Lk = lx[kx] + ly[ky];
+    if constexpr (D == 3) {
+      s[2] = sz[kz];
+      Lk += lz[kz];
+    }
+    const int64_t mi = (int64_t)i * P + f;
+    cplx<T> cn;
+    if constexpr (MODE == 0) {
+      const bool k0 = (kx == 0 && ky == 0 && kz == 0);
+      // F-hat = f-hat + i s . tau-hat
+      cplx<T> F = lds[D * PS + e];
+      T bs = T(0);
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const cplx<T> tc = lds[c * PS + e];
+        F.x -= s[c] * tc.y;
+        F.y += s[c] * tc.x;
+        bs += B0[c] * s[c];
+      }
+      if (k0) {
+        double b0g = 0.0;
+        for (int c = 0; c < D; ++c) b0g += ctl->B0[c] * ctl->g[c];
+        F.x -= (T)((double)gg.ntot * b0g);
+      }
+      const cplx<T> co = chat[mi];
+      if (inv_dt != T(0)) {
+        const cplx<T> cm = chat_m[mi];
+        F.x += inv_dt * cm.x;
+        F.y += inv_dt * cm.y;
+      }
+      // chi-hat = F / (1/dt + A0 L + i B0 . s)
+      const T dr = inv_dt + A0 * Lk, di = bs;
+      const T inv = T(1) / (dr * dr + di * di);
+      cn = cmake<T>((F.x * dr + F.y * di) * inv, (F.y * dr - F.x * di) * inv);
+      if (k0 && steady) cn = cmake<T>(T(0), T(0));
+      chat[mi] = cn;
+      const double w = (kx == 0 || 2 * kx == gg.nx) ? 1.0 : 2.0;
+      const double ddx = (double)cn.x - co.x, ddy = (double)cn.y - co.y;
+      double s2 = 0.0;
+#pragma unroll
+      for (int c = 0; c < D; ++c) s2 += (double)s[c] * s[c];
+      const double a2 = w * (ddx * ddx + ddy * ddy);
+      acc[0] += a2;
+      acc[1] += a2 * s2;
+    } else {
+      cn = chat[mi];
+    }
+    // grad chi-hat / N = i s chi-hat / N
+#pragma unroll
+    for (int c = 0; c < D; ++c) lds[c * PS + e] = cmake<T>(-s[c] * cn.y * inv_ntot, s[c] * cn.x * inv_ntot);
+  }
+  __syncthreads();
+  PencilFFT<T, L, D, 1>::run_lds(t, act, lds + colt, PS, C::TX, tw);
+  __syncthreads();
+  for (int e = threadIdx.x; e < D * PS; e += C::NT) {
+    const int c = e / PS, rem = e - c * PS;
+    const int i = rem / C::TX, col = rem - i * C::TX;
+    const int f = f0 + col;
+    if (f < P) spec[c * gg.nspec + (int64_t)i * P + f] = lds[e];
+  }
+  if constexpr (MODE == 0) {
+    block_sum<2>(acc, red);
+    if (threadIdx.x == 0) {
+      partials[blockIdx.x * 2 + 0] = acc[0];
+      partials[blockIdx.x * 2 + 1] = acc[1];
+      __threadfence();
+      const unsigned prev = atomicAdd(&ctl->counter, 1u);
+      s_last = (prev == gridDim.x - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (s_last) {
+      __threadfence();
+      double tot[2] = {0.0, 0.0};
+      for (int j = threadIdx.x; j < (int)gridDim.x; j += blockDim.x) {
+        tot[0] += partials[j * 2 + 0];
+        tot[1] += partials[j * 2 + 1];
+      }
+      block_sum<2>(tot, red);
+      if (threadIdx.x == 0) {
+        const double inv_n = 1.0 / (double)gg.ntot;
+        const double r1 = sqrt(tot[0] * inv_n), r2 = sqrt(tot[1] * inv_n);
+        ctl->r1 = r1;
+        ctl->r2 = r2;
+        const int64_t it = ctl->iter + 1;
+        ctl->iter = it;
+        ctl->total_iter += 1;
+        if (!isfinite(r1) || !isfinite(r2)) {
+          ctl->done = 1;
+          ctl->status = -5;
+        } else if (r1 <= ctl->sqrt_n1 * ctl->eps && r2 <= ctl->sqrt_n2 * ctl->eps) {
+          ctl->done = 1;
+          ctl->status = 0;
+        } else if (it >= ctl->max_iter) {
+          ctl->done = 1;
+          ctl->status = 1;
+        }
+        ctl->counter = 0u;
+      }
+    }
+  }
+}
+
+template <typename T, int M, int D>
+__global__ __launch_bounds__((RowCfgN<T, M, D + 1>::NT)) void k_transport_local(
+    cplx<T>* __restrict__ spec, const T* __restrict__ u, const uint8_t* __restrict__ H,
+    const TransportCtl* __restrict__ ctl, int nrows, int64_t ntot, int64_t nspec,
+    const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ rtw) {
+  using C = RowCfgN<T, M, D + 1>;
+  constexpr int NX = 2 * M;
+  extern __shared__ __align__(16) char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  T* ldsr = reinterpret_cast<T*>(smem_raw);
+  if (ctl->done) return;
+  const int row0 = blockIdx.x * C::RB;
+  const int nr = min(C::RB, nrows - row0);
+  for (int c = 0; c < D; ++c) {
+    const cplx<T>* src = spec + c * nspec + (int64_t)row0 * (M + 1);
+    for (int v = threadIdx.x; v < nr * (M + 1); v += C::NT) lds[c * C::FS + v] = src[v];
+  }
+  __syncthreads();
+  const int row = threadIdx.x / C::TPP, t = threadIdx.x % C::TPP;
+  rows_c2r_lds<T, M, D>(lds, C::FS, row, t, row < nr, tw, rtw);
+
+  const T g[3] = {(T)ctl->g[0], (T)ctl->g[1], (T)ctl->g[2]};
+  const T B0[3] = {(T)ctl->B0[0], (T)ctl->B0[1], (T)ctl->B0[2]};
+  const T A0 = (T)ctl->A0, Pe = (T)ctl->Pe, eta = (T)ctl->eta, dif = (T)ctl->diff;
+  const T calF = (T)ctl->calF;
+  const int64_t off = (int64_t)row0 * NX;
+  for (int v = threadIdx.x; v < nr * NX; v += C::NT) {
+    const int r = v / NX, x = v - r * NX;
+    const int li = r * 2 * C::RP + x;
+    const bool solid = H[off + v] != 0;
+    const T Aa = solid ? eta : dif;
+    T fval = solid ? T(0) : calF;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const T e = ldsr[2 * c * C::FS + li] + g[c];
+      const T Bc = solid ? T(0) : Pe * u[c * ntot + off + v];
+      fval -= (Bc - B0[c]) * e;
+      ldsr[2 * c * C::FS + li] = (Aa - A0) * e;
+    }
+    ldsr[2 * D * C::FS + li] = fval;
+  }
+  __syncthreads();
+  rows_r2c_lds<T, M, D + 1>(lds, C::FS, row, t, row < nr, tw, rtw);
+  for (int c = 0; c <= D; ++c) {
+    cplx<T>* dst = spec + c * nspec + (int64_t)row0 * (M + 1);
+    for (int v = threadIdx.x; v < nr * (M + 1); v += C::NT) dst[v] = lds[c * C::FS + v];
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+int transport_green_blocks(const Geom& g, int prec_bytes) {
+  switch (g.last_n) {
+#define CASE(LL)                                                                              \
+  case LL:                                                                                    \
+    if (g.dim == 3)                                                                           \
+      return (int)((g.plane + (prec_bytes == 8 ? ColCfg<double, LL, 4>::TX                    \
+                                               : ColCfg<float, LL, 4>::TX) - 1) /             \
+                   (prec_bytes == 8 ? ColCfg<double, LL, 4>::TX : ColCfg<float, LL, 4>::TX)); \
+    return (int)((g.plane + (prec_bytes == 8 ? ColCfg<double, LL, 3>::TX                      \
+                                             : ColCfg<float, LL, 3>::TX) - 1) /               \
+                 (prec_bytes == 8 ? ColCfg<double, LL, 3>::TX : ColCfg<float, LL, 3>::TX));
+    ACM_COL_LENGTHS(CASE)
+#undef CASE
+    default:
+      return -1;
+  }
+}
+
+template <typename T>
+hipError_t launch_transport_green(const Geom& g, const DevTables<T>& tb, int mode, void* spec,
+                                  void* chat, const void* chat_m, double* partials,
+                                  TransportCtl* ctl, hipStream_t s) {
+  const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
+  const T* rt = tb.rtab;
+  TGreenGeom gg{g.dim, g.nx, g.xh, (int)g.plane, g.nspec, g.ntot};
+  const cplx<T>* tw = ct + (g.dim == 3 ? tb.off.tw_z : tb.off.tw_y);
+  auto* sp = reinterpret_cast<cplx<T>*>(spec);
+  auto* cp = reinterpret_cast<cplx<T>*>(chat);
+  auto* cm = reinterpret_cast<const cplx<T>*>(chat_m);
+#define LAUNCH_TG(LL, DD, MM)                                                                \
+  {                                                                                          \
+    using C = ColCfg<T, LL, DD + 1>;                                                         \
+    const int nb = (int)((g.plane + C::TX - 1) / C::TX);                                     \
+    hipLaunchKernelGGL((k_transport_green<T, LL, DD, MM>), dim3(nb), dim3(C::NT),            \
+                       C::LDS_BYTES, s, sp, cp, cm, partials, ctl, gg, tw, rt + tb.off.sx,    \
+                       rt + tb.off.lx, rt + tb.off.sy, rt + tb.off.ly, rt + tb.off.sz,       \
+                       rt + tb.off.lz);                                                      \
+  }
+  switch (g.last_n) {
+#define CASE(LL)                            \
+  case LL:                                  \
+    if (g.dim == 3) {                       \
+      if (mode == 0) LAUNCH_TG(LL, 3, 0)    \
+      else LAUNCH_TG(LL, 3, 1)              \
+    } else {                                \
+      if (mode == 0) LAUNCH_TG(LL, 2, 0)    \
+      else LAUNCH_TG(LL, 2, 1)              \
+    }                                       \
+    return hipGetLastError();
+    ACM_COL_LENGTHS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef LAUNCH_TG
+}
+
+template <typename T>
+hipError_t launch_transport_local(const Geom& g, const DevTables<T>& tb, void* spec, const T* u,
+                                  const uint8_t* H, const TransportCtl* ctl, hipStream_t s) {
+  const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
+  auto* sp = reinterpret_cast<cplx<T>*>(spec);
+#define LAUNCH_TL(MM, DD)                                                                     \
+  {                                                                                           \
+    using C = RowCfgN<T, MM, DD + 1>;                                                         \
+    dim3 grid((unsigned)((g.nrows + C::RB - 1) / C::RB));                                     \
+    hipLaunchKernelGGL((k_transport_local<T, MM, DD>), grid, dim3(C::NT), C::LDS_BYTES, s, sp, \
+                       u, H, ctl, (int)g.nrows, g.ntot, g.nspec, ct + tb.off.tw_x,            \
+                       ct + tb.off.rtw);                                                      \
+  }
+  switch (g.nx / 2) {
+#define CASE(MM)                    \
+  case MM:                          \
+    if (g.dim == 3)                 \
+      LAUNCH_TL(MM, 3)              \
+    else                            \
+      LAUNCH_TL(MM, 2)              \
+    return hipGetLastError();
+    ACM_ROW_LENGTHS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef LAUNCH_TL
+}
+
+#define INST(T)                                                                              \
+  template hipError_t launch_transport_green<T>(const Geom&, const DevTables<T>&, int, void*, \
+                                                void*, const void*, double*, TransportCtl*,  \
+                                                hipStream_t);                                \
+  template hipError_t launch_transport_local<T>(const Geom&, const DevTables<T>&, void*,      \
+                                                const T*, const uint8_t*,                    \
+                                                const TransportCtl*, hipStream_t);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace acm

@@ -30,65 +30,87 @@ struct RowCfg {
   static constexpr int LDS_BYTES = RB * RP * (int)sizeof(cplx<T>);
 };
 
-// Turn half spectra X[0..M] of every row into real rows x[0..2M) in place
-// (the row then reads as T[2M]).  The inverse is unnormalised along x, so the
-// real row equals nx * (inverse DFT of X).  Ends with a barrier.
-template <typename T, int M>
-__device__ __forceinline__ void rows_c2r_lds(cplx<T>* lds, int row, int t, bool active,
-                                             const cplx<T>* __restrict__ tw,
+// Row pitch RP (complex values) defaults to M + 1.
+// Multi-field row blocks: NF fields, field f's rows start at lds + f*fstride.
+template <typename T, int M, int NF>
+struct RowCfgN {
+  static constexpr int TPP = Plan<M>::TPP;
+  static constexpr int RP = M + 1;
+  static constexpr int RB_THREADS = cmax(1, 256 / TPP);
+  static constexpr int RB_LDS = cmax(1, (48 * 1024) / (NF * RP * (int)sizeof(cplx<T>)));
+  static constexpr int RB = cmin(RB_THREADS, RB_LDS);
+  static constexpr int NT = ((TPP * RB + 63) / 64) * 64;
+  static constexpr int FS = RB * RP;  // complex values per field block
+  static constexpr int LDS_BYTES = NF * FS * (int)sizeof(cplx<T>);
+};
+
+// Turn half spectra X[0..M] of row `row` of NF fields into real rows x[0..2M)
+// in place (the row then reads as T[2M]).  The inverse is unnormalised along
+// x, so the real row equals nx * (inverse DFT of X).  Ends with a barrier.
+template <typename T, int M, int NF = 1, int RP = M + 1>
+__device__ __forceinline__ void rows_c2r_lds(cplx<T>* lds, int fstride, int row, int t,
+                                             bool active, const cplx<T>* __restrict__ tw,
                                              const cplx<T>* __restrict__ rtw) {
-  using C = RowCfg<T, M>;
-  cplx<T>* r = lds + row * C::RP;
+  constexpr int TPP = Plan<M>::TPP;
   if (active) {
-    for (int k = t; k <= M / 2; k += C::TPP) {
-      if (k == 0) {
-        cplx<T> x0 = r[0], xm = r[M];
-        cplx<T> S = cadd(x0, cconj(xm));
-        cplx<T> D = csub(x0, cconj(xm));
-        r[0] = cmake<T>(S.x - D.y, S.y + D.x);
-      } else if (2 * k == M) {
-        r[k] = cscale(cconj(r[k]), T(2));
-      } else {
-        cplx<T> xk = r[k], xm = r[M - k];
-        cplx<T> S = cadd(xk, cconj(xm));
-        cplx<T> D = csub(xk, cconj(xm));
-        cplx<T> P = cmulc(D, rtw[k]);  // D * conj(W^k)
-        r[k] = cmake<T>(S.x - P.y, S.y + P.x);
-        r[M - k] = cmake<T>(S.x + P.y, P.x - S.y);  // conj(S) + i conj(P)
+    for (int k = t; k <= M / 2; k += TPP) {
+      const cplx<T> wk = rtw[k];
+#pragma unroll
+      for (int fi = 0; fi < NF; ++fi) {
+        cplx<T>* r = lds + fi * fstride + row * RP;
+        if (k == 0) {
+          cplx<T> x0 = r[0], xm = r[M];
+          cplx<T> S = cadd(x0, cconj(xm));
+          cplx<T> D = csub(x0, cconj(xm));
+          r[0] = cmake<T>(S.x - D.y, S.y + D.x);
+        } else if (2 * k == M) {
+          r[k] = cscale(cconj(r[k]), T(2));
+        } else {
+          cplx<T> xk = r[k], xm = r[M - k];
+          cplx<T> S = cadd(xk, cconj(xm));
+          cplx<T> D = csub(xk, cconj(xm));
+          cplx<T> P = cmulc(D, wk);  // D * conj(W^k)
+          r[k] = cmake<T>(S.x - P.y, S.y + P.x);
+          r[M - k] = cmake<T>(S.x + P.y, P.x - S.y);  // conj(S) + i conj(P)
+        }
       }
     }
   }
   __syncthreads();
-  PencilFFT<T, M, 1, +1>::run_lds(t, active, r, 0, 1, tw);
+  PencilFFT<T, M, NF, +1>::run_lds(t, active, lds + row * RP, fstride, 1, tw);
   __syncthreads();
 }
 
-// Turn real rows x[0..2M) (stored as M complex) into half spectra X[0..M] in
-// place (forward, unnormalised).  Ends with a barrier.
-template <typename T, int M>
-__device__ __forceinline__ void rows_r2c_lds(cplx<T>* lds, int row, int t, bool active,
-                                             const cplx<T>* __restrict__ tw,
+// Turn real rows x[0..2M) (stored as M complex) of NF fields into half spectra
+// X[0..M] in place (forward, unnormalised).  Ends with a barrier.
+template <typename T, int M, int NF = 1, int RP = M + 1>
+__device__ __forceinline__ void rows_r2c_lds(cplx<T>* lds, int fstride, int row, int t,
+                                             bool active, const cplx<T>* __restrict__ tw,
                                              const cplx<T>* __restrict__ rtw) {
-  using C = RowCfg<T, M>;
-  cplx<T>* r = lds + row * C::RP;
-  PencilFFT<T, M, 1, -1>::run_lds(t, active, r, 0, 1, tw);
+  constexpr int TPP = Plan<M>::TPP;
+  PencilFFT<T, M, NF, -1>::run_lds(t, active, lds + row * RP, fstride, 1, tw);
   __syncthreads();
   if (active) {
-    for (int k = t; k <= M / 2; k += C::TPP) {
-      if (k == 0) {
-        cplx<T> z = r[0];
-        r[0] = cmake<T>(z.x + z.y, T(0));
-        r[M] = cmake<T>(z.x - z.y, T(0));
-      } else if (2 * k == M) {
-        r[k] = cconj(r[k]);
-      } else {
-        cplx<T> zk = r[k], zm = r[M - k];
-        cplx<T> E = cscale(cadd(zk, cconj(zm)), T(0.5));
-        cplx<T> D = csub(zk, cconj(zm));
-        cplx<T> O = cmake<T>(T(0.5) * D.y, T(-0.5) * D.x);
-        cplx<T> WO = cmul(rtw[k], O);
-        r[k] = cadd(E, WO);
-        r[M - k] = cconj(csub(E, WO));
+    for (int k = t; k <= M / 2; k += TPP) {
+      const cplx<T> wk = rtw[k];
+#pragma unroll
+      for (int fi = 0; fi < NF; ++fi) {
+        cplx<T>* r = lds + fi * fstride + row * RP;
+        if (k == 0) {
+          cplx<T> z = r[0];
+          r[0] = cmake<T>(z.x + z.y, T(0));
+          r[M] = cmake<T>(z.x - z.y, T(0));
+        } else if (2 * k == M) {
+          r[k] = cconj(r[k]);
+        } else {
+          cplx<T> zk = r[k], zm = r[M - k];
+          cplx<T> E = cscale(cadd(zk, cconj(zm)), T(0.5));
+          cplx<T> D = csub(zk, cconj(zm));
+          cplx<T> O = cmake<T>(T(0.5) * D.y, T(-0.5) * D.x);
+          cplx<T> WO = cmul(wk, O);
+          r[k] = cadd(E, WO);
+          r[M - k] = cconj(csub(E, WO));
+        }
       }
     }
   }

@@ -2,6 +2,7 @@
 // symbol tables computed in FP64), workspace, the graph-replayed iteration
 // loops and the read-out transforms.
 #include <math.h>
+#include <stdint.h>
 #include <string.h>
 
 #include <chrono>
@@ -270,7 +271,17 @@ static acm_status stokes_impl(CellPlan* pl, const uint8_t* H, const double* gp, 
   const size_t spec_b = cbytes * (size_t)g.nspec * d;
   const size_t one_b = cbytes * (size_t)g.nspec;
   const size_t a_b = sizeof(T) * (size_t)g.ntot * d;
-  const int ngreen = pl->green_blocks, nlocal = pl->local_blocks;
+  const int ngreen = pl->green_blocks;
+  const bool aligned = ((uintptr_t)u % 32 == 0) && ((uintptr_t)H % 16 == 0);
+  bool use_slab = false;
+  if (o.pass_mode == 2) {
+    if (!(slab_supported<T>(g) && aligned))
+      return fail(ACM_E_INVALID, "fused xy passes need a 3D cell with nx == ny <= 128 and aligned u, H");
+    use_slab = true;
+  } else if (o.pass_mode == 0) {
+    use_slab = slab_supported<T>(g) && aligned;
+  }
+  const int nlocal = std::max(pl->local_blocks, slab_local_blocks<T>(g));
   const size_t part_b = sizeof(double) * (size_t)(3 * ngreen + 4 * nlocal);
   const int hist_cap = o.history_cap > 0 ? o.history_cap : 0;
   const size_t hist_b = sizeof(double) * kHistDoubles * (size_t)std::max(hist_cap, 1);
@@ -339,9 +350,20 @@ static acm_status stokes_impl(CellPlan* pl, const uint8_t* H, const double* gp, 
     e = launch_stokes_green<T>(g, tb, spec, qhat, dhat, part, dctl, nullptr, s);
     if (e != hipSuccess) return e;
     prof.end(KK_GREEN, ev0);
+    if (use_slab) {
+      prof.begin(KK_LOCAL, &ev0);
+      e = launch_slab_local<T>(g, tb, spec, uu, a, H, part, ngreen, dctl, dhist, s);
+      if (e != hipSuccess) return e;
+      prof.end(KK_LOCAL, ev0);
+      prof.begin(KK_RHS, &ev0);
+      e = launch_slab_rhs<T>(g, tb, spec, uu, a, H, dctl, s);
+      if (e != hipSuccess) return e;
+      prof.end(KK_RHS, ev0);
+      return hipSuccess;
+    }
     if (d == 3) {
       prof.begin(KK_YINV, &ev0);
-      e = launch_cols<T>(g, tb, 1, +1, d, spec, s);
+      e = launch_cols<T>(g, tb, 1, +1, d, spec, s, &dctl->done);
       if (e != hipSuccess) return e;
       prof.end(KK_YINV, ev0);
     }
@@ -355,7 +377,7 @@ static acm_status stokes_impl(CellPlan* pl, const uint8_t* H, const double* gp, 
     prof.end(KK_RHS, ev0);
     if (d == 3) {
       prof.begin(KK_YFWD, &ev0);
-      e = launch_cols<T>(g, tb, 1, -1, d, spec, s);
+      e = launch_cols<T>(g, tb, 1, -1, d, spec, s, &dctl->done);
       if (e != hipSuccess) return e;
       prof.end(KK_YFWD, ev0);
     }
@@ -471,6 +493,274 @@ static acm_status stokes_impl(CellPlan* pl, const uint8_t* H, const double* gp, 
   return hctl->status == 0 ? ACM_OK : ACM_NOT_CONVERGED;
 }
 
+// --------------------------------------------------------------- reductions
+// Run a partial-sum kernel and add the block partials on the host in order.
+template <typename Launch>
+static acm_status reduce_on_host(const Geom& g, hipStream_t s, std::vector<double>* out,
+                                 Launch&& launch) {
+  const int nb = reduction_blocks(g);
+  DevBuf part;
+  HIP_TRY(hipMalloc(&part.p, sizeof(double) * 16 * (size_t)nb));
+  int ns = 0;
+  HIP_TRY(launch((double*)part.p, &ns));
+  std::vector<double> h((size_t)nb * ns);
+  HIP_TRY(hipMemcpyAsync(h.data(), part.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  out->assign(ns, 0.0);
+  for (int b = 0; b < nb; ++b)
+    for (int k = 0; k < ns; ++k) (*out)[k] += h[(size_t)b * ns + k];
+  return ACM_OK;
+}
+
+// --------------------------------------------------------------- transport
+template <typename T>
+static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, const double* gchi,
+                                 double Pe, double diff, double eta, double A0, const double* B0,
+                                 double dt, int n_steps, const acm_opts& o, T* chi,
+                                 acm_stats* st, hipStream_t caller) {
+  const Geom& g = pl->g;
+  const int d = g.dim;
+  DevTables<T> tb = tables_of<T>(pl);
+  hipStream_t s = work_stream(pl->device);
+  if (!s) return fail(ACM_E_HIP, "cannot create work stream");
+  HIP_TRY(join_from(caller, s));
+
+  // pore-averaged velocity (Section 2) for calF = Pe (1-H) ubar . g
+  std::vector<double> fs;
+  acm_status r = reduce_on_host(g, s, &fs, [&](double* part, int* ns) {
+    return launch_flow_sums<T>(g, u, H, part, ns, s);
+  });
+  if (r != ACM_OK) return r;
+  if (!(fs[0] > 0.0)) return fail(ACM_E_INVALID, "H has no pore voxel");
+  double ubar_g = 0.0;
+  for (int c = 0; c < d; ++c) ubar_g += (fs[1 + c] / fs[0]) * gchi[c];
+
+  const size_t cb = sizeof(T) * 2;
+  const size_t spec_b = cb * (size_t)g.nspec * (d + 1);
+  const size_t one_b = cb * (size_t)g.nspec;
+  const int ngreen = transport_green_blocks(g, pl->prec);
+  const size_t part_b = sizeof(double) * 2 * (size_t)ngreen;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  DevBuf ws;
+  HIP_TRY(hipMalloc(&ws.p, al(spec_b) + 2 * al(one_b) + al(part_b) + al(sizeof(TransportCtl))));
+  char* cur = (char*)ws.p;
+  auto take = [&](size_t b) {
+    void* p = cur;
+    cur += al(b);
+    return p;
+  };
+  void* spec = take(spec_b);
+  void* chat = take(one_b);
+  void* chat_m = take(one_b);
+  double* part = (double*)take(part_b);
+  TransportCtl* dctl = (TransportCtl*)take(sizeof(TransportCtl));
+
+  const bool steady = !isfinite(dt);
+  TransportCtl c{};
+  c.eps = o.eps;
+  c.sqrt_n1 = sqrt((double)g.ntot);
+  c.sqrt_n2 = sqrt((double)d * (double)g.ntot);
+  c.inv_dt = steady ? 0.0 : 1.0 / dt;
+  c.A0 = A0;
+  for (int k = 0; k < 3; ++k) {
+    c.B0[k] = k < d ? B0[k] : 0.0;
+    c.g[k] = k < d ? gchi[k] : 0.0;
+  }
+  c.Pe = Pe;
+  c.eta = eta;
+  c.diff = diff;
+  c.calF = Pe * ubar_g;
+  c.max_iter = o.max_iter;
+  c.steady = steady ? 1 : 0;
+  c.status = 1;
+  HIP_TRY(hipMemcpyAsync(dctl, &c, sizeof(c), hipMemcpyHostToDevice, s));
+
+  // chi-hat^0 = FFT(chi^0); grad chi-hat^0 in the layout the local pass reads
+  {
+    hipError_t e = launch_rows_r2c<T>(g, tb, 1, chi, chat, s);
+    if (e == hipSuccess) e = launch_cols<T>(g, tb, 1, -1, 1, chat, s);
+    if (e == hipSuccess && d == 3) e = launch_cols<T>(g, tb, 2, -1, 1, chat, s);
+    if (e == hipSuccess) e = launch_transport_green<T>(g, tb, 1, spec, chat, chat_m, part, dctl, s);
+    if (e != hipSuccess) return fail(ACM_E_HIP, std::string("set-up: ") + hipGetErrorString(e));
+  }
+
+  Profiler prof;
+  prof.on = o.profile != 0;
+  prof.s = s;
+  auto one_iter = [&]() -> hipError_t {
+    hipError_t e;
+    hipEvent_t ev0 = nullptr;
+    if (d == 3) {
+      prof.begin(KK_YINV, &ev0);
+      e = launch_cols<T>(g, tb, 1, +1, d, spec, s, &dctl->done);
+      if (e != hipSuccess) return e;
+      prof.end(KK_YINV, ev0);
+    }
+    prof.begin(KK_T_LOCAL, &ev0);
+    e = launch_transport_local<T>(g, tb, spec, u, H, dctl, s);
+    if (e != hipSuccess) return e;
+    prof.end(KK_T_LOCAL, ev0);
+    if (d == 3) {
+      prof.begin(KK_YFWD, &ev0);
+      e = launch_cols<T>(g, tb, 1, -1, d + 1, spec, s, &dctl->done);
+      if (e != hipSuccess) return e;
+      prof.end(KK_YFWD, ev0);
+    }
+    prof.begin(KK_T_GREEN, &ev0);
+    e = launch_transport_green<T>(g, tb, 0, spec, chat, chat_m, part, dctl, s);
+    if (e != hipSuccess) return e;
+    prof.end(KK_T_GREEN, ev0);
+    return hipSuccess;
+  };
+
+  int K = o.check_every;
+  if (K <= 0) K = 16;
+  if (o.max_iter < K) K = (int)std::max<int64_t>(1, o.max_iter);
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  const bool use_graph = o.use_graph && !prof.on;
+  if (use_graph) {
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < K && e == hipSuccess; ++k) e = one_iter();
+    hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return fail(ACM_E_HIP, std::string("kernel launch during capture: ") + hipGetErrorString(e));
+    }
+    HIP_TRY(e2);
+    HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  }
+  struct GraphFree {
+    hipGraph_t g;
+    hipGraphExec_t x;
+    ~GraphFree() {
+      if (x) (void)hipGraphExecDestroy(x);
+      if (g) (void)hipGraphDestroy(g);
+    }
+  } gf{graph, exec};
+  TransportCtl* hctl = nullptr;
+  HIP_TRY(hipHostMalloc((void**)&hctl, sizeof(TransportCtl), hipHostMallocDefault));
+  struct HostFree {
+    void* p;
+    ~HostFree() {
+      if (p) (void)hipHostFree(p);
+    }
+  } hf{hctl};
+
+  auto t0 = std::chrono::steady_clock::now();
+  int64_t total = 0;
+  int status = 0;
+  for (int step = 0; step < n_steps; ++step) {
+    if (!steady) HIP_TRY(hipMemcpyAsync(chat_m, chat, one_b, hipMemcpyDeviceToDevice, s));
+    c.iter = 0;
+    c.total_iter = total;
+    c.done = 0;
+    c.status = 1;
+    c.counter = 0;
+    HIP_TRY(hipMemcpyAsync(dctl, &c, sizeof(c), hipMemcpyHostToDevice, s));
+    int64_t launched = 0;
+    for (;;) {
+      if (use_graph) {
+        HIP_TRY(hipGraphLaunch(exec, s));
+      } else {
+        for (int k = 0; k < K; ++k) {
+          hipError_t e = one_iter();
+          if (e != hipSuccess) return fail(ACM_E_HIP, std::string("launch: ") + hipGetErrorString(e));
+        }
+      }
+      launched += K;
+      HIP_TRY(hipMemcpyAsync(hctl, dctl, sizeof(TransportCtl), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      prof.collect();
+      if (hctl->done) break;
+      if (launched > o.max_iter + 2LL * K) break;
+    }
+    total = hctl->total_iter;
+    if (hctl->status == -5) {
+      status = -5;
+      break;
+    }
+    if (hctl->status != 0) status = 1;
+  }
+  auto t1 = std::chrono::steady_clock::now();
+  if (status == -5) return fail(ACM_E_DIVERGED, "a transport residual became non-finite");
+  // read-out: chi = inverse FFT of chi-hat
+  HIP_TRY(hipMemcpyAsync(spec, chat, one_b, hipMemcpyDeviceToDevice, s));
+  {
+    hipError_t e = hipSuccess;
+    if (d == 3) e = launch_cols<T>(g, tb, 2, +1, 1, spec, s);
+    if (e == hipSuccess) e = launch_cols<T>(g, tb, 1, +1, 1, spec, s);
+    if (e == hipSuccess) e = launch_rows_c2r<T>(g, tb, 1, spec, chi, 1.0 / (double)g.ntot, s);
+    if (e != hipSuccess) return fail(ACM_E_HIP, hipGetErrorString(e));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  if (st) {
+    memset(st, 0, sizeof(*st));
+    st->iters = total;
+    st->r_p[0] = hctl->r1;
+    st->r_p[1] = hctl->r2;
+    st->tol_p[0] = c.sqrt_n1 * o.eps;
+    st->tol_p[1] = c.sqrt_n2 * o.eps;
+    st->seconds = std::chrono::duration<double>(t1 - t0).count();
+    st->converged = status == 0;
+    st->status = status;
+    for (int k = 0; k < KK_COUNT; ++k) {
+      st->kernel_ms[k] = prof.ms[k];
+      st->kernel_calls[k] = prof.calls[k];
+    }
+  }
+  return status == 0 ? ACM_OK : ACM_NOT_CONVERGED;
+}
+
+// --------------------------------------------------------------- properties
+template <typename T>
+static acm_status props_impl(CellPlan* pl, const uint8_t* H, int n_flow, const void* const* u,
+                             int n_chi, const void* const* chi, const void* u_tr, double nu,
+                             double Pe, double* K, double* D, double* mass, hipStream_t caller) {
+  const Geom& g = pl->g;
+  const int d = g.dim;
+  hipStream_t s = work_stream(pl->device);
+  if (!s) return fail(ACM_E_HIP, "cannot create work stream");
+  HIP_TRY(join_from(caller, s));
+  const double N = (double)g.ntot;
+  std::vector<double> fs;
+  if (K) {
+    for (int i = 0; i < n_flow; ++i) {
+      acm_status r = reduce_on_host(g, s, &fs, [&](double* part, int* ns) {
+        return launch_flow_sums<T>(g, (const T*)u[i], H, part, ns, s);
+      });
+      if (r != ACM_OK) return r;
+      for (int j = 0; j < d; ++j) K[i * d + j] = fs[1 + d + j] / (N * nu);
+    }
+  }
+  if (n_chi > 0 && (D || mass)) {
+    acm_status r = reduce_on_host(g, s, &fs, [&](double* part, int* ns) {
+      return launch_flow_sums<T>(g, (const T*)u_tr, H, part, ns, s);
+    });
+    if (r != ACM_OK) return r;
+    const double npore = fs[0];
+    if (!(npore > 0.0)) return fail(ACM_E_INVALID, "H has no pore voxel");
+    std::vector<double> ubar(d);
+    for (int c = 0; c < d; ++c) ubar[c] = fs[1 + c] / npore;
+    const double por = npore / N;
+    for (int j = 0; j < n_chi; ++j) {
+      std::vector<double> cs;
+      r = reduce_on_host(g, s, &cs, [&](double* part, int* ns) {
+        return launch_chi_sums<T>(g, (const T*)chi[j], (const T*)u_tr, H, part, ns, s);
+      });
+      if (r != ACM_OK) return r;
+      if (mass) mass[j] = cs[0] / N;
+      if (D)
+        for (int i = 0; i < d; ++i)
+          D[i * n_chi + j] = (i == j ? por : 0.0) + Pe * (ubar[i] * cs[1] - cs[2 + i]) / N +
+                             cs[2 + d + i] / N;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  return ACM_OK;
+}
+
 // --------------------------------------------------------------------- FFT
 template <typename T>
 static acm_status fft_impl(CellPlan* pl, int nfields, const void* in, void* out, bool forward,
@@ -530,7 +820,7 @@ void acm_default_opts(acm_opts* o) {
 
 const char* acm_last_error(void) { return g_err.c_str(); }
 
-int32_t acm_version(void) { return 1; }
+int32_t acm_version(void) { return 2; }
 
 acm_status acm_stokes_solve(const acm_grid* grid, const uint8_t* H, const double* g_p, double nu,
                             const acm_penalty* pen, const acm_opts* opts, void* u, void* q,
@@ -599,18 +889,55 @@ acm_status acm_transport_step(const acm_grid* grid, const uint8_t* H, const void
                               const double* g_chi, double Pe, double diffusivity, double eta,
                               double A0, const double* B0, double dt, int32_t n_steps,
                               const acm_opts* opts, void* chi, acm_stats* stats, void* stream) {
-  (void)grid; (void)H; (void)u; (void)g_chi; (void)Pe; (void)diffusivity; (void)eta; (void)A0;
-  (void)B0; (void)dt; (void)n_steps; (void)opts; (void)chi; (void)stats; (void)stream;
-  return fail(ACM_E_INVALID, "acm_transport_step: not available in this build");
+  g_err.clear();
+  acm_opts O;
+  acm_default_opts(&O);
+  if (opts) O = *opts;
+  if (!H || !u || !g_chi || !B0 || !chi) return fail(ACM_E_INVALID, "H, u, g_chi, B0, chi must be non-NULL");
+  if (!(A0 > 0.0) || !isfinite(A0)) return fail(ACM_E_INVALID, "A0 must be positive");
+  if (!(eta > 0.0) || !(diffusivity > 0.0)) return fail(ACM_E_INVALID, "eta and diffusivity must be positive");
+  if (!isfinite(Pe)) return fail(ACM_E_INVALID, "Pe must be finite");
+  if (n_steps < 1) return fail(ACM_E_INVALID, "n_steps >= 1 required");
+  if (isfinite(dt) ? !(dt > 0.0) : !(dt > 0.0)) return fail(ACM_E_INVALID, "dt must be > 0 or +INFINITY");
+  if (!isfinite(dt) && n_steps != 1) return fail(ACM_E_INVALID, "the steady problem takes n_steps = 1");
+  if (!(O.eps >= 0.0) || O.max_iter < 1) return fail(ACM_E_INVALID, "eps >= 0 and max_iter >= 1 required");
+  CellPlan* pl = nullptr;
+  acm_status r = get_plan(grid, O.precision, &pl);
+  if (r != ACM_OK) return r;
+  for (int k = 0; k < grid->dim; ++k)
+    if (!isfinite(g_chi[k]) || !isfinite(B0[k])) return fail(ACM_E_INVALID, "g_chi, B0 must be finite");
+  if (O.precision == ACM_FP64)
+    return transport_impl<double>(pl, H, (const double*)u, g_chi, Pe, diffusivity, eta, A0, B0, dt,
+                                  n_steps, O, (double*)chi, stats, (hipStream_t)stream);
+  return transport_impl<float>(pl, H, (const float*)u, g_chi, Pe, diffusivity, eta, A0, B0, dt,
+                               n_steps, O, (float*)chi, stats, (hipStream_t)stream);
 }
 
 acm_status acm_effective_props(const acm_grid* grid, int32_t precision, const uint8_t* H,
                                int32_t n_flow, const void* const* u, int32_t n_chi,
                                const void* const* chi, const void* u_transport, double nu,
                                double Pe, double* K, double* D, double* mass, void* stream) {
-  (void)grid; (void)precision; (void)H; (void)n_flow; (void)u; (void)n_chi; (void)chi;
-  (void)u_transport; (void)nu; (void)Pe; (void)K; (void)D; (void)mass; (void)stream;
-  return fail(ACM_E_INVALID, "acm_effective_props: not available in this build");
+  g_err.clear();
+  if (!H) return fail(ACM_E_INVALID, "H must be non-NULL");
+  if (n_flow < 0 || n_chi < 0) return fail(ACM_E_INVALID, "counts must be >= 0");
+  if (K && n_flow > 0 && !u) return fail(ACM_E_INVALID, "u must be non-NULL when K is requested");
+  if (n_chi > 0 && (D || mass) && (!chi || !u_transport))
+    return fail(ACM_E_INVALID, "chi and u_transport must be non-NULL when D or mass is requested");
+  if (K && !(nu > 0.0)) return fail(ACM_E_INVALID, "nu must be positive");
+  CellPlan* pl = nullptr;
+  acm_status r = get_plan(grid, precision, &pl);
+  if (r != ACM_OK) return r;
+  if (K)
+    for (int i = 0; i < n_flow; ++i)
+      if (!u[i]) return fail(ACM_E_INVALID, "null flow field");
+  if (n_chi > 0 && (D || mass))
+    for (int j = 0; j < n_chi; ++j)
+      if (!chi[j]) return fail(ACM_E_INVALID, "null chi field");
+  if (precision == ACM_FP64)
+    return props_impl<double>(pl, H, n_flow, u, n_chi, chi, u_transport, nu, Pe, K, D, mass,
+                              (hipStream_t)stream);
+  return props_impl<float>(pl, H, n_flow, u, n_chi, chi, u_transport, nu, Pe, K, D, mass,
+                           (hipStream_t)stream);
 }
 
 }  // extern "C"

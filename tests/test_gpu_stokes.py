@@ -10,6 +10,9 @@ from paper_2312_15554_amd import inputs as I
 from tests.gpu_common import dev, host, require_gpu
 
 
+SLAB_SHAPES = [(16, 32, 32), (8, 48, 48), (8, 96, 96)]
+
+
 def _solve(H, g, **kw):
     from paper_2312_15554_amd.api import acm_stokes_solve
     return acm_stokes_solve(dev(H), g, **kw)
@@ -43,6 +46,28 @@ def test_fixed_penalty_iterates_match_oracle(shape, dtype):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("shape", SLAB_SHAPES)
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("pass_mode", [1, 2])
+def test_fused_and_separate_passes_match_oracle(shape, dtype, pass_mode):
+    """Both 3D pass structures (separate x/y passes and fused xy slabs)
+    reproduce the oracle's iterates with fixed penalties."""
+    require_gpu()
+    print(f"pass parity shape={shape} dtype={dtype} mode={pass_mode}", flush=True)
+    H = I.overlapping_spheres(shape, shape[-1] / 16.0, 0.5, seed=5)
+    g = (0.7, -0.2, 1.0)
+    M = 25
+    r = _solve(H, g, dtype=dtype, penalty=dict(alpha=40.0, beta=60.0, b=25.0, adaptive=0),
+               eps=0.0, max_iter=M, pass_mode=pass_mode)
+    o = O.stokes_admm(H, g, alpha=40.0, beta=60.0, b=25.0, adaptive=False, eps=0.0, max_iter=M)
+    tol = 1e-11 if dtype == torch.float64 else 2e-5
+    u = host(r["u"])
+    assert np.abs(u - o["u"]).max() < tol * np.abs(o["u"]).max()
+    for k in range(3):
+        assert abs(r["stats"]["r_d"][k] - o["r_d"][k]) <= tol * 100 * o["r_d"][k] + 1e-12
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_poiseuille_closed_form(dtype):
     require_gpu()
@@ -60,22 +85,44 @@ def test_poiseuille_closed_form(dtype):
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_converged_permeability_matches_oracle(dtype):
-    """Converged K tensor of a 16^3 overlapping-sphere cell vs the oracle at a
-    tight tolerance (both reach the same discrete fixed point)."""
+def test_converged_permeability_matches_kkt_solution(dtype):
+    """Converged K tensor of a 16^3 overlapping-sphere cell against the exact
+    discrete fixed point (sparse KKT solve of the same discretisation)."""
     require_gpu()
     H = I.overlapping_spheres(16, 1.0, 0.45, seed=3)
-    eps = 1e-10 if dtype == torch.float64 else 1e-8
-    us_gpu, us_or = [], []
+    eps = 1e-11 if dtype == torch.float64 else 1e-8
+    us_gpu, us_ref = [], []
     for g in [(1, 0, 0), (0, 1, 0), (0, 0, 1)]:
+        print(f"converged K dtype={dtype} g={g}", flush=True)
         r = _solve(H, g, dtype=dtype, eps=eps, max_iter=200000)
         assert r["stats"]["converged"], r["stats"]
         us_gpu.append(host(r["u"]).astype(np.float64))
-        us_or.append(O.stokes_admm(H, g, eps=1e-11)["u"])
+        us_ref.append(O.brute_force_stokes(H, g)[0])
     Kg = O.permeability_darcy(us_gpu)
-    Ko = O.permeability_darcy(us_or)
-    rel = np.abs(Kg - Ko).max() / np.abs(Ko).max()
-    assert rel < (1e-8 if dtype == torch.float64 else 1e-5), rel
+    Kr = O.permeability_darcy(us_ref)
+    rel = np.abs(Kg - Kr).max() / np.abs(Kr).max()
+    # FP32 transforms settle at a noise floor of a few 1e-5 in K on this cell
+    assert rel < (1e-7 if dtype == torch.float64 else 1e-4), rel
+
+
+@pytest.mark.gpu
+def test_fp32_permeability_tracks_fp64_at_same_eps():
+    """At the benchmark tolerance eps = 1e-6 the FP32 path (FP32 transforms,
+    FP64 reductions) and the FP64 path (whose iterates follow the oracle's)
+    give the same K to a few 1e-5."""
+    require_gpu()
+    H = I.overlapping_spheres(32, 2.0, 0.4, seed=1)
+    Ks = {}
+    for dt in (torch.float64, torch.float32):
+        us = []
+        for g in [(1, 0, 0), (0, 1, 0), (0, 0, 1)]:
+            r = _solve(H, g, dtype=dt, eps=1e-6, max_iter=100000)
+            assert r["stats"]["converged"]
+            us.append(host(r["u"]).astype(np.float64))
+        Ks[dt] = O.permeability_darcy(us)
+    rel = np.abs(Ks[torch.float32] - Ks[torch.float64]).max() / np.abs(Ks[torch.float64]).max()
+    print("K fp32 vs fp64 rel", rel)
+    assert rel < 1e-4, rel
 
 
 @pytest.mark.gpu
@@ -85,13 +132,41 @@ def test_abi_error_codes():
     from paper_2312_15554_amd.api import acm_stokes_solve
     Hf = torch.zeros((16, 16), dtype=torch.uint8, device="cuda")
     with pytest.raises(abi.AcmError) as e:
-        acm_stokes_solve(Hf, (1.0, 0.0))
+        acm_stokes_solve(Hf, (1.0, 0.0), max_iter=10)
     assert e.value.status == abi.ACM_E_INVALID
     Hb = torch.ones((20, 20), dtype=torch.uint8, device="cuda")
     with pytest.raises(abi.AcmError) as e:
-        acm_stokes_solve(Hb, (1.0, 0.0))
+        acm_stokes_solve(Hb, (1.0, 0.0), max_iter=10)
     assert e.value.status == abi.ACM_E_UNSUPPORTED_SIZE
     H = dev(I.centred_disc(16))
     r = acm_stokes_solve(H, (1.0, 0.0), max_iter=1)
     assert r["status"] == abi.ACM_NOT_CONVERGED and r["stats"]["iters"] == 1
     assert torch.isfinite(r["u"]).all()
+
+
+def _golden():
+    import json
+    import os
+    return json.load(open(os.path.join(os.path.dirname(__file__), "golden", "stokes_reference.json")))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_c1_model_cell_matches_oracle(dtype):
+    """2D model cell (64^2 disc, eps = 1e-8, model-geometry schedule): k_xx of
+    the HIP path against the oracle's ADMM run to the same eps (stored by
+    tests/golden/make_golden.py) and against the exact KKT value."""
+    require_gpu()
+    ref = _golden()["c1"]
+    H = I.centred_disc(64, 0.2)
+    r = _solve(H, (1.0, 0.0), dtype=dtype, eps=ref["admm_eps"], max_iter=200000,
+               penalty=dict(tau=tuple(ref["admm_tau"])))
+    assert r["stats"]["converged"]
+    k = float(r["u"][0].double().mean())
+    if dtype == torch.float64:
+        assert r["stats"]["iters"] == ref["admm_iters"]
+        assert abs(k - ref["admm_kxx"]) < 1e-10 * ref["admm_kxx"]
+    else:
+        assert abs(r["stats"]["iters"] - ref["admm_iters"]) < 0.1 * ref["admm_iters"]
+        assert abs(k - ref["admm_kxx"]) < 1e-5 * ref["admm_kxx"]
+    assert abs(k - ref["kkt_kxx"]) < 5e-5 * ref["kkt_kxx"]

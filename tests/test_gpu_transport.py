@@ -1,0 +1,118 @@
+"""Parity of the HIP Lippmann-Schwinger transport path and the effective
+properties (through the C ABI) with the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import acm_oracle as O
+from paper_2312_15554_amd import inputs as I
+from tests.gpu_common import dev, host, require_gpu
+
+
+_FLOWS = {}
+
+
+def _flow(H, g):
+    key = (H.tobytes(), H.shape, tuple(g))
+    if key not in _FLOWS:
+        u, _ = O.brute_force_stokes(H, g)
+        _FLOWS[key] = u / np.abs(u).max()
+    return _FLOWS[key]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("shape", [(16, 16), (16, 24, 32), (16, 16, 16)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("dt", [math.inf, 5e-3])
+def test_ls_iterates_match_oracle(shape, dtype, dt):
+    """Fixed iteration count (eps = 0): chi of the HIP path equals the
+    oracle's after the same LS iterations (eq. iter / eq. fft_solute)."""
+    require_gpu()
+    from paper_2312_15554_amd.api import acm_transport_step
+    print(f"LS parity shape={shape} dtype={dtype} dt={dt}", flush=True)
+    d = len(shape)
+    H = I.random_mask(shape, 23, 0.3)
+    u = I.random_field((d,) + shape, 29) * (1 - H)  # any advecting field will do here
+    g = (0.3, 1.0, -0.5)[:d]
+    B0 = (0.6, 0.0, 0.1)[:d]
+    M, steps = 12, (1 if math.isinf(dt) else 3)
+    r = acm_transport_step(dev(H), dev(u, dtype), g, 4.0, A0=0.55, B0=B0, eta=0.01, dt=dt,
+                           n_steps=steps, eps=0.0, max_iter=M)
+    o = O.transport_ls(H, u, g, 4.0, A0=0.55, B0=B0, eta=0.01, dt=dt, n_steps=steps, eps=0.0,
+                       max_iter=M)
+    assert r["stats"]["iters"] == M * steps
+    chi = host(r["chi"])
+    tol = 1e-11 if dtype == torch.float64 else 3e-5
+    assert np.abs(chi - o["chi"]).max() < tol * np.abs(o["chi"]).max()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_steady_transport_matches_brute_force(dtype):
+    require_gpu()
+    from paper_2312_15554_amd.api import acm_transport_step
+    H = I.random_mask((16, 16, 16), 5, 0.3)
+    u = _flow(H, (1.0, 0.0, 0.0))
+    g = (1.0, 0.0, 0.0)
+    ref = O.brute_force_transport(H, u, g, 5.0, A0=0.55, eta=0.01)
+    eps = 1e-11 if dtype == torch.float64 else 1e-7
+    r = acm_transport_step(dev(H), dev(u, dtype), g, 5.0, A0=0.55, B0=(1.0, 0, 0), eta=0.01,
+                           eps=eps, max_iter=20000)
+    assert r["stats"]["converged"]
+    tol = 1e-7 if dtype == torch.float64 else 5e-5
+    assert np.abs(host(r["chi"]) - ref).max() < tol * np.abs(ref).max()
+
+
+@pytest.mark.gpu
+def test_diffusion_mode_decay_closed_form():
+    require_gpu()
+    from paper_2312_15554_amd.api import acm_transport_step
+    shape = (32, 32, 32)
+    H = np.zeros(shape, np.uint8)
+    u = np.zeros((3,) + shape)
+    z, y, x = np.meshgrid(*[(np.arange(32) + 0.5) / 32] * 3, indexing="ij")
+    mode = (1, 2, 1)
+    chi0 = np.cos(2 * np.pi * (mode[0] * x + mode[1] * y + mode[2] * z))
+    dt, n = 2e-3, 10
+    r = acm_transport_step(dev(H), dev(u, torch.float32), (0.0, 0.0, 0.0), 0.0, A0=0.55, B0=(0, 0, 0),
+                           dt=dt, n_steps=n, eps=1e-7, max_iter=500, chi=dev(chi0, torch.float32))
+    amp = O.diffusion_mode_amplitude(shape, mode, dt, n, 0.55)
+    assert r["stats"]["converged"]
+    assert np.abs(host(r["chi"]) - amp * chi0).max() < 5e-6
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_effective_props_match_oracle_on_same_fields(dtype):
+    require_gpu()
+    from paper_2312_15554_amd.api import acm_effective_props
+    shape = (16, 24, 32)
+    H = I.random_mask(shape, 31, 0.35)
+    us = [I.random_field((3,) + shape, s) * (1 - H) for s in (1, 2, 3)]
+    chis = [I.random_field(shape, s) for s in (4, 5, 6)]
+    r = acm_effective_props(dev(H), [dev(x, dtype) for x in us], [dev(x, dtype) for x in chis],
+                            u_transport=dev(us[0], dtype), nu=0.7, Pe=3.0)
+    cast = (lambda a: a.astype(np.float32).astype(np.float64)) if dtype == torch.float32 else (lambda a: a)
+    Ko = O.permeability_darcy([cast(x) for x in us], nu=0.7)
+    Do = O.effective_diffusivity(H, cast(us[0]), [cast(c) for c in chis], 3.0)
+    mo = np.array([O.solute_mass(cast(c)) for c in chis])
+    assert np.allclose(r["K"], Ko, rtol=1e-12, atol=1e-14)
+    assert np.allclose(r["D"], Do, rtol=1e-12, atol=1e-13)
+    assert np.allclose(r["mass"], mo, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.gpu
+def test_mismatched_buffers_are_rejected_before_launch():
+    require_gpu()
+    from paper_2312_15554_amd.api import acm_stokes_solve, acm_transport_step
+    H = dev(np.zeros((16, 16, 16), np.uint8))
+    u64 = torch.zeros((3, 16, 16, 16), dtype=torch.float64, device="cuda")
+    chi32 = torch.zeros((16, 16, 16), dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        acm_transport_step(H, u64, (1, 0, 0), 1.0, chi=chi32, max_iter=10)
+    with pytest.raises(ValueError):
+        acm_stokes_solve(H, (1, 0, 0), u=u64, max_iter=10)  # default dtype is float32
+    with pytest.raises(ValueError):
+        acm_transport_step(H, u64[:2].contiguous(), (1, 0, 0), 1.0, max_iter=10)
