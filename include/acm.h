@@ -139,6 +139,26 @@ acm_status acm_stokes_solve(const acm_grid* grid, const uint8_t* H, const double
                             acm_stats* stats, double* history, void* stream);
 
 /*
+ * Many independent Stokes cells (possibly of different sizes) in one call.
+ * Cells with the same grid share every launch of a pass (the cell index is a
+ * grid dimension of each kernel); different sizes run as parallel branches of
+ * one captured HIP graph.  Each cell keeps its own control block: penalties,
+ * residuals and convergence are per cell (as acm_stokes_solve), and a cell
+ * that has converged is skipped by every later launch.
+ *   ncell  number of cells; grids[i] its grid; H[i], u[i] device pointers
+ *   g_p    host array ncell x 3 (entries beyond a cell's dim ignored)
+ *   q      NULL or array of ncell device pointers (entries may be NULL)
+ *   stats  NULL or host array of ncell records; stats[i].seconds is the time
+ *          from the first iteration until cell i was seen converged.
+ * Returns ACM_OK if every cell converged, ACM_NOT_CONVERGED if any did not
+ * (per-cell status in stats), or a negative status.
+ */
+acm_status acm_stokes_solve_batched(int32_t ncell, const acm_grid* grids, const uint8_t* const* H,
+                                    const double* g_p, double nu, const acm_penalty* pen,
+                                    const acm_opts* opts, void* const* u, void* const* q,
+                                    acm_stats* stats, void* stream);
+
+/*
  * Penalised advection-diffusion (Section 3.2, eq. penalization) by the
  * Lippmann-Schwinger iteration (eq. iter solved by eq. fft_solute, stopping
  * test eq. tol_solute):

@@ -49,6 +49,10 @@ SIGNATURES = {
     "acm_stokes_solve": (C.c_int, [C.POINTER(acm_grid), C.c_void_p, C.POINTER(C.c_double), C.c_double,
                                    C.POINTER(acm_penalty), C.POINTER(acm_opts), C.c_void_p, C.c_void_p,
                                    C.POINTER(acm_stats), C.POINTER(C.c_double), C.c_void_p]),
+    "acm_stokes_solve_batched": (C.c_int, [C.c_int32, C.POINTER(acm_grid), C.POINTER(C.c_void_p),
+                                           C.POINTER(C.c_double), C.c_double, C.POINTER(acm_penalty),
+                                           C.POINTER(acm_opts), C.POINTER(C.c_void_p),
+                                           C.POINTER(C.c_void_p), C.POINTER(acm_stats), C.c_void_p]),
     "acm_transport_step": (C.c_int, [C.POINTER(acm_grid), C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
                                      C.c_double, C.c_double, C.c_double, C.c_double,
                                      C.POINTER(C.c_double), C.c_double, C.c_int32,

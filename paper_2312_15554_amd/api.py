@@ -140,6 +140,48 @@ def acm_stokes_solve(H: torch.Tensor, g, nu: float = 1.0, *, dtype=torch.float32
     return dict(u=u, q=q, status=status, stats=stats_dict(st), history=history)
 
 
+def acm_stokes_solve_batched(Hs, gs, nu: float = 1.0, *, dtype=torch.float32,
+                             penalty: dict | None = None, eps: float = 1e-6,
+                             max_iter: int = 1_000_000, check_every: int = 0,
+                             use_graph: bool = True, us=None, qs=None, warm_start: bool = False,
+                             pass_mode: int = 0, stream=None) -> dict:
+    """Many cells in one call (acm_stokes_solve_batched).  Hs: list of uint8
+    device tensors (any supported sizes), gs: list of body forces.  Returns
+    dict(us, qs, status, stats=[per-cell dicts])."""
+    lib = abi.load()
+    n = len(Hs)
+    if len(gs) != n:
+        raise ValueError("one body force per cell")
+    grids = (abi.acm_grid * n)()
+    gp = (C.c_double * (3 * n))()
+    if us is None:
+        us = [torch.empty((len(H.shape),) + tuple(H.shape), dtype=dtype, device=H.device) for H in Hs]
+    for i, H in enumerate(Hs):
+        _check_H(H)
+        shape = tuple(H.shape)
+        _expect(us[i], (len(shape),) + shape, dtype, f"u[{i}]")
+        if qs is not None and qs[i] is not None:
+            _expect(qs[i], shape, dtype, f"q[{i}]")
+        g1 = _grid(shape)
+        grids[i].dim = g1.dim
+        for k in range(3):
+            grids[i].n[k] = g1.n[k]
+            gp[3 * i + k] = float(gs[i][k]) if k < len(gs[i]) else 0.0
+    hp = (C.c_void_p * n)(*[H.data_ptr() for H in Hs])
+    up = (C.c_void_p * n)(*[u.data_ptr() for u in us])
+    qp = None
+    if qs is not None:
+        qp = (C.c_void_p * n)(*[(q.data_ptr() if q is not None else None) for q in qs])
+    pen = default_penalty(**(penalty or {}))
+    opts = default_opts(eps=eps, max_iter=max_iter, precision=_prec(dtype), check_every=check_every,
+                        use_graph=int(use_graph), warm_start=int(warm_start), pass_mode=int(pass_mode))
+    st = (abi.acm_stats * n)()
+    status = lib.acm_stokes_solve_batched(n, grids, hp, gp, float(nu), C.byref(pen), C.byref(opts),
+                                          up, qp, st, _stream(stream))
+    abi.check(status)
+    return dict(us=us, qs=qs, status=status, stats=[stats_dict(st[i]) for i in range(n)])
+
+
 def acm_fft_r2c(x: torch.Tensor, cell_shape, stream=None) -> torch.Tensor:
     """Forward real FFT of x with shape (nfields, *cell_shape) -> half spectra
     (nfields, *cell_shape[:-1], nx//2+1) complex."""

@@ -77,6 +77,26 @@ struct TransportCtl {
   int32_t steady;
 };
 
+// Per-cell device pointers of one Stokes solve.  Kernels of a batched launch
+// read the entry of their cell (blockIdx.z); a single cell passes it by value.
+struct StokesCellArgs {
+  void* spec;          // complex [d][nspec]
+  void* qhat;          // complex [nspec]
+  void* dhat;          // complex [nspec]
+  void* u;             // real [d][ntot]
+  void* a;             // real [d][ntot]
+  const uint8_t* H;    // uint8 [ntot]
+  double* part;        // green partials [3*ngreen] then local partials [4*nlocal]
+  StokesCtl* ctl;
+  double* hist;        // may be null
+};
+
+// Per-cell pointers of a column (y or z) transform.
+struct ColCellArgs {
+  void* data;
+  const int32_t* skip;  // may be null; when *skip != 0 the cell is skipped
+};
+
 enum KernelKind {
   KK_GREEN = 0,
   KK_LOCAL = 1,
@@ -114,19 +134,23 @@ hipError_t launch_rows_c2r(const Geom& g, const DevTables<T>& tb, int nfields, c
 template <typename T>
 hipError_t launch_cols(const Geom& g, const DevTables<T>& tb, int axis, int sign, int nfields,
                        void* data, hipStream_t s, const int32_t* skip = nullptr);
-
-// Stokes ADMM passes.
+// Batched form: cells[0..ncells) (device array) with one transform each.
 template <typename T>
-hipError_t launch_stokes_green(const Geom& g, const DevTables<T>& tb, void* spec, void* qhat,
-                               void* dhat, double* partials, StokesCtl* ctl, int* nblocks,
+hipError_t launch_cols_batched(const Geom& g, const DevTables<T>& tb, int axis, int sign,
+                               int nfields, const ColCellArgs* cells, int ncells, hipStream_t s);
+
+// Stokes ADMM passes.  `one` is used when `many` is null (single cell);
+// otherwise cell i = blockIdx.z reads many[i] and ncells cells are launched.
+template <typename T>
+hipError_t launch_stokes_green(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
+                               const StokesCellArgs* many, int ncells, hipStream_t s);
+template <typename T>
+hipError_t launch_stokes_local(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
+                               const StokesCellArgs* many, int ncells, int green_blocks,
                                hipStream_t s);
 template <typename T>
-hipError_t launch_stokes_local(const Geom& g, const DevTables<T>& tb, const void* spec, T* u,
-                               T* a, const uint8_t* H, double* partials, int green_blocks,
-                               StokesCtl* ctl, double* hist, int* nblocks, hipStream_t s);
-template <typename T>
-hipError_t launch_stokes_rhs(const Geom& g, const DevTables<T>& tb, void* spec, const T* u,
-                             const T* a, const uint8_t* H, StokesCtl* ctl, hipStream_t s);
+hipError_t launch_stokes_rhs(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
+                             const StokesCellArgs* many, int ncells, hipStream_t s);
 
 // Lippmann-Schwinger passes.  mode 0: LS update; mode 1: grad chi-hat only.
 template <typename T>
@@ -147,18 +171,24 @@ hipError_t launch_chi_sums(const Geom& g, const T* chi, const T* u, const uint8_
                            double* part, int* nsums, hipStream_t s);
 int reduction_blocks(const Geom& g);
 
+// Warm start: a = H (g - grad q + nu Delta_h u0), div = div_c u0 (real, in
+// `div`), then u <- (1-H) u in place.  q may be null (q0 = 0).
+template <typename T>
+hipError_t launch_warm_init(const Geom& g, const T* u, const T* q, const uint8_t* H, T* a, T* div,
+                            double nu, const double* gp, hipStream_t s);
+
 // Fused xy-slab Stokes passes (3D, nx == ny, slab of one field in LDS).
 template <typename T>
 bool slab_supported(const Geom& g);
 template <typename T>
 int slab_local_blocks(const Geom& g);
 template <typename T>
-hipError_t launch_slab_local(const Geom& g, const DevTables<T>& tb, const void* spec, T* u, T* a,
-                             const uint8_t* H, double* partials, int green_blocks,
-                             StokesCtl* ctl, double* hist, hipStream_t s);
+hipError_t launch_slab_local(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
+                             const StokesCellArgs* many, int ncells, int green_blocks,
+                             hipStream_t s);
 template <typename T>
-hipError_t launch_slab_rhs(const Geom& g, const DevTables<T>& tb, void* spec, const T* u,
-                           const T* a, const uint8_t* H, StokesCtl* ctl, hipStream_t s);
+hipError_t launch_slab_rhs(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
+                           const StokesCellArgs* many, int ncells, hipStream_t s);
 
 // Grid-size helpers used by the host to size partial-sum buffers.
 int stokes_green_blocks(const Geom& g, int precision_bytes);

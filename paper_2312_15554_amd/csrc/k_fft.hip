@@ -69,12 +69,14 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_rows_c2r(const cplx<T>* 
 }
 
 template <typename T, int L, int SIGN>
-__global__ __launch_bounds__((ColCfg<T, L, 1>::NT)) void k_cols(cplx<T>* __restrict__ data,
+__global__ __launch_bounds__((ColCfg<T, L, 1>::NT)) void k_cols(ColCellArgs one,
+                                                              const ColCellArgs* __restrict__ many,
                                                               int64_t field_stride, ColMap m,
-                                                              const cplx<T>* __restrict__ tw,
-                                                              const int32_t* __restrict__ skip) {
+                                                              const cplx<T>* __restrict__ tw) {
   using C = ColCfg<T, L, 1>;
-  if (skip != nullptr && *skip) return;
+  const ColCellArgs ca = many ? many[blockIdx.z] : one;
+  if (ca.skip != nullptr && *ca.skip) return;
+  cplx<T>* data = reinterpret_cast<cplx<T>*>(ca.data);
   extern __shared__ __align__(16) char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* base = data + blockIdx.y * field_stride;
@@ -138,8 +140,9 @@ hipError_t launch_rows_c2r(const Geom& g, const DevTables<T>& tb, int nfields, c
 }
 
 template <typename T>
-hipError_t launch_cols(const Geom& g, const DevTables<T>& tb, int axis, int sign, int nfields,
-                       void* data, hipStream_t s, const int32_t* skip) {
+static hipError_t cols_impl(const Geom& g, const DevTables<T>& tb, int axis, int sign,
+                            int nfields, const ColCellArgs& one, const ColCellArgs* many,
+                            int ncells, hipStream_t s) {
   const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
   ColMap m;
   int L;
@@ -161,18 +164,18 @@ hipError_t launch_cols(const Geom& g, const DevTables<T>& tb, int axis, int sign
   } else {
     return hipErrorInvalidValue;
   }
-  cplx<T>* d = reinterpret_cast<cplx<T>*>(data);
   switch (L) {
 #define CASE(LL)                                                                            \
   case LL: {                                                                                \
     using C = ColCfg<T, LL, 1>;                                                             \
-    dim3 grid((unsigned)((m.ncols + C::TX - 1) / C::TX), (unsigned)nfields);                \
+    dim3 grid((unsigned)((m.ncols + C::TX - 1) / C::TX), (unsigned)nfields,                 \
+              (unsigned)ncells);                                                            \
     if (sign < 0)                                                                           \
-      hipLaunchKernelGGL((k_cols<T, LL, -1>), grid, dim3(C::NT), C::LDS_BYTES, s, d,         \
-                         g.nspec, m, tw, skip);                                             \
+      hipLaunchKernelGGL((k_cols<T, LL, -1>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many, \
+                         g.nspec, m, tw);                                                   \
     else                                                                                    \
-      hipLaunchKernelGGL((k_cols<T, LL, 1>), grid, dim3(C::NT), C::LDS_BYTES, s, d, g.nspec, \
-                         m, tw, skip);                                                      \
+      hipLaunchKernelGGL((k_cols<T, LL, 1>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many,  \
+                         g.nspec, m, tw);                                                   \
     return hipGetLastError();                                                               \
   }
     ACM_COL_LENGTHS(CASE)
@@ -182,13 +185,29 @@ hipError_t launch_cols(const Geom& g, const DevTables<T>& tb, int axis, int sign
   }
 }
 
+template <typename T>
+hipError_t launch_cols(const Geom& g, const DevTables<T>& tb, int axis, int sign, int nfields,
+                       void* data, hipStream_t s, const int32_t* skip) {
+  ColCellArgs one{data, skip};
+  return cols_impl<T>(g, tb, axis, sign, nfields, one, nullptr, 1, s);
+}
+
+template <typename T>
+hipError_t launch_cols_batched(const Geom& g, const DevTables<T>& tb, int axis, int sign,
+                               int nfields, const ColCellArgs* cells, int ncells, hipStream_t s) {
+  ColCellArgs one{nullptr, nullptr};
+  return cols_impl<T>(g, tb, axis, sign, nfields, one, cells, ncells, s);
+}
+
 #define INST(T)                                                                              \
   template hipError_t launch_rows_r2c<T>(const Geom&, const DevTables<T>&, int, const T*,    \
                                          void*, hipStream_t);                                \
   template hipError_t launch_rows_c2r<T>(const Geom&, const DevTables<T>&, int, const void*, \
                                          T*, double, hipStream_t);                           \
   template hipError_t launch_cols<T>(const Geom&, const DevTables<T>&, int, int, int, void*, \
-                                     hipStream_t, const int32_t*);
+                                     hipStream_t, const int32_t*);                           \
+  template hipError_t launch_cols_batched<T>(const Geom&, const DevTables<T>&, int, int, int, \
+                                             const ColCellArgs*, int, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

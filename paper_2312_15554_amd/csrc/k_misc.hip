@@ -114,6 +114,78 @@ hipError_t launch_chi_sums(const Geom& g, const T* chi, const T* u, const uint8_
   return hipGetLastError();
 }
 
+
+// Warm-start state (initial guess u_in, q_in): with u0 = (1-H) u_in,
+//   a0 = lambda0 = H (g - grad_c q0 + nu Delta_h u0)   (the reaction the
+//   fixed point carries in the solid), div = central divergence of u0.
+// Real-space stencils: central first differences, compact second differences.
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_warm_init(const T* __restrict__ u, const T* __restrict__ q,
+                                                   const uint8_t* __restrict__ H, T* __restrict__ a,
+                                                   T* __restrict__ div, int nx, int ny, int nz,
+                                                   double nu, double g0, double g1, double g2) {
+  const int64_t ntot = (int64_t)nx * ny * nz;
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= ntot) return;
+  const int x = (int)(v % nx);
+  const int64_t yz = v / nx;
+  const int y = (int)(yz % ny);
+  const int z = (int)(yz / ny);
+  const int n[3] = {nx, ny, nz};
+  int64_t nb_p[3], nb_m[3];
+  {
+    const int xp = x + 1 == nx ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
+    nb_p[0] = v - x + xp;
+    nb_m[0] = v - x + xm;
+    const int yp = y + 1 == ny ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
+    nb_p[1] = v + (int64_t)(yp - y) * nx;
+    nb_m[1] = v + (int64_t)(ym - y) * nx;
+    if (D == 3) {
+      const int zp = z + 1 == nz ? 0 : z + 1, zm = z == 0 ? nz - 1 : z - 1;
+      nb_p[2] = v + (int64_t)(zp - z) * nx * ny;
+      nb_m[2] = v + (int64_t)(zm - z) * nx * ny;
+    }
+  }
+  auto u0 = [&](int c, int64_t w) -> double { return H[w] ? 0.0 : (double)u[c * ntot + w]; };
+  const double g[3] = {g0, g1, g2};
+  double dv = 0.0;
+  const bool solid = H[v] != 0;
+  for (int c = 0; c < D; ++c) {
+    dv += 0.5 * n[c] * (u0(c, nb_p[c]) - u0(c, nb_m[c]));
+    double lap = 0.0;
+    const double uc = u0(c, v);
+    for (int j = 0; j < D; ++j)
+      lap += (u0(c, nb_p[j]) - 2.0 * uc + u0(c, nb_m[j])) * (double)n[j] * n[j];
+    const double gq = q ? 0.5 * n[c] * ((double)q[nb_p[c]] - (double)q[nb_m[c]]) : 0.0;
+    a[c * ntot + v] = solid ? (T)(g[c] - gq + nu * lap) : T(0);
+  }
+  div[v] = (T)dv;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_mask_pore(T* __restrict__ u, const uint8_t* __restrict__ H,
+                                                   int d, int64_t ntot) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= ntot || !H[v]) return;
+  for (int c = 0; c < d; ++c) u[c * ntot + v] = T(0);
+}
+
+template <typename T>
+hipError_t launch_warm_init(const Geom& g, const T* u, const T* q, const uint8_t* H, T* a, T* div,
+                            double nu, const double* gp, hipStream_t s) {
+  const unsigned nb = (unsigned)((g.ntot + 255) / 256);
+  if (g.dim == 3)
+    hipLaunchKernelGGL((k_warm_init<T, 3>), dim3(nb), dim3(256), 0, s, u, q, H, a, div, g.nx, g.ny,
+                       g.nz, nu, gp[0], gp[1], gp[2]);
+  else
+    hipLaunchKernelGGL((k_warm_init<T, 2>), dim3(nb), dim3(256), 0, s, u, q, H, a, div, g.nx, g.ny,
+                       g.nz, nu, gp[0], gp[1], 0.0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_mask_pore<T>), dim3(nb), dim3(256), 0, s, const_cast<T*>(u), H, g.dim, g.ntot);
+  return hipGetLastError();
+}
+
 int reduction_blocks(const Geom& g) {
   return (int)std::min<int64_t>(kRedBlocks, (g.ntot + kRedThreads - 1) / kRedThreads);
 }
@@ -122,7 +194,9 @@ int reduction_blocks(const Geom& g) {
   template hipError_t launch_flow_sums<T>(const Geom&, const T*, const uint8_t*, double*,    \
                                           int*, hipStream_t);                                \
   template hipError_t launch_chi_sums<T>(const Geom&, const T*, const T*, const uint8_t*,    \
-                                         double*, int*, hipStream_t);
+                                         double*, int*, hipStream_t);                        \
+  template hipError_t launch_warm_init<T>(const Geom&, const T*, const T*, const uint8_t*,   \
+                                          T*, T*, double, const double*, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

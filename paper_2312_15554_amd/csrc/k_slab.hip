@@ -58,12 +58,19 @@ __device__ __forceinline__ void slab_cols(cplx<T>* lds, const cplx<T>* __restric
 
 template <typename T, int NX, int NY>
 __global__ __launch_bounds__(512) void k_slab_local(
-    const cplx<T>* __restrict__ spec, T* __restrict__ u, T* __restrict__ a,
-    const uint8_t* __restrict__ H, double* __restrict__ lpart, const double* __restrict__ gpart,
-    int ngreen, StokesCtl* ctl, double* hist, int64_t ntot, int64_t nspec,
-    const cplx<T>* __restrict__ twx, const cplx<T>* __restrict__ twy,
+    StokesCellArgs one, const StokesCellArgs* __restrict__ many, int ngreen, int64_t ntot,
+    int64_t nspec, const cplx<T>* __restrict__ twx, const cplx<T>* __restrict__ twy,
     const cplx<T>* __restrict__ rtw) {
   using S = SlabCfg<T, NX, NY>;
+  const StokesCellArgs ca = many ? many[blockIdx.z] : one;
+  const cplx<T>* __restrict__ spec = reinterpret_cast<const cplx<T>*>(ca.spec);
+  T* __restrict__ u = reinterpret_cast<T*>(ca.u);
+  T* __restrict__ a = reinterpret_cast<T*>(ca.a);
+  const uint8_t* __restrict__ H = ca.H;
+  const double* __restrict__ gpart = ca.part;
+  double* __restrict__ lpart = ca.part + 3 * (int64_t)ngreen;
+  StokesCtl* ctl = ca.ctl;
+  double* hist = ca.hist;
   using V = typename Vec4<T>::type;
   extern __shared__ __align__(32) char smem_raw[];
   __shared__ double red[4 * 8];
@@ -174,16 +181,19 @@ __global__ __launch_bounds__(512) void k_slab_local(
 }
 
 template <typename T, int NX, int NY>
-__global__ __launch_bounds__(512) void k_slab_rhs(cplx<T>* __restrict__ spec,
-                                                  const T* __restrict__ u,
-                                                  const T* __restrict__ a,
-                                                  const uint8_t* __restrict__ H,
-                                                  const StokesCtl* __restrict__ ctl,
+__global__ __launch_bounds__(512) void k_slab_rhs(StokesCellArgs one,
+                                                  const StokesCellArgs* __restrict__ many,
                                                   int64_t ntot, int64_t nspec,
                                                   const cplx<T>* __restrict__ twx,
                                                   const cplx<T>* __restrict__ twy,
                                                   const cplx<T>* __restrict__ rtw) {
   using S = SlabCfg<T, NX, NY>;
+  const StokesCellArgs ca = many ? many[blockIdx.z] : one;
+  cplx<T>* __restrict__ spec = reinterpret_cast<cplx<T>*>(ca.spec);
+  const T* __restrict__ u = reinterpret_cast<const T*>(ca.u);
+  const T* __restrict__ a = reinterpret_cast<const T*>(ca.a);
+  const uint8_t* __restrict__ H = ca.H;
+  const StokesCtl* __restrict__ ctl = ca.ctl;
   using V = typename Vec4<T>::type;
   extern __shared__ __align__(32) char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -275,21 +285,18 @@ int slab_local_blocks(const Geom& g) {
 }
 
 template <typename T>
-hipError_t launch_slab_local(const Geom& g, const DevTables<T>& tb, const void* spec, T* u, T* a,
-                             const uint8_t* H, double* partials, int green_blocks,
-                             StokesCtl* ctl, double* hist, hipStream_t s) {
+hipError_t launch_slab_local(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
+                             const StokesCellArgs* many, int ncells, int green_blocks,
+                             hipStream_t s) {
   const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
-  const double* gpart = partials;
-  double* lpart = partials + 3 * (int64_t)green_blocks;
-  dim3 grid((unsigned)g.nz, (unsigned)g.dim);
+  dim3 grid((unsigned)g.nz, (unsigned)g.dim, (unsigned)ncells);
   switch (g.nx) {
 #define CASE(N)                                                                                \
   case N: {                                                                                    \
     using S = SlabCfg<T, N, N>;                                                                \
-    hipLaunchKernelGGL((k_slab_local<T, N, N>), grid, dim3(S::NT), S::LDS_BYTES, s,             \
-                       reinterpret_cast<const cplx<T>*>(spec), u, a, H, lpart, gpart,          \
-                       green_blocks, ctl, hist, g.ntot, g.nspec, ct + tb.off.tw_x,             \
-                       ct + tb.off.tw_y, ct + tb.off.rtw);                                     \
+    hipLaunchKernelGGL((k_slab_local<T, N, N>), grid, dim3(S::NT), S::LDS_BYTES, s, one, many,  \
+                       green_blocks, g.ntot, g.nspec, ct + tb.off.tw_x, ct + tb.off.tw_y,      \
+                       ct + tb.off.rtw);                                                       \
     return hipGetLastError();                                                                  \
   }
     ACM_SLAB_LENGTHS(CASE)
@@ -300,17 +307,16 @@ hipError_t launch_slab_local(const Geom& g, const DevTables<T>& tb, const void* 
 }
 
 template <typename T>
-hipError_t launch_slab_rhs(const Geom& g, const DevTables<T>& tb, void* spec, const T* u,
-                           const T* a, const uint8_t* H, StokesCtl* ctl, hipStream_t s) {
+hipError_t launch_slab_rhs(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
+                           const StokesCellArgs* many, int ncells, hipStream_t s) {
   const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
-  dim3 grid((unsigned)g.nz, (unsigned)g.dim);
+  dim3 grid((unsigned)g.nz, (unsigned)g.dim, (unsigned)ncells);
   switch (g.nx) {
 #define CASE(N)                                                                                \
   case N: {                                                                                    \
     using S = SlabCfg<T, N, N>;                                                                \
-    hipLaunchKernelGGL((k_slab_rhs<T, N, N>), grid, dim3(S::NT), S::LDS_BYTES, s,               \
-                       reinterpret_cast<cplx<T>*>(spec), u, a, H, ctl, g.ntot, g.nspec,        \
-                       ct + tb.off.tw_x, ct + tb.off.tw_y, ct + tb.off.rtw);                   \
+    hipLaunchKernelGGL((k_slab_rhs<T, N, N>), grid, dim3(S::NT), S::LDS_BYTES, s, one, many,    \
+                       g.ntot, g.nspec, ct + tb.off.tw_x, ct + tb.off.tw_y, ct + tb.off.rtw);  \
     return hipGetLastError();                                                                  \
   }
     ACM_SLAB_LENGTHS(CASE)
@@ -323,11 +329,12 @@ hipError_t launch_slab_rhs(const Geom& g, const DevTables<T>& tb, void* spec, co
 #define INST(T)                                                                                \
   template bool slab_supported<T>(const Geom&);                                                \
   template int slab_local_blocks<T>(const Geom&);                                              \
-  template hipError_t launch_slab_local<T>(const Geom&, const DevTables<T>&, const void*, T*,  \
-                                           T*, const uint8_t*, double*, int, StokesCtl*,       \
-                                           double*, hipStream_t);                              \
-  template hipError_t launch_slab_rhs<T>(const Geom&, const DevTables<T>&, void*, const T*,    \
-                                         const T*, const uint8_t*, StokesCtl*, hipStream_t);
+  template hipError_t launch_slab_local<T>(const Geom&, const DevTables<T>&,                   \
+                                           const StokesCellArgs&, const StokesCellArgs*, int,   \
+                                           int, hipStream_t);                                  \
+  template hipError_t launch_slab_rhs<T>(const Geom&, const DevTables<T>&,                     \
+                                         const StokesCellArgs&, const StokesCellArgs*, int,     \
+                                         hipStream_t);
 INST(float)
 INST(double)
 #undef INST

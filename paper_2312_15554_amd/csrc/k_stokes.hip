@@ -32,12 +32,17 @@ struct GreenGeom {
 
 template <typename T, int L, int NC>
 __global__ __launch_bounds__((ColCfg<T, L, NC>::NT)) void k_stokes_green(
-    cplx<T>* __restrict__ spec, cplx<T>* __restrict__ qhat, cplx<T>* __restrict__ dhat,
-    double* __restrict__ partials, const StokesCtl* __restrict__ ctl, GreenGeom gg,
+    StokesCellArgs one, const StokesCellArgs* __restrict__ many, GreenGeom gg,
     const cplx<T>* __restrict__ tw, const T* __restrict__ sx, const T* __restrict__ lx,
     const T* __restrict__ sy, const T* __restrict__ ly, const T* __restrict__ sz,
     const T* __restrict__ lz) {
   using C = ColCfg<T, L, NC>;
+  const StokesCellArgs ca = many ? many[blockIdx.z] : one;
+  cplx<T>* __restrict__ spec = reinterpret_cast<cplx<T>*>(ca.spec);
+  cplx<T>* __restrict__ qhat = reinterpret_cast<cplx<T>*>(ca.qhat);
+  cplx<T>* __restrict__ dhat = reinterpret_cast<cplx<T>*>(ca.dhat);
+  double* __restrict__ partials = ca.part;
+  const StokesCtl* __restrict__ ctl = ca.ctl;
   constexpr int PS = L * C::TX;  // LDS pencil-set stride per field
   extern __shared__ __align__(16) char smem_raw[];
   __shared__ double red[3 * 16];
@@ -149,11 +154,18 @@ __global__ __launch_bounds__((ColCfg<T, L, NC>::NT)) void k_stokes_green(
 
 template <typename T, int M>
 __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_stokes_local(
-    const cplx<T>* __restrict__ spec, T* __restrict__ u, T* __restrict__ a,
-    const uint8_t* __restrict__ H, double* __restrict__ lpart, const double* __restrict__ gpart,
-    int ngreen, StokesCtl* ctl, double* hist, int nrows, int64_t ntot, int64_t nspec,
-    const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ rtw) {
+    StokesCellArgs one, const StokesCellArgs* __restrict__ many, int ngreen, int nrows,
+    int64_t ntot, int64_t nspec, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ rtw) {
   using C = RowCfg<T, M>;
+  const StokesCellArgs ca = many ? many[blockIdx.z] : one;
+  const cplx<T>* __restrict__ spec = reinterpret_cast<const cplx<T>*>(ca.spec);
+  T* __restrict__ u = reinterpret_cast<T*>(ca.u);
+  T* __restrict__ a = reinterpret_cast<T*>(ca.a);
+  const uint8_t* __restrict__ H = ca.H;
+  const double* __restrict__ gpart = ca.part;
+  double* __restrict__ lpart = ca.part + 3 * (int64_t)ngreen;
+  StokesCtl* ctl = ca.ctl;
+  double* hist = ca.hist;
   constexpr int NX = 2 * M;
   extern __shared__ __align__(16) char smem_raw[];
   __shared__ double red[7 * 16];
@@ -216,10 +228,15 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_stokes_local(
 
 template <typename T, int M>
 __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_stokes_rhs(
-    cplx<T>* __restrict__ spec, const T* __restrict__ u, const T* __restrict__ a,
-    const uint8_t* __restrict__ H, const StokesCtl* __restrict__ ctl, int nrows, int64_t ntot,
+    StokesCellArgs one, const StokesCellArgs* __restrict__ many, int nrows, int64_t ntot,
     int64_t nspec, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ rtw) {
   using C = RowCfg<T, M>;
+  const StokesCellArgs ca = many ? many[blockIdx.z] : one;
+  cplx<T>* __restrict__ spec = reinterpret_cast<cplx<T>*>(ca.spec);
+  const T* __restrict__ u = reinterpret_cast<const T*>(ca.u);
+  const T* __restrict__ a = reinterpret_cast<const T*>(ca.a);
+  const uint8_t* __restrict__ H = ca.H;
+  const StokesCtl* __restrict__ ctl = ca.ctl;
   constexpr int NX = 2 * M;
   extern __shared__ __align__(16) char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -280,34 +297,28 @@ int stokes_local_blocks(const Geom& g, int prec_bytes) {
 }
 
 template <typename T>
-hipError_t launch_stokes_green(const Geom& g, const DevTables<T>& tb, void* spec, void* qhat,
-                               void* dhat, double* partials, StokesCtl* ctl, int* nblocks,
-                               hipStream_t s) {
+hipError_t launch_stokes_green(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
+                               const StokesCellArgs* many, int ncells, hipStream_t s) {
   const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
   const T* rt = tb.rtab;
   GreenGeom gg{g.dim, g.nx, g.xh, (int)g.plane, g.nspec, g.ntot};
   const cplx<T>* tw = ct + (g.dim == 3 ? tb.off.tw_z : tb.off.tw_y);
   const T* szp = rt + tb.off.sz;
   const T* lzp = rt + tb.off.lz;
-  auto* sp = reinterpret_cast<cplx<T>*>(spec);
-  auto* qp = reinterpret_cast<cplx<T>*>(qhat);
-  auto* dp = reinterpret_cast<cplx<T>*>(dhat);
   switch (g.last_n) {
 #define CASE(LL)                                                                              \
   case LL: {                                                                                  \
     if (g.dim == 3) {                                                                         \
       using C = ColCfg<T, LL, 3>;                                                             \
       const int nb = (int)((g.plane + C::TX - 1) / C::TX);                                    \
-      if (nblocks) *nblocks = nb;                                                             \
-      hipLaunchKernelGGL((k_stokes_green<T, LL, 3>), dim3(nb), dim3(C::NT), C::LDS_BYTES, s,   \
-                         sp, qp, dp, partials, ctl, gg, tw, rt + tb.off.sx, rt + tb.off.lx,     \
+      hipLaunchKernelGGL((k_stokes_green<T, LL, 3>), dim3(nb, 1, ncells), dim3(C::NT),         \
+                         C::LDS_BYTES, s, one, many, gg, tw, rt + tb.off.sx, rt + tb.off.lx,   \
                          rt + tb.off.sy, rt + tb.off.ly, szp, lzp);                           \
     } else {                                                                                  \
       using C = ColCfg<T, LL, 2>;                                                             \
       const int nb = (int)((g.plane + C::TX - 1) / C::TX);                                    \
-      if (nblocks) *nblocks = nb;                                                             \
-      hipLaunchKernelGGL((k_stokes_green<T, LL, 2>), dim3(nb), dim3(C::NT), C::LDS_BYTES, s,   \
-                         sp, qp, dp, partials, ctl, gg, tw, rt + tb.off.sx, rt + tb.off.lx,     \
+      hipLaunchKernelGGL((k_stokes_green<T, LL, 2>), dim3(nb, 1, ncells), dim3(C::NT),         \
+                         C::LDS_BYTES, s, one, many, gg, tw, rt + tb.off.sx, rt + tb.off.lx,   \
                          rt + tb.off.sy, rt + tb.off.ly, szp, lzp);                           \
     }                                                                                         \
     return hipGetLastError();                                                                 \
@@ -320,22 +331,18 @@ hipError_t launch_stokes_green(const Geom& g, const DevTables<T>& tb, void* spec
 }
 
 template <typename T>
-hipError_t launch_stokes_local(const Geom& g, const DevTables<T>& tb, const void* spec, T* u,
-                               T* a, const uint8_t* H, double* partials, int green_blocks,
-                               StokesCtl* ctl, double* hist, int* nblocks, hipStream_t s) {
+hipError_t launch_stokes_local(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
+                               const StokesCellArgs* many, int ncells, int green_blocks,
+                               hipStream_t s) {
   const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
-  const double* gpart = partials;
-  double* lpart = partials + 3 * (int64_t)green_blocks;
   switch (g.nx / 2) {
 #define CASE(M)                                                                               \
   case M: {                                                                                   \
     using C = RowCfg<T, M>;                                                                   \
-    dim3 grid((unsigned)((g.nrows + C::RB - 1) / C::RB), (unsigned)g.dim);                    \
-    if (nblocks) *nblocks = (int)(grid.x * grid.y);                                           \
-    hipLaunchKernelGGL((k_stokes_local<T, M>), grid, dim3(C::NT), C::LDS_BYTES, s,             \
-                       reinterpret_cast<const cplx<T>*>(spec), u, a, H, lpart, gpart,         \
-                       green_blocks, ctl, hist, (int)g.nrows, g.ntot, g.nspec,                \
-                       ct + tb.off.tw_x, ct + tb.off.rtw);                                    \
+    dim3 grid((unsigned)((g.nrows + C::RB - 1) / C::RB), (unsigned)g.dim, (unsigned)ncells);  \
+    hipLaunchKernelGGL((k_stokes_local<T, M>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many,  \
+                       green_blocks, (int)g.nrows, g.ntot, g.nspec, ct + tb.off.tw_x,         \
+                       ct + tb.off.rtw);                                                      \
     return hipGetLastError();                                                                 \
   }
     ACM_ROW_LENGTHS(CASE)
@@ -346,17 +353,16 @@ hipError_t launch_stokes_local(const Geom& g, const DevTables<T>& tb, const void
 }
 
 template <typename T>
-hipError_t launch_stokes_rhs(const Geom& g, const DevTables<T>& tb, void* spec, const T* u,
-                             const T* a, const uint8_t* H, StokesCtl* ctl, hipStream_t s) {
+hipError_t launch_stokes_rhs(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
+                             const StokesCellArgs* many, int ncells, hipStream_t s) {
   const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
   switch (g.nx / 2) {
 #define CASE(M)                                                                               \
   case M: {                                                                                   \
     using C = RowCfg<T, M>;                                                                   \
-    dim3 grid((unsigned)((g.nrows + C::RB - 1) / C::RB), (unsigned)g.dim);                    \
-    hipLaunchKernelGGL((k_stokes_rhs<T, M>), grid, dim3(C::NT), C::LDS_BYTES, s,               \
-                       reinterpret_cast<cplx<T>*>(spec), u, a, H, ctl, (int)g.nrows, g.ntot,  \
-                       g.nspec, ct + tb.off.tw_x, ct + tb.off.rtw);                           \
+    dim3 grid((unsigned)((g.nrows + C::RB - 1) / C::RB), (unsigned)g.dim, (unsigned)ncells);  \
+    hipLaunchKernelGGL((k_stokes_rhs<T, M>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many,    \
+                       (int)g.nrows, g.ntot, g.nspec, ct + tb.off.tw_x, ct + tb.off.rtw);     \
     return hipGetLastError();                                                                 \
   }
     ACM_ROW_LENGTHS(CASE)
@@ -367,13 +373,15 @@ hipError_t launch_stokes_rhs(const Geom& g, const DevTables<T>& tb, void* spec, 
 }
 
 #define INST(T)                                                                                \
-  template hipError_t launch_stokes_green<T>(const Geom&, const DevTables<T>&, void*, void*,   \
-                                             void*, double*, StokesCtl*, int*, hipStream_t);   \
-  template hipError_t launch_stokes_local<T>(const Geom&, const DevTables<T>&, const void*, T*, \
-                                             T*, const uint8_t*, double*, int, StokesCtl*,     \
-                                             double*, int*, hipStream_t);                      \
-  template hipError_t launch_stokes_rhs<T>(const Geom&, const DevTables<T>&, void*, const T*,  \
-                                           const T*, const uint8_t*, StokesCtl*, hipStream_t);
+  template hipError_t launch_stokes_green<T>(const Geom&, const DevTables<T>&,                 \
+                                             const StokesCellArgs&, const StokesCellArgs*, int, \
+                                             hipStream_t);                                     \
+  template hipError_t launch_stokes_local<T>(const Geom&, const DevTables<T>&,                 \
+                                             const StokesCellArgs&, const StokesCellArgs*, int, \
+                                             int, hipStream_t);                                \
+  template hipError_t launch_stokes_rhs<T>(const Geom&, const DevTables<T>&,                   \
+                                           const StokesCellArgs&, const StokesCellArgs*, int,   \
+                                           hipStream_t);
 INST(float)
 INST(double)
 #undef INST

@@ -256,143 +256,261 @@ static hipError_t join_from(hipStream_t caller, hipStream_t ws) {
 }
 
 // ------------------------------------------------------------------ Stokes
+// One Stokes cell of a (possibly batched) call.
+struct StokesCellIn {
+  const uint8_t* H;
+  double g[3];
+  void* u;
+  void* q;
+};
+
+// Extra default-priority streams used as graph branches (one per size class).
+static std::vector<hipStream_t> branch_streams(int dev, int n) {
+  static std::mutex mu;
+  static std::map<int, std::vector<hipStream_t>> pool;
+  std::lock_guard<std::mutex> lk(mu);
+  auto& v = pool[dev];
+  while ((int)v.size() < n) {
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) break;
+    v.push_back(st);
+  }
+  return std::vector<hipStream_t>(v.begin(), v.begin() + std::min<int>(n, (int)v.size()));
+}
+
+// Cells sharing one plan (same grid and precision) are launched together.
 template <typename T>
-static acm_status stokes_impl(CellPlan* pl, const uint8_t* H, const double* gp, double nu,
-                              const acm_penalty& pen, const acm_opts& o, void* u, void* q,
-                              acm_stats* st, double* history, hipStream_t caller) {
-  const Geom& g = pl->g;
+struct StokesGroup {
+  CellPlan* pl = nullptr;
+  std::vector<int> cells;  // indices into the call's cell list
+  bool slab = false;
+  int ngreen = 0, nlocal = 0;
+  size_t spec_b = 0, one_b = 0, a_b = 0, part_b = 0, cell_b = 0;
+  DevBuf ws;
+  DevBuf dargs_buf, dcols_buf;
+  std::vector<StokesCellArgs> hargs;
+  std::vector<ColCellArgs> hcols;
+  const StokesCellArgs* dargs() const { return (const StokesCellArgs*)dargs_buf.p; }
+  const ColCellArgs* dcols() const { return (const ColCellArgs*)dcols_buf.p; }
+};
+
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <typename T>
+static hipError_t enqueue_iteration(StokesGroup<T>& G, hipStream_t s, Profiler* prof) {
+  const Geom& g = G.pl->g;
+  DevTables<T> tb = tables_of<T>(G.pl);
+  const int n = (int)G.cells.size();
+  const StokesCellArgs& one = G.hargs[0];
+  const StokesCellArgs* many = n > 1 ? G.dargs() : nullptr;
   const int d = g.dim;
-  DevTables<T> tb = tables_of<T>(pl);
-  hipStream_t s = work_stream(pl->device);
+  hipError_t e;
+  hipEvent_t ev0 = nullptr;
+  auto cols = [&](int sign, int kind) -> hipError_t {
+    prof->begin(kind, &ev0);
+    hipError_t r = n > 1 ? launch_cols_batched<T>(g, tb, 1, sign, d, G.dcols(), n, s)
+                         : launch_cols<T>(g, tb, 1, sign, d, one.spec, s, &one.ctl->done);
+    prof->end(kind, ev0);
+    return r;
+  };
+  prof->begin(KK_GREEN, &ev0);
+  e = launch_stokes_green<T>(g, tb, one, many, n, s);
+  if (e != hipSuccess) return e;
+  prof->end(KK_GREEN, ev0);
+  if (G.slab) {
+    prof->begin(KK_LOCAL, &ev0);
+    e = launch_slab_local<T>(g, tb, one, many, n, G.ngreen, s);
+    if (e != hipSuccess) return e;
+    prof->end(KK_LOCAL, ev0);
+    prof->begin(KK_RHS, &ev0);
+    e = launch_slab_rhs<T>(g, tb, one, many, n, s);
+    if (e != hipSuccess) return e;
+    prof->end(KK_RHS, ev0);
+    return hipSuccess;
+  }
+  if (d == 3 && (e = cols(+1, KK_YINV)) != hipSuccess) return e;
+  prof->begin(KK_LOCAL, &ev0);
+  e = launch_stokes_local<T>(g, tb, one, many, n, G.ngreen, s);
+  if (e != hipSuccess) return e;
+  prof->end(KK_LOCAL, ev0);
+  prof->begin(KK_RHS, &ev0);
+  e = launch_stokes_rhs<T>(g, tb, one, many, n, s);
+  if (e != hipSuccess) return e;
+  prof->end(KK_RHS, ev0);
+  if (d == 3 && (e = cols(-1, KK_YFWD)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+template <typename T>
+static acm_status stokes_run(const std::vector<CellPlan*>& plans,
+                             const std::vector<StokesCellIn>& cells, double nu,
+                             const acm_penalty& pen, const acm_opts& o, acm_stats* stats,
+                             double* history, hipStream_t caller) {
+  const int ncell = (int)cells.size();
+  const int dev = plans[0]->device;
+  hipStream_t s = work_stream(dev);
   if (!s) return fail(ACM_E_HIP, "cannot create work stream");
   HIP_TRY(join_from(caller, s));
 
-  const size_t cbytes = sizeof(T) * 2;
-  const size_t spec_b = cbytes * (size_t)g.nspec * d;
-  const size_t one_b = cbytes * (size_t)g.nspec;
-  const size_t a_b = sizeof(T) * (size_t)g.ntot * d;
-  const int ngreen = pl->green_blocks;
-  const bool aligned = ((uintptr_t)u % 32 == 0) && ((uintptr_t)H % 16 == 0);
-  bool use_slab = false;
-  if (o.pass_mode == 2) {
-    if (!(slab_supported<T>(g) && aligned))
-      return fail(ACM_E_INVALID, "fused xy passes need a 3D cell with nx == ny <= 128 and aligned u, H");
-    use_slab = true;
-  } else if (o.pass_mode == 0) {
-    use_slab = slab_supported<T>(g) && aligned;
+  // ---- group cells by plan
+  std::vector<std::unique_ptr<StokesGroup<T>>> groups;
+  for (int i = 0; i < ncell; ++i) {
+    StokesGroup<T>* G = nullptr;
+    for (auto& gp : groups)
+      if (gp->pl == plans[i]) G = gp.get();
+    if (!G) {
+      groups.emplace_back(new StokesGroup<T>());
+      G = groups.back().get();
+      G->pl = plans[i];
+    }
+    G->cells.push_back(i);
   }
-  const int nlocal = std::max(pl->local_blocks, slab_local_blocks<T>(g));
-  const size_t part_b = sizeof(double) * (size_t)(3 * ngreen + 4 * nlocal);
-  const int hist_cap = o.history_cap > 0 ? o.history_cap : 0;
-  const size_t hist_b = sizeof(double) * kHistDoubles * (size_t)std::max(hist_cap, 1);
-  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  const size_t total = al(spec_b) + 2 * al(one_b) + al(a_b) + al(part_b) + al(sizeof(StokesCtl)) +
-                       al(hist_b);
-  DevBuf ws;
-  HIP_TRY(hipMalloc(&ws.p, total));
-  char* cur = (char*)ws.p;
-  auto take = [&](size_t b) {
-    void* r = cur;
-    cur += al(b);
-    return r;
-  };
-  void* spec = take(spec_b);
-  void* qhat = take(one_b);
-  void* dhat = take(one_b);
-  T* a = (T*)take(a_b);
-  double* part = (double*)take(part_b);
-  StokesCtl* dctl = (StokesCtl*)take(sizeof(StokesCtl));
-  double* dhist = hist_cap > 0 ? (double*)take(hist_b) : nullptr;
-  T* uu = (T*)u;
+  const int hist_cap = (ncell == 1 && o.history_cap > 0) ? o.history_cap : 0;
+  DevBuf ctl_buf, hist_buf;
+  HIP_TRY(hipMalloc(&ctl_buf.p, sizeof(StokesCtl) * ncell));
+  StokesCtl* dctl = (StokesCtl*)ctl_buf.p;
+  if (hist_cap > 0) HIP_TRY(hipMalloc(&hist_buf.p, sizeof(double) * kHistDoubles * hist_cap));
 
-  // ---- initial state X^0 (zero start): u = ut = q = a = lambda = 0
-  if (o.warm_start) return fail(ACM_E_INVALID, "warm_start is not available in this build");
-  HIP_TRY(hipMemsetAsync(spec, 0, spec_b, s));
-  HIP_TRY(hipMemsetAsync(qhat, 0, one_b, s));
-  HIP_TRY(hipMemsetAsync(dhat, 0, one_b, s));
-  HIP_TRY(hipMemsetAsync(a, 0, a_b, s));
-  HIP_TRY(hipMemsetAsync(uu, 0, a_b, s));
-  HIP_TRY(hipMemsetAsync(part, 0, part_b, s));
-
-  StokesCtl c{};
-  const double p0 = nu * (double)std::max(g.nx, std::max(g.ny, g.nz));
-  c.psi[0] = pen.alpha > 0 ? pen.alpha : p0;
-  c.psi[1] = pen.beta > 0 ? pen.beta : p0;
-  c.psi[2] = pen.b > 0 ? pen.b : p0;
-  for (int k = 0; k < 3; ++k) {
-    c.phi[k] = pen.phi[k];
-    c.tau[k] = pen.tau[k];
-    c.psi_min[k] = pen.psi_min[k] > 0 ? pen.psi_min[k] : 1e-3 * c.psi[k];
-    c.g[k] = k < d ? gp[k] : 0.0;
+  for (auto& Gp : groups) {
+    StokesGroup<T>& G = *Gp;
+    const Geom& g = G.pl->g;
+    const int d = g.dim;
+    const size_t cb = sizeof(T) * 2;
+    G.spec_b = cb * (size_t)g.nspec * d;
+    G.one_b = cb * (size_t)g.nspec;
+    G.a_b = sizeof(T) * (size_t)g.ntot * d;
+    G.ngreen = G.pl->green_blocks;
+    bool aligned = true;
+    for (int i : G.cells)
+      aligned = aligned && ((uintptr_t)cells[i].u % 32 == 0) && ((uintptr_t)cells[i].H % 16 == 0);
+    if (o.pass_mode == 2) {
+      if (!(slab_supported<T>(g) && aligned))
+        return fail(ACM_E_INVALID,
+                    "fused xy passes need a 3D cell with nx == ny <= 128 and aligned u, H");
+      G.slab = true;
+    } else if (o.pass_mode == 0) {
+      G.slab = slab_supported<T>(g) && aligned;
+    }
+    G.nlocal = std::max(G.pl->local_blocks, slab_local_blocks<T>(g));
+    G.part_b = sizeof(double) * (size_t)(3 * G.ngreen + 4 * G.nlocal);
+    G.cell_b = al256(G.spec_b) + 2 * al256(G.one_b) + al256(G.a_b) + al256(G.part_b);
+    HIP_TRY(hipMalloc(&G.ws.p, G.cell_b * G.cells.size()));
+    for (size_t k = 0; k < G.cells.size(); ++k) {
+      const int i = G.cells[k];
+      char* base = (char*)G.ws.p + k * G.cell_b;
+      StokesCellArgs A;
+      A.spec = base;
+      A.qhat = base + al256(G.spec_b);
+      A.dhat = (char*)A.qhat + al256(G.one_b);
+      A.a = (char*)A.dhat + al256(G.one_b);
+      A.part = (double*)((char*)A.a + al256(G.a_b));
+      A.u = cells[i].u;
+      A.H = cells[i].H;
+      A.ctl = dctl + i;
+      A.hist = hist_cap > 0 ? (double*)hist_buf.p : nullptr;
+      G.hargs.push_back(A);
+      G.hcols.push_back(ColCellArgs{A.spec, &A.ctl->done});
+    }
+    if (G.cells.size() > 1) {
+      HIP_TRY(hipMalloc(&G.dargs_buf.p, sizeof(StokesCellArgs) * G.cells.size()));
+      HIP_TRY(hipMalloc(&G.dcols_buf.p, sizeof(ColCellArgs) * G.cells.size()));
+      HIP_TRY(hipMemcpyAsync(G.dargs_buf.p, G.hargs.data(), sizeof(StokesCellArgs) * G.cells.size(),
+                             hipMemcpyHostToDevice, s));
+      HIP_TRY(hipMemcpyAsync(G.dcols_buf.p, G.hcols.data(), sizeof(ColCellArgs) * G.cells.size(),
+                             hipMemcpyHostToDevice, s));
+    }
+    // zero start: spectra, q-hat, div-hat, a and partials of every cell
+    if (!o.warm_start) {
+      HIP_TRY(hipMemsetAsync(G.ws.p, 0, G.cell_b * G.cells.size(), s));
+      for (int i : G.cells) HIP_TRY(hipMemsetAsync(cells[i].u, 0, G.a_b, s));
+    } else {
+      for (const auto& A : G.hargs) HIP_TRY(hipMemsetAsync(A.part, 0, G.part_b, s));
+    }
   }
-  c.c_prev = 0.0;
-  c.eps = o.eps;
-  c.sqrt_n[0] = sqrt((double)d * (double)g.ntot);
-  c.sqrt_n[1] = sqrt((double)g.ntot);
-  c.sqrt_n[2] = c.sqrt_n[0];
-  c.nu = nu;
-  c.iter = 0;
-  c.max_iter = o.max_iter;
-  c.done = 0;
-  c.status = 1;
-  c.adaptive = pen.adaptive;
-  c.counter = 0;
-  c.hist_cap = hist_cap;
-  HIP_TRY(hipMemcpyAsync(dctl, &c, sizeof(c), hipMemcpyHostToDevice, s));
+
+  // ---- control blocks
+  std::vector<StokesCtl> hc(ncell);
+  for (int i = 0; i < ncell; ++i) {
+    const Geom& g = plans[i]->g;
+    const int d = g.dim;
+    StokesCtl& c = hc[i];
+    memset(&c, 0, sizeof(c));
+    const double p0 = nu * (double)std::max(g.nx, std::max(g.ny, g.nz));
+    c.psi[0] = pen.alpha > 0 ? pen.alpha : p0;
+    c.psi[1] = pen.beta > 0 ? pen.beta : p0;
+    c.psi[2] = pen.b > 0 ? pen.b : p0;
+    for (int k = 0; k < 3; ++k) {
+      c.phi[k] = pen.phi[k];
+      c.tau[k] = pen.tau[k];
+      c.psi_min[k] = pen.psi_min[k] > 0 ? pen.psi_min[k] : 1e-3 * c.psi[k];
+      c.g[k] = k < d ? cells[i].g[k] : 0.0;
+    }
+    c.c_prev = 0.0;
+    c.eps = o.eps;
+    c.sqrt_n[0] = sqrt((double)d * (double)g.ntot);
+    c.sqrt_n[1] = sqrt((double)g.ntot);
+    c.sqrt_n[2] = c.sqrt_n[0];
+    c.nu = nu;
+    c.max_iter = o.max_iter;
+    c.status = 1;
+    c.adaptive = pen.adaptive;
+    c.hist_cap = hist_cap;
+  }
+  HIP_TRY(hipMemcpyAsync(dctl, hc.data(), sizeof(StokesCtl) * ncell, hipMemcpyHostToDevice, s));
+
+  // ---- warm start: u0 = (1-H) u_in, q0 = q_in, a0 = lambda0 = H (g - grad q0 +
+  // nu Delta u0); q-hat0 = FFT(q0), div-hat0 = FFT(div u0); the Step-1
+  // right-hand side from the rhs pass (c_prev = 0: u0 vanishes in the solid).
+  if (o.warm_start) {
+    for (auto& Gp : groups) {
+      StokesGroup<T>& G = *Gp;
+      const Geom& g = G.pl->g;
+      DevTables<T> tb = tables_of<T>(G.pl);
+      for (size_t k = 0; k < G.cells.size(); ++k) {
+        const StokesCellArgs& A = G.hargs[k];
+        const StokesCellIn& C = cells[G.cells[k]];
+        T* divbuf = (T*)A.spec;  // scratch: the spectra are rebuilt below
+        hipError_t e = launch_warm_init<T>(g, (const T*)A.u, (const T*)C.q, A.H, (T*)A.a, divbuf,
+                                           nu, hc[G.cells[k]].g, s);
+        if (e == hipSuccess) e = launch_rows_r2c<T>(g, tb, 1, divbuf, A.dhat, s);
+        if (e == hipSuccess) e = launch_cols<T>(g, tb, 1, -1, 1, A.dhat, s);
+        if (e == hipSuccess && g.dim == 3) e = launch_cols<T>(g, tb, 2, -1, 1, A.dhat, s);
+        if (e == hipSuccess) {
+          if (C.q) {
+            e = launch_rows_r2c<T>(g, tb, 1, (const T*)C.q, A.qhat, s);
+            if (e == hipSuccess) e = launch_cols<T>(g, tb, 1, -1, 1, A.qhat, s);
+            if (e == hipSuccess && g.dim == 3) e = launch_cols<T>(g, tb, 2, -1, 1, A.qhat, s);
+          } else {
+            e = hipMemsetAsync(A.qhat, 0, G.one_b, s);
+          }
+        }
+        if (e == hipSuccess) {
+          if (G.slab) {
+            e = launch_slab_rhs<T>(g, tb, A, nullptr, 1, s);
+          } else {
+            e = launch_stokes_rhs<T>(g, tb, A, nullptr, 1, s);
+            if (e == hipSuccess && g.dim == 3) e = launch_cols<T>(g, tb, 1, -1, g.dim, A.spec, s);
+          }
+        }
+        if (e != hipSuccess) return fail(ACM_E_HIP, std::string("warm start: ") + hipGetErrorString(e));
+      }
+    }
+  }
 
   Profiler prof;
   prof.on = o.profile != 0;
   prof.s = s;
-  auto one_iter = [&]() -> hipError_t {
-    hipError_t e;
-    hipEvent_t ev0 = nullptr;
-    prof.begin(KK_GREEN, &ev0);
-    e = launch_stokes_green<T>(g, tb, spec, qhat, dhat, part, dctl, nullptr, s);
-    if (e != hipSuccess) return e;
-    prof.end(KK_GREEN, ev0);
-    if (use_slab) {
-      prof.begin(KK_LOCAL, &ev0);
-      e = launch_slab_local<T>(g, tb, spec, uu, a, H, part, ngreen, dctl, dhist, s);
-      if (e != hipSuccess) return e;
-      prof.end(KK_LOCAL, ev0);
-      prof.begin(KK_RHS, &ev0);
-      e = launch_slab_rhs<T>(g, tb, spec, uu, a, H, dctl, s);
-      if (e != hipSuccess) return e;
-      prof.end(KK_RHS, ev0);
-      return hipSuccess;
-    }
-    if (d == 3) {
-      prof.begin(KK_YINV, &ev0);
-      e = launch_cols<T>(g, tb, 1, +1, d, spec, s, &dctl->done);
-      if (e != hipSuccess) return e;
-      prof.end(KK_YINV, ev0);
-    }
-    prof.begin(KK_LOCAL, &ev0);
-    e = launch_stokes_local<T>(g, tb, spec, uu, a, H, part, ngreen, dctl, dhist, nullptr, s);
-    if (e != hipSuccess) return e;
-    prof.end(KK_LOCAL, ev0);
-    prof.begin(KK_RHS, &ev0);
-    e = launch_stokes_rhs<T>(g, tb, spec, uu, a, H, dctl, s);
-    if (e != hipSuccess) return e;
-    prof.end(KK_RHS, ev0);
-    if (d == 3) {
-      prof.begin(KK_YFWD, &ev0);
-      e = launch_cols<T>(g, tb, 1, -1, d, spec, s, &dctl->done);
-      if (e != hipSuccess) return e;
-      prof.end(KK_YFWD, ev0);
-    }
-    return hipSuccess;
-  };
 
   int K = o.check_every;
   if (K <= 0) {
-    const double work = (double)g.ntot * d;
+    double work = 0.0;
+    for (int i = 0; i < ncell; ++i) work += (double)plans[i]->g.ntot * plans[i]->g.dim;
     K = (int)std::min(200.0, std::max(8.0, 3.0e8 / work));
   }
   if (o.max_iter < K) K = (int)std::max<int64_t>(1, o.max_iter);
 
   StokesCtl* hctl = nullptr;
-  HIP_TRY(hipHostMalloc((void**)&hctl, sizeof(StokesCtl), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc((void**)&hctl, sizeof(StokesCtl) * ncell, hipHostMallocDefault));
   struct HostFree {
     void* p;
     ~HostFree() {
@@ -402,11 +520,39 @@ static acm_status stokes_impl(CellPlan* pl, const uint8_t* H, const double* gp, 
 
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
+  std::vector<hipEvent_t> evs;
+  struct EvFree {
+    std::vector<hipEvent_t>* v;
+    ~EvFree() {
+      for (auto e : *v) (void)hipEventDestroy(e);
+    }
+  } evf{&evs};
   const bool use_graph = o.use_graph && !prof.on;
   if (use_graph) {
+    std::vector<hipStream_t> br;
+    if (groups.size() > 1) {
+      br = branch_streams(dev, (int)groups.size());
+      if (br.size() < groups.size()) return fail(ACM_E_HIP, "cannot create branch streams");
+      for (size_t i = 0; i < 2 * groups.size(); ++i) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        evs.push_back(e);
+      }
+    }
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int k = 0; k < K && e == hipSuccess; ++k) e = one_iter();
+    if (groups.size() == 1) {
+      for (int k = 0; k < K && e == hipSuccess; ++k) e = enqueue_iteration<T>(*groups[0], s, &prof);
+    } else {
+      for (size_t gi = 0; gi < groups.size() && e == hipSuccess; ++gi) {
+        e = hipEventRecord(evs[2 * gi], s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(br[gi], evs[2 * gi], 0);
+        for (int k = 0; k < K && e == hipSuccess; ++k)
+          e = enqueue_iteration<T>(*groups[gi], br[gi], &prof);
+        if (e == hipSuccess) e = hipEventRecord(evs[2 * gi + 1], br[gi]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, evs[2 * gi + 1], 0);
+      }
+    }
     hipError_t e2 = hipStreamEndCapture(s, &graph);
     if (e != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -425,72 +571,124 @@ static acm_status stokes_impl(CellPlan* pl, const uint8_t* H, const double* gp, 
   } gf{graph, exec};
 
   auto t0 = std::chrono::steady_clock::now();
+  std::vector<double> t_done(ncell, -1.0);
   int64_t launched = 0;
   for (;;) {
     if (use_graph) {
       HIP_TRY(hipGraphLaunch(exec, s));
     } else {
-      for (int k = 0; k < K; ++k) {
-        hipError_t e = one_iter();
-        if (e != hipSuccess) return fail(ACM_E_HIP, std::string("launch: ") + hipGetErrorString(e));
-      }
+      for (int k = 0; k < K; ++k)
+        for (auto& Gp : groups) {
+          hipError_t e = enqueue_iteration<T>(*Gp, s, &prof);
+          if (e != hipSuccess) return fail(ACM_E_HIP, std::string("launch: ") + hipGetErrorString(e));
+        }
     }
     launched += K;
-    HIP_TRY(hipMemcpyAsync(hctl, dctl, sizeof(StokesCtl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hctl, dctl, sizeof(StokesCtl) * ncell, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     prof.collect();
-    if (hctl->done) break;
+    bool all = true;
+    const double now = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int i = 0; i < ncell; ++i) {
+      if (hctl[i].done && t_done[i] < 0) t_done[i] = now;
+      all = all && hctl[i].done;
+    }
+    if (all) break;
     if (launched > o.max_iter + 2LL * K) break;  // safety net: the device caps iterations itself
   }
   auto t1 = std::chrono::steady_clock::now();
 
   // ---- read-out of q: inverse transform of q-hat
-  if (q) {
-    HIP_TRY(hipMemcpyAsync(spec, qhat, one_b, hipMemcpyDeviceToDevice, s));
-    if (d == 3) {
-      hipError_t e = launch_cols<T>(g, tb, 2, +1, 1, spec, s);
-      if (e == hipSuccess) e = launch_cols<T>(g, tb, 1, +1, 1, spec, s);
-      if (e != hipSuccess) return fail(ACM_E_HIP, hipGetErrorString(e));
-    } else {
-      hipError_t e = launch_cols<T>(g, tb, 1, +1, 1, spec, s);
+  for (auto& Gp : groups) {
+    StokesGroup<T>& G = *Gp;
+    const Geom& g = G.pl->g;
+    DevTables<T> tb = tables_of<T>(G.pl);
+    for (size_t k = 0; k < G.cells.size(); ++k) {
+      const StokesCellIn& C = cells[G.cells[k]];
+      if (!C.q) continue;
+      const StokesCellArgs& A = G.hargs[k];
+      HIP_TRY(hipMemcpyAsync(A.spec, A.qhat, G.one_b, hipMemcpyDeviceToDevice, s));
+      hipError_t e = hipSuccess;
+      if (g.dim == 3) e = launch_cols<T>(g, tb, 2, +1, 1, A.spec, s);
+      if (e == hipSuccess) e = launch_cols<T>(g, tb, 1, +1, 1, A.spec, s);
+      if (e == hipSuccess) e = launch_rows_c2r<T>(g, tb, 1, A.spec, (T*)C.q, 1.0 / (double)g.ntot, s);
       if (e != hipSuccess) return fail(ACM_E_HIP, hipGetErrorString(e));
     }
-    hipError_t e = launch_rows_c2r<T>(g, tb, 1, spec, (T*)q, 1.0 / (double)g.ntot, s);
-    if (e != hipSuccess) return fail(ACM_E_HIP, hipGetErrorString(e));
   }
   if (history && hist_cap > 0) {
     std::vector<double> h((size_t)hist_cap * kHistDoubles);
-    HIP_TRY(hipMemcpyAsync(h.data(), dhist, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h.data(), hist_buf.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    const int64_t n = hctl->iter;
+    const int64_t n = hctl[0].iter;
     const int64_t keep = std::min<int64_t>(n, hist_cap);
     for (int64_t i = 0; i < keep; ++i) {
-      const int64_t it = n - keep + i;  // 0-based iteration index
+      const int64_t it = n - keep + i;
       memcpy(history + i * kHistDoubles, h.data() + (it % hist_cap) * kHistDoubles,
              sizeof(double) * kHistDoubles);
     }
   }
   HIP_TRY(hipStreamSynchronize(s));
-  if (st) {
+  const double total_s = std::chrono::duration<double>(t1 - t0).count();
+  int worst = 0;
+  for (int i = 0; i < ncell; ++i) {
+    const StokesCtl& c = hctl[i];
+    if (c.status == -5) worst = -5;
+    else if (c.status != 0 && worst == 0) worst = 1;
+    if (!stats) continue;
+    acm_stats* st = stats + i;
     memset(st, 0, sizeof(*st));
-    st->iters = hctl->iter;
+    st->iters = c.iter;
     for (int k = 0; k < 3; ++k) {
-      st->r_p[k] = hctl->rp[k];
-      st->r_d[k] = hctl->rd[k];
-      st->tol_p[k] = hctl->tp[k];
-      st->tol_d[k] = hctl->td[k];
-      st->psi[k] = hctl->psi[k];
+      st->r_p[k] = c.rp[k];
+      st->r_d[k] = c.rd[k];
+      st->tol_p[k] = c.tp[k];
+      st->tol_d[k] = c.td[k];
+      st->psi[k] = c.psi[k];
     }
-    st->seconds = std::chrono::duration<double>(t1 - t0).count();
-    st->converged = hctl->status == 0;
-    st->status = hctl->status;
-    for (int k = 0; k < KK_COUNT; ++k) {
-      st->kernel_ms[k] = prof.ms[k];
-      st->kernel_calls[k] = prof.calls[k];
-    }
+    st->seconds = ncell == 1 ? total_s : (t_done[i] >= 0 ? t_done[i] : total_s);
+    st->converged = c.status == 0;
+    st->status = c.status;
+    if (i == 0)
+      for (int k = 0; k < KK_COUNT; ++k) {
+        st->kernel_ms[k] = prof.ms[k];
+        st->kernel_calls[k] = prof.calls[k];
+      }
   }
-  if (hctl->status == -5) return fail(ACM_E_DIVERGED, "a residual became non-finite");
-  return hctl->status == 0 ? ACM_OK : ACM_NOT_CONVERGED;
+  if (worst == -5) return fail(ACM_E_DIVERGED, "a residual became non-finite");
+  return worst == 0 ? ACM_OK : ACM_NOT_CONVERGED;
+}
+
+// Argument checks shared by the single and batched Stokes entry points.
+static acm_status check_stokes_cell(const acm_grid* grid, const uint8_t* H, const double* g_p,
+                                    void* u, int precision, hipStream_t cs, CellPlan** pl) {
+  if (!H || !g_p || !u) return fail(ACM_E_INVALID, "H, g_p and u must be non-NULL");
+  acm_status r = get_plan(grid, precision, pl);
+  if (r != ACM_OK) return r;
+  for (int k = 0; k < grid->dim; ++k)
+    if (!isfinite(g_p[k])) return fail(ACM_E_INVALID, "g_p must be finite");
+  // H must contain a solid voxel: with no solid the mean of a grows without
+  // bound under a body force and no steady flow exists.
+  std::vector<uint8_t> hh((size_t)(*pl)->g.ntot);
+  hipError_t e = hipMemcpyAsync(hh.data(), H, hh.size(), hipMemcpyDeviceToHost, cs);
+  if (e == hipSuccess) e = hipStreamSynchronize(cs);
+  if (e != hipSuccess) return fail(ACM_E_HIP, std::string("reading H: ") + hipGetErrorString(e));
+  bool any = false;
+  for (uint8_t v : hh) {
+    if (v > 1) return fail(ACM_E_INVALID, "H must hold 0 or 1");
+    any |= v == 1;
+  }
+  if (!any) return fail(ACM_E_INVALID, "H has no solid voxel: no steady flow under a body force");
+  return ACM_OK;
+}
+
+static acm_status check_penalty_opts(const acm_penalty& P, const acm_opts& O, double nu) {
+  if (!(nu > 0.0) || !isfinite(nu)) return fail(ACM_E_INVALID, "nu must be positive");
+  if (!(O.eps >= 0.0) || O.max_iter < 1) return fail(ACM_E_INVALID, "eps >= 0 and max_iter >= 1 required");
+  if (O.pass_mode < 0 || O.pass_mode > 2) return fail(ACM_E_INVALID, "pass_mode must be 0, 1 or 2");
+  for (int k = 0; k < 3; ++k)
+    if (!(P.phi[k] >= 1.0) || !(P.tau[k] > 0.0))
+      return fail(ACM_E_INVALID, "phi >= 1 and tau > 0 required");
+  return ACM_OK;
 }
 
 // --------------------------------------------------------------- reductions
@@ -832,35 +1030,45 @@ acm_status acm_stokes_solve(const acm_grid* grid, const uint8_t* H, const double
   acm_default_opts(&O);
   if (pen) P = *pen;
   if (opts) O = *opts;
-  if (!H || !g_p || !u) return fail(ACM_E_INVALID, "H, g_p and u must be non-NULL");
-  if (!(nu > 0.0) || !isfinite(nu)) return fail(ACM_E_INVALID, "nu must be positive");
-  if (!(O.eps >= 0.0) || O.max_iter < 1) return fail(ACM_E_INVALID, "eps >= 0 and max_iter >= 1 required");
-  for (int k = 0; k < 3; ++k)
-    if (!(P.phi[k] >= 1.0) || !(P.tau[k] > 0.0))
-      return fail(ACM_E_INVALID, "phi >= 1 and tau > 0 required");
-  CellPlan* pl = nullptr;
-  acm_status r = get_plan(grid, O.precision, &pl);
+  acm_status r = check_penalty_opts(P, O, nu);
   if (r != ACM_OK) return r;
-  for (int k = 0; k < grid->dim; ++k)
-    if (!isfinite(g_p[k])) return fail(ACM_E_INVALID, "g_p must be finite");
-  // H must contain a solid voxel: with no solid the mean of a grows without
-  // bound under a body force and no steady flow exists.
-  {
-    hipStream_t cs = (hipStream_t)stream;
-    std::vector<uint8_t> hh((size_t)pl->g.ntot);
-    hipError_t e = hipMemcpyAsync(hh.data(), H, hh.size(), hipMemcpyDeviceToHost, cs);
-    if (e == hipSuccess) e = hipStreamSynchronize(cs);
-    if (e != hipSuccess) return fail(ACM_E_HIP, std::string("reading H: ") + hipGetErrorString(e));
-    bool any = false;
-    for (uint8_t v : hh) {
-      if (v > 1) return fail(ACM_E_INVALID, "H must hold 0 or 1");
-      any |= v == 1;
-    }
-    if (!any) return fail(ACM_E_INVALID, "H has no solid voxel: no steady flow under a body force");
+  CellPlan* pl = nullptr;
+  r = check_stokes_cell(grid, H, g_p, u, O.precision, (hipStream_t)stream, &pl);
+  if (r != ACM_OK) return r;
+  StokesCellIn c{H, {0, 0, 0}, u, q};
+  for (int k = 0; k < grid->dim; ++k) c.g[k] = g_p[k];
+  std::vector<CellPlan*> plans{pl};
+  std::vector<StokesCellIn> cells{c};
+  if (O.precision == ACM_FP64)
+    return stokes_run<double>(plans, cells, nu, P, O, stats, history, (hipStream_t)stream);
+  return stokes_run<float>(plans, cells, nu, P, O, stats, history, (hipStream_t)stream);
+}
+
+acm_status acm_stokes_solve_batched(int32_t ncell, const acm_grid* grids, const uint8_t* const* H,
+                                    const double* g_p, double nu, const acm_penalty* pen,
+                                    const acm_opts* opts, void* const* u, void* const* q,
+                                    acm_stats* stats, void* stream) {
+  g_err.clear();
+  if (ncell < 1 || !grids || !H || !g_p || !u) return fail(ACM_E_INVALID, "ncell >= 1 and non-NULL arrays required");
+  acm_penalty P;
+  acm_opts O;
+  acm_default_penalty(&P);
+  acm_default_opts(&O);
+  if (pen) P = *pen;
+  if (opts) O = *opts;
+  acm_status r = check_penalty_opts(P, O, nu);
+  if (r != ACM_OK) return r;
+  std::vector<CellPlan*> plans(ncell);
+  std::vector<StokesCellIn> cells(ncell);
+  for (int i = 0; i < ncell; ++i) {
+    r = check_stokes_cell(grids + i, H[i], g_p + 3 * i, u[i], O.precision, (hipStream_t)stream,
+                          &plans[i]);
+    if (r != ACM_OK) return fail(r, "cell " + std::to_string(i) + ": " + g_err);
+    cells[i] = StokesCellIn{H[i], {g_p[3 * i], g_p[3 * i + 1], g_p[3 * i + 2]}, u[i], q ? q[i] : nullptr};
   }
   if (O.precision == ACM_FP64)
-    return stokes_impl<double>(pl, H, g_p, nu, P, O, u, q, stats, history, (hipStream_t)stream);
-  return stokes_impl<float>(pl, H, g_p, nu, P, O, u, q, stats, history, (hipStream_t)stream);
+    return stokes_run<double>(plans, cells, nu, P, O, stats, nullptr, (hipStream_t)stream);
+  return stokes_run<float>(plans, cells, nu, P, O, stats, nullptr, (hipStream_t)stream);
 }
 
 acm_status acm_fft_r2c(const acm_grid* grid, int32_t precision, int32_t nfields, const void* in,

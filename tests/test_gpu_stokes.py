@@ -170,3 +170,27 @@ def test_c1_model_cell_matches_oracle(dtype):
         assert abs(r["stats"]["iters"] - ref["admm_iters"]) < 0.1 * ref["admm_iters"]
         assert abs(k - ref["admm_kxx"]) < 1e-5 * ref["admm_kxx"]
     assert abs(k - ref["kkt_kxx"]) < 5e-5 * ref["kkt_kxx"]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("shape,pass_mode", [((16, 16), 0), ((16, 32, 32), 1), ((16, 32, 32), 2)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_warm_start_iterates_match_oracle(shape, pass_mode, dtype):
+    """Warm start (u0 = (1-H) u_in, q0 = q_in, a0 = lambda0 = H (g - grad q0 +
+    nu Delta u0)) followed by fixed-penalty iterations, against the oracle."""
+    require_gpu()
+    print(f"warm start shape={shape} mode={pass_mode} dtype={dtype}", flush=True)
+    d = len(shape)
+    H = I.random_mask(shape, 41, 0.3)
+    g = (1.0, 0.3, -0.2)[:d]
+    u_in = I.random_field((d,) + shape, 42, 1e-2)
+    q_in = I.random_field(shape, 43, 1e-1)
+    M = 20
+    r = _solve(H, g, dtype=dtype, penalty=dict(alpha=40.0, beta=60.0, b=25.0, adaptive=0),
+               eps=0.0, max_iter=M, warm_start=True, u=dev(u_in, dtype), q=dev(q_in, dtype),
+               pass_mode=pass_mode)
+    o = O.stokes_admm(H, g, alpha=40.0, beta=60.0, b=25.0, adaptive=False, eps=0.0, max_iter=M,
+                      u_init=u_in, q_init=q_in)
+    tol = 1e-11 if dtype == torch.float64 else 3e-5
+    assert np.abs(host(r["u"]) - o["u"]).max() < tol * np.abs(o["u"]).max()
+    assert np.abs(host(r["q"]) - o["q"]).max() < tol * 10 * np.abs(o["q"]).max()
