@@ -200,6 +200,50 @@ acm_status acm_fft_r2c(const acm_grid* grid, int32_t precision, int32_t nfields,
 acm_status acm_fft_c2r(const acm_grid* grid, int32_t precision, int32_t nfields, const void* in,
                        void* out, void* stream);
 
+/*
+ * Fourier-neural-operator warm start for the Stokes ADMM (g = e_x).  The
+ * network (Li et al., ICLR 2021) maps H to (u_x, u_y, u_z, p):
+ *   v0 = Pw H + Pb;  v_{l+1} = act(W_l v_l + b_l + K_l v_l), act = GELU except
+ *   after the last layer; K_l = inverse real FFT of R_l (complex C x C per kept
+ *   mode: kx < m, ky, kz in [0,m) U [n-m,n)) applied to the forward real FFT;
+ *   out = Q2 GELU(Q1 v_L + c1) + c2.
+ * Parameters: one flat array (layout Pw[C] Pb[C] | per layer R[nm][C][C]
+ * complex as (re,im), W[C][C], b[C] | Q1[Cp][C] c1[Cp] Q2[4][Cp] c2[4],
+ * nm = (2m)^2 m); kernels read the BF16 copy, Adam updates the FP32 master
+ * and refreshes the BF16 copy.  Activations and accumulations are FP32.
+ * Grids must be cubic 3D with n in the supported set, channels in
+ * {4, 8, 16, 32}, hidden * channels <= 4096, 2 * modes <= n.
+ * H: uint8 [batch][n^3]; out, dout: float [batch][4][n^3] (device).
+ * The workspace (device, caller-owned) keeps the activations of a training
+ * forward pass for the following backward pass with the same arguments.
+ */
+typedef struct {
+  int32_t channels; /* C */
+  int32_t hidden;   /* Cp, projection width */
+  int32_t modes;    /* m, kept modes per axis */
+  int32_t layers;   /* L, Fourier layers */
+} acm_fno_shape;
+
+int64_t acm_fno_param_count(const acm_fno_shape* shape);  /* floats; -1 if invalid */
+int64_t acm_fno_workspace_bytes(const acm_fno_shape* shape, const acm_grid* grid, int32_t batch,
+                                int32_t train);            /* -1 if invalid */
+acm_status acm_fno_forward(const acm_fno_shape* shape, const acm_grid* grid, int32_t batch,
+                           const uint16_t* params_bf16, const uint8_t* H, float* out,
+                           void* workspace, int64_t workspace_bytes, int32_t train, void* stream);
+/* grad (device, param_count floats) receives d(sum dout * out)/d(params);
+ * complex weights get (d/dRe, d/dIm). */
+acm_status acm_fno_backward(const acm_fno_shape* shape, const acm_grid* grid, int32_t batch,
+                            const uint16_t* params_bf16, const uint8_t* H, const float* dout,
+                            float* grad, void* workspace, int64_t workspace_bytes, void* stream);
+/* One Adam step (Kingma & Ba) on n parameters; step counts from 1. */
+acm_status acm_fno_adam(int64_t n, float* params, uint16_t* params_bf16, const float* grad,
+                        float* m, float* v, int64_t step, double lr, double beta1, double beta2,
+                        double eps, void* stream);
+acm_status acm_fno_to_bf16(int64_t n, const float* params, uint16_t* params_bf16, void* stream);
+/* loss = mean (out - target)^2 (FP64 sum, host); dout = 2 (out - target) / n. */
+acm_status acm_fno_mse(int64_t n, const float* out, const float* target, float* dout,
+                       double* loss, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

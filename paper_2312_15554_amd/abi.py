@@ -40,6 +40,11 @@ class acm_stats(C.Structure):
                 ("kernel_ms", C.c_double * 8), ("kernel_calls", C.c_int64 * 8)]
 
 
+class acm_fno_shape(C.Structure):
+    _fields_ = [("channels", C.c_int32), ("hidden", C.c_int32), ("modes", C.c_int32),
+                ("layers", C.c_int32)]
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "acm_default_penalty": (None, [C.POINTER(acm_penalty)]),
@@ -61,6 +66,18 @@ SIGNATURES = {
                                       C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p), C.c_void_p,
                                       C.c_double, C.c_double, C.POINTER(C.c_double),
                                       C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]),
+    "acm_fno_param_count": (C.c_int64, [C.POINTER(acm_fno_shape)]),
+    "acm_fno_workspace_bytes": (C.c_int64, [C.POINTER(acm_fno_shape), C.POINTER(acm_grid), C.c_int32,
+                                            C.c_int32]),
+    "acm_fno_forward": (C.c_int, [C.POINTER(acm_fno_shape), C.POINTER(acm_grid), C.c_int32, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]),
+    "acm_fno_backward": (C.c_int, [C.POINTER(acm_fno_shape), C.POINTER(acm_grid), C.c_int32, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "acm_fno_adam": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_int64, C.c_double, C.c_double, C.c_double, C.c_double, C.c_void_p]),
+    "acm_fno_to_bf16": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "acm_fno_mse": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
+                              C.c_void_p]),
     "acm_fft_r2c": (C.c_int, [C.POINTER(acm_grid), C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "acm_fft_c2r": (C.c_int, [C.POINTER(acm_grid), C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
 }

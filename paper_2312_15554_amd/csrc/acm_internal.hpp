@@ -190,6 +190,37 @@ template <typename T>
 hipError_t launch_slab_rhs(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
                            const StokesCellArgs* many, int ncells, hipStream_t s);
 
+// FNO kernels (k_fno.hip).
+hipError_t fno_lift(const uint8_t* H, const uint16_t* Pw, const uint16_t* Pb, float* v, int C,
+                    int64_t nvox, int B, hipStream_t s);
+hipError_t fno_gather(const void* spec, void* out, const int* midx, int nm, int64_t nspec,
+                      int nfields, hipStream_t s);
+hipError_t fno_mix(const void* Xm, const uint16_t* R, void* spec, const int* midx, int nm, int C,
+                   int B, int64_t nspec, bool adjoint, hipStream_t s);
+hipError_t fno_dR(const void* Fm, const void* Xm, const float* mw, float* dR, int nm, int C,
+                  int B, float inv_n, hipStream_t s);
+hipError_t fno_pointwise(int C, const float* vin, const float* k, const uint16_t* W,
+                         const uint16_t* b, float* pre, float* vout, int64_t nvox, int B,
+                         int act, hipStream_t s);
+hipError_t fno_pointwise_bwd(int C, const float* dv, const float* pre, const uint16_t* W,
+                             float* dpre, float* dvdir, int64_t nvox, int B, int act,
+                             hipStream_t s);
+hipError_t fno_add(float* a, const float* b, int64_t n, hipStream_t s);
+hipError_t fno_project(int C, const float* v, const uint16_t* Q1, const uint16_t* c1,
+                       const uint16_t* Q2, const uint16_t* c2, float* out, int Cp, int64_t nvox,
+                       int B, hipStream_t s);
+hipError_t fno_project_bwd(int C, const float* v, const float* dout, const uint16_t* Q1,
+                           const uint16_t* c1, const uint16_t* Q2, float* h, float* dh, float* dv,
+                           int Cp, int64_t nvox, int B, hipStream_t s);
+int fno_outer_blocks(int64_t nvox, int B);
+hipError_t fno_outer(const float* A, const float* Bm, const uint8_t* Bu8, int P, int Q,
+                     int64_t nvox, int B, float* part, float* out, hipStream_t s);
+hipError_t fno_adam(float* p, uint16_t* pb, const float* g, float* m, float* v, int64_t n,
+                    float lr, float b1, float b2, float eps, float c1, float c2, hipStream_t s);
+hipError_t fno_to_bf16(const float* p, uint16_t* pb, int64_t n, hipStream_t s);
+hipError_t fno_mse(const float* out, const float* tgt, float* dout, int64_t n, double inv_count,
+                   double* part, int nblk, hipStream_t s);
+
 // Grid-size helpers used by the host to size partial-sum buffers.
 int stokes_green_blocks(const Geom& g, int precision_bytes);
 int stokes_local_blocks(const Geom& g, int precision_bytes);

@@ -1,0 +1,535 @@
+// Fourier-neural-operator warm start: forward, backward and Adam kernels.
+//
+// The network maps the solid indicator H of a cell to an initial guess
+// (u_x, u_y, u_z, p) for the Stokes ADMM (Li et al., ICLR 2021, Fourier
+// neural operator):
+//   v0 = Pw H + Pb;  v_{l+1} = act_l(W_l v_l + b_l + K_l v_l);
+//   K_l v = inverse real FFT of (R_l . forward real FFT of v) on the kept modes
+//   (kx < m, ky and kz in [0, m) U [N-m, N));  act = GELU (tanh form) except
+//   after the last layer;  out = Q2 GELU(Q1 v_L + c1) + c2.
+// Weights are BF16 (rounded from FP32 master copies by the Adam kernel);
+// activations, transforms and every accumulation are FP32, weight-gradient
+// reductions are deterministic (per-block partials, then an ordered sum).
+#include "pass_common.hpp"
+
+namespace acm {
+
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  const uint32_t u = __float_as_uint(f);
+  const uint32_t r = ((u >> 16) & 1u) + 0x7fffu;  // round to nearest even
+  return (uint16_t)((u + r) >> 16);
+}
+__device__ __forceinline__ float gelu_f(float x) {
+  const float k = 0.7978845608028654f;
+  return 0.5f * x * (1.f + tanhf(k * (x + 0.044715f * x * x * x)));
+}
+__device__ __forceinline__ float gelu_grad_f(float x) {
+  const float k = 0.7978845608028654f;
+  const float t = tanhf(k * (x + 0.044715f * x * x * x));
+  return 0.5f * (1.f + t) + 0.5f * x * (1.f - t * t) * k * (1.f + 3.f * 0.044715f * x * x);
+}
+
+// ------------------------------------------------------------------- lift
+__global__ __launch_bounds__(256) void k_fno_lift(const uint8_t* __restrict__ H,
+                                                  const uint16_t* __restrict__ Pw,
+                                                  const uint16_t* __restrict__ Pb,
+                                                  float* __restrict__ v, int C, int64_t nvox,
+                                                  int B) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (x >= nvox) return;
+  const float h = H[(int64_t)b * nvox + x] ? 1.f : 0.f;
+  for (int c = 0; c < C; ++c) v[((int64_t)b * C + c) * nvox + x] = bf2f(Pw[c]) * h + bf2f(Pb[c]);
+}
+
+// ----------------------------------------------------------- kept modes
+// Gather the kept modes of every (b, c) half spectrum into a compact array
+// [B*C][nm] and (optionally) clear the full spectrum afterwards is done by the
+// host with a memset.
+__global__ __launch_bounds__(256) void k_fno_gather(const float2* __restrict__ spec,
+                                                    float2* __restrict__ out,
+                                                    const int* __restrict__ midx, int nm,
+                                                    int64_t nspec, int nfields) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int f = blockIdx.y;
+  if (j >= nm || f >= nfields) return;
+  out[(int64_t)f * nm + j] = spec[(int64_t)f * nspec + midx[j]];
+}
+
+// Y[b][o][m] = sum_i R[m][o][i] X[b][i][m] (conj(R) and sum over o when
+// ADJ: Z[b][i][m] = sum_o conj(R[m][o][i]) X[b][o][m]); scattered into the
+// (cleared) full spectrum at the kept-mode offsets.
+template <bool ADJ>
+__global__ __launch_bounds__(256) void k_fno_mix(const float2* __restrict__ Xm,
+                                                 const uint16_t* __restrict__ R,
+                                                 float2* __restrict__ spec,
+                                                 const int* __restrict__ midx, int nm, int C,
+                                                 int64_t nspec) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int o = blockIdx.y;  // output channel
+  const int b = blockIdx.z;
+  if (j >= nm) return;
+  float ar = 0.f, ai = 0.f;
+  for (int i = 0; i < C; ++i) {
+    // R[m][o][i] complex (re, im) as bf16 pairs; adjoint uses R[m][i][o] conjugated
+    const int64_t ri = ADJ ? (((int64_t)j * C + i) * C + o) : (((int64_t)j * C + o) * C + i);
+    const float rr = bf2f(R[2 * ri]), rim = bf2f(R[2 * ri + 1]);
+    const float2 x = Xm[((int64_t)b * C + i) * nm + j];
+    if (!ADJ) {
+      ar += rr * x.x - rim * x.y;
+      ai += rr * x.y + rim * x.x;
+    } else {
+      ar += rr * x.x + rim * x.y;
+      ai += rr * x.y - rim * x.x;
+    }
+  }
+  spec[((int64_t)b * C + o) * nspec + midx[j]] = make_float2(ar, ai);
+}
+
+// dR[m][o][i] = sum_b (w_m / N) F[b][o][m] conj(X[b][i][m])  (float pairs)
+__global__ __launch_bounds__(256) void k_fno_dR(const float2* __restrict__ Fm,
+                                                const float2* __restrict__ Xm,
+                                                const float* __restrict__ mw,
+                                                float* __restrict__ dR, int nm, int C, int B,
+                                                float inv_n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)nm * C * C;
+  if (t >= total) return;
+  const int i = (int)(t % C);
+  const int o = (int)((t / C) % C);
+  const int j = (int)(t / ((int64_t)C * C));
+  float ar = 0.f, ai = 0.f;
+  for (int b = 0; b < B; ++b) {
+    const float2 f = Fm[((int64_t)b * C + o) * nm + j];
+    const float2 x = Xm[((int64_t)b * C + i) * nm + j];
+    ar += f.x * x.x + f.y * x.y;
+    ai += f.y * x.x - f.x * x.y;
+  }
+  const float s = mw[j] * inv_n;
+  dR[2 * t] = ar * s;
+  dR[2 * t + 1] = ai * s;
+}
+
+// --------------------------------------------------------- pointwise layer
+// pre = W v + b + k;  vout = act(pre).  One thread per voxel; C <= 64.
+template <int C>
+__global__ __launch_bounds__(256) void k_fno_pointwise(const float* __restrict__ vin,
+                                                       const float* __restrict__ k,
+                                                       const uint16_t* __restrict__ W,
+                                                       const uint16_t* __restrict__ bias,
+                                                       float* __restrict__ pre,
+                                                       float* __restrict__ vout, int64_t nvox,
+                                                       int act) {
+  __shared__ float sW[C * C];
+  __shared__ float sb[C];
+  for (int e = threadIdx.x; e < C * C; e += blockDim.x) sW[e] = bf2f(W[e]);
+  for (int e = threadIdx.x; e < C; e += blockDim.x) sb[e] = bf2f(bias[e]);
+  __syncthreads();
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (x >= nvox) return;
+  const int64_t base = (int64_t)b * C * nvox + x;
+  float v[C];
+#pragma unroll
+  for (int i = 0; i < C; ++i) v[i] = vin[base + i * nvox];
+  for (int o = 0; o < C; ++o) {
+    float acc = sb[o] + k[base + o * nvox];
+#pragma unroll
+    for (int i = 0; i < C; ++i) acc += sW[o * C + i] * v[i];
+    if (pre) pre[base + o * nvox] = acc;
+    vout[base + o * nvox] = act ? gelu_f(acc) : acc;
+  }
+}
+
+// dpre = dv * act'(pre);  dvdir = W^T dpre.
+template <int C>
+__global__ __launch_bounds__(256) void k_fno_pointwise_bwd(const float* __restrict__ dv,
+                                                           const float* __restrict__ pre,
+                                                           const uint16_t* __restrict__ W,
+                                                           float* __restrict__ dpre,
+                                                           float* __restrict__ dvdir,
+                                                           int64_t nvox, int act) {
+  __shared__ float sW[C * C];
+  for (int e = threadIdx.x; e < C * C; e += blockDim.x) sW[e] = bf2f(W[e]);
+  __syncthreads();
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (x >= nvox) return;
+  const int64_t base = (int64_t)b * C * nvox + x;
+  float dp[C];
+#pragma unroll
+  for (int o = 0; o < C; ++o) {
+    const float g = dv[base + o * nvox];
+    dp[o] = act ? g * gelu_grad_f(pre[base + o * nvox]) : g;
+    dpre[base + o * nvox] = dp[o];
+  }
+  for (int i = 0; i < C; ++i) {
+    float acc = 0.f;
+#pragma unroll
+    for (int o = 0; o < C; ++o) acc += sW[o * C + i] * dp[o];
+    dvdir[base + i * nvox] = acc;
+  }
+}
+
+// dv += other
+__global__ __launch_bounds__(256) void k_fno_add(float* __restrict__ a, const float* __restrict__ b,
+                                                 int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] += b[i];
+}
+
+// --------------------------------------------------------------- projection
+// out[o] = sum_j Q2[o][j] GELU(sum_i Q1[j][i] v[i] + c1[j]) + c2[o]; optionally
+// store h (Cp channels) for the backward pass.
+template <int C>
+__global__ __launch_bounds__(256) void k_fno_project(const float* __restrict__ v,
+                                                     const uint16_t* __restrict__ Q1,
+                                                     const uint16_t* __restrict__ c1,
+                                                     const uint16_t* __restrict__ Q2,
+                                                     const uint16_t* __restrict__ c2,
+                                                     float* __restrict__ out, int Cp,
+                                                     int64_t nvox) {
+  extern __shared__ float sh[];
+  float* sQ1 = sh;               // Cp*C
+  float* sc1 = sQ1 + Cp * C;     // Cp
+  float* sQ2 = sc1 + Cp;         // 4*Cp
+  for (int e = threadIdx.x; e < Cp * C; e += blockDim.x) sQ1[e] = bf2f(Q1[e]);
+  for (int e = threadIdx.x; e < Cp; e += blockDim.x) sc1[e] = bf2f(c1[e]);
+  for (int e = threadIdx.x; e < 4 * Cp; e += blockDim.x) sQ2[e] = bf2f(Q2[e]);
+  __syncthreads();
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (x >= nvox) return;
+  float vv[C];
+#pragma unroll
+  for (int i = 0; i < C; ++i) vv[i] = v[((int64_t)b * C + i) * nvox + x];
+  float o4[4] = {bf2f(c2[0]), bf2f(c2[1]), bf2f(c2[2]), bf2f(c2[3])};
+  for (int j = 0; j < Cp; ++j) {
+    float hp = sc1[j];
+#pragma unroll
+    for (int i = 0; i < C; ++i) hp += sQ1[j * C + i] * vv[i];
+    const float h = gelu_f(hp);
+#pragma unroll
+    for (int o = 0; o < 4; ++o) o4[o] += sQ2[o * Cp + j] * h;
+  }
+#pragma unroll
+  for (int o = 0; o < 4; ++o) out[((int64_t)b * 4 + o) * nvox + x] = o4[o];
+}
+
+// Backward of the projection: writes h and dh (Cp channels each, for the
+// weight gradients) and dv = Q1^T dh.
+template <int C>
+__global__ __launch_bounds__(256) void k_fno_project_bwd(const float* __restrict__ v,
+                                                         const float* __restrict__ dout,
+                                                         const uint16_t* __restrict__ Q1,
+                                                         const uint16_t* __restrict__ c1,
+                                                         const uint16_t* __restrict__ Q2,
+                                                         float* __restrict__ h_out,
+                                                         float* __restrict__ dh_out,
+                                                         float* __restrict__ dv, int Cp,
+                                                         int64_t nvox) {
+  extern __shared__ float sh[];
+  float* sQ1 = sh;
+  float* sc1 = sQ1 + Cp * C;
+  float* sQ2 = sc1 + Cp;
+  for (int e = threadIdx.x; e < Cp * C; e += blockDim.x) sQ1[e] = bf2f(Q1[e]);
+  for (int e = threadIdx.x; e < Cp; e += blockDim.x) sc1[e] = bf2f(c1[e]);
+  for (int e = threadIdx.x; e < 4 * Cp; e += blockDim.x) sQ2[e] = bf2f(Q2[e]);
+  __syncthreads();
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (x >= nvox) return;
+  float vv[C], dvv[C];
+#pragma unroll
+  for (int i = 0; i < C; ++i) {
+    vv[i] = v[((int64_t)b * C + i) * nvox + x];
+    dvv[i] = 0.f;
+  }
+  float d4[4];
+#pragma unroll
+  for (int o = 0; o < 4; ++o) d4[o] = dout[((int64_t)b * 4 + o) * nvox + x];
+  for (int j = 0; j < Cp; ++j) {
+    float hp = sc1[j];
+#pragma unroll
+    for (int i = 0; i < C; ++i) hp += sQ1[j * C + i] * vv[i];
+    float g = 0.f;
+#pragma unroll
+    for (int o = 0; o < 4; ++o) g += sQ2[o * Cp + j] * d4[o];
+    const float dh = g * gelu_grad_f(hp);
+    h_out[((int64_t)b * Cp + j) * nvox + x] = gelu_f(hp);
+    dh_out[((int64_t)b * Cp + j) * nvox + x] = dh;
+#pragma unroll
+    for (int i = 0; i < C; ++i) dvv[i] += sQ1[j * C + i] * dh;
+  }
+#pragma unroll
+  for (int i = 0; i < C; ++i) dv[((int64_t)b * C + i) * nvox + x] = dvv[i];
+}
+
+// ----------------------------------------------------- outer-product sums
+// part[blk][p*Q + q] = sum over this block's voxels (all b) of A[b][p][x] * Bm[b][q][x]
+// (Bm == null: Bm = 1, giving sums of A; Bm_u8: a uint8 field as 0/1).
+constexpr int kOuterTile = 64;
+__global__ __launch_bounds__(256) void k_fno_outer(const float* __restrict__ A,
+                                                   const float* __restrict__ Bm,
+                                                   const uint8_t* __restrict__ Bu8, int P, int Q,
+                                                   int64_t nvox, int B, int64_t chunk,
+                                                   float* __restrict__ part) {
+  extern __shared__ float sm[];
+  float* sA = sm;                       // P * kOuterTile
+  float* sB = sA + P * kOuterTile;      // Q * kOuterTile
+  const int PQ = P * Q;
+  constexpr int MAXE = 16;  // entries per thread: P*Q <= 16*256
+  float acc[MAXE];
+#pragma unroll
+  for (int e = 0; e < MAXE; ++e) acc[e] = 0.f;
+  const int64_t total = nvox * B;
+  const int64_t beg = (int64_t)blockIdx.x * chunk;
+  const int64_t end = beg + chunk < total ? beg + chunk : total;
+  for (int64_t t0 = beg; t0 < end; t0 += kOuterTile) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < (P + Q) * kOuterTile; e += blockDim.x) {
+      const int r = e / kOuterTile, c = e - r * kOuterTile;
+      const int64_t t = t0 + c;
+      float val = 0.f;
+      if (t < end) {
+        const int64_t b = t / nvox, x = t - b * nvox;
+        if (r < P) {
+          val = A[(b * P + r) * nvox + x];
+        } else {
+          const int q = r - P;
+          val = Bm ? Bm[(b * Q + q) * nvox + x] : (Bu8 ? (Bu8[b * nvox + x] ? 1.f : 0.f) : 1.f);
+        }
+      }
+      sm[e] = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < MAXE; ++k) {
+      const int e = threadIdx.x + k * 256;
+      if (e < PQ) {
+        const int p = e / Q, q = e - p * Q;
+        float s = 0.f;
+        for (int c = 0; c < kOuterTile; ++c) s += sA[p * kOuterTile + c] * sB[q * kOuterTile + c];
+        acc[k] += s;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < MAXE; ++k) {
+    const int e = threadIdx.x + k * 256;
+    if (e < PQ) part[(int64_t)blockIdx.x * PQ + e] = acc[k];
+  }
+}
+
+// out[e] = sum over blocks (in order) of part[blk][e]
+__global__ __launch_bounds__(256) void k_fno_sum_parts(const float* __restrict__ part, int nblk,
+                                                       int n, float* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double s = 0.0;
+  for (int k = 0; k < nblk; ++k) s += part[(int64_t)k * n + e];
+  out[e] = (float)s;
+}
+
+// ------------------------------------------------------------------- Adam
+__global__ __launch_bounds__(256) void k_fno_adam(float* __restrict__ p, uint16_t* __restrict__ pb,
+                                                  const float* __restrict__ g,
+                                                  float* __restrict__ m, float* __restrict__ v,
+                                                  int64_t n, float lr, float b1, float b2,
+                                                  float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  p[i] = pi;
+  pb[i] = f2bf(pi);
+}
+
+__global__ __launch_bounds__(256) void k_fno_to_bf16(const float* __restrict__ p,
+                                                     uint16_t* __restrict__ pb, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) pb[i] = f2bf(p[i]);
+}
+
+// loss = sum (out - target)^2 / count ;  dout = 2 (out - target) / count
+__global__ __launch_bounds__(256) void k_fno_mse(const float* __restrict__ out,
+                                                 const float* __restrict__ tgt,
+                                                 float* __restrict__ dout, int64_t n,
+                                                 double inv_count, double* __restrict__ part) {
+  __shared__ double red[4];
+  double acc[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double d = (double)out[i] - (double)tgt[i];
+    acc[0] += d * d;
+    dout[i] = (float)(2.0 * d * inv_count);
+  }
+  block_sum<1>(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc[0] * inv_count;
+}
+
+// ------------------------------------------------------------- host glue
+struct FnoLaunch {
+  hipStream_t s;
+};
+
+hipError_t fno_lift(const uint8_t* H, const uint16_t* Pw, const uint16_t* Pb, float* v, int C,
+                    int64_t nvox, int B, hipStream_t s) {
+  dim3 grid((unsigned)((nvox + 255) / 256), (unsigned)B);
+  hipLaunchKernelGGL(k_fno_lift, grid, dim3(256), 0, s, H, Pw, Pb, v, C, nvox, B);
+  return hipGetLastError();
+}
+
+hipError_t fno_gather(const void* spec, void* out, const int* midx, int nm, int64_t nspec,
+                      int nfields, hipStream_t s) {
+  dim3 grid((unsigned)((nm + 255) / 256), (unsigned)nfields);
+  hipLaunchKernelGGL(k_fno_gather, grid, dim3(256), 0, s, (const float2*)spec, (float2*)out, midx,
+                     nm, nspec, nfields);
+  return hipGetLastError();
+}
+
+hipError_t fno_mix(const void* Xm, const uint16_t* R, void* spec, const int* midx, int nm, int C,
+                   int B, int64_t nspec, bool adjoint, hipStream_t s) {
+  dim3 grid((unsigned)((nm + 255) / 256), (unsigned)C, (unsigned)B);
+  if (adjoint)
+    hipLaunchKernelGGL(k_fno_mix<true>, grid, dim3(256), 0, s, (const float2*)Xm, R, (float2*)spec,
+                       midx, nm, C, nspec);
+  else
+    hipLaunchKernelGGL(k_fno_mix<false>, grid, dim3(256), 0, s, (const float2*)Xm, R,
+                       (float2*)spec, midx, nm, C, nspec);
+  return hipGetLastError();
+}
+
+hipError_t fno_dR(const void* Fm, const void* Xm, const float* mw, float* dR, int nm, int C,
+                  int B, float inv_n, hipStream_t s) {
+  const int64_t total = (int64_t)nm * C * C;
+  hipLaunchKernelGGL(k_fno_dR, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                     (const float2*)Fm, (const float2*)Xm, mw, dR, nm, C, B, inv_n);
+  return hipGetLastError();
+}
+
+#define FNO_CHANNELS(X) X(4) X(8) X(16) X(32)
+
+hipError_t fno_pointwise(int C, const float* vin, const float* k, const uint16_t* W,
+                         const uint16_t* b, float* pre, float* vout, int64_t nvox, int B,
+                         int act, hipStream_t s) {
+  dim3 grid((unsigned)((nvox + 255) / 256), (unsigned)B);
+  switch (C) {
+#define CASE(CC)                                                                              \
+  case CC:                                                                                    \
+    hipLaunchKernelGGL((k_fno_pointwise<CC>), grid, dim3(256), 0, s, vin, k, W, b, pre, vout, \
+                       nvox, act);                                                            \
+    return hipGetLastError();
+    FNO_CHANNELS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t fno_pointwise_bwd(int C, const float* dv, const float* pre, const uint16_t* W,
+                             float* dpre, float* dvdir, int64_t nvox, int B, int act,
+                             hipStream_t s) {
+  dim3 grid((unsigned)((nvox + 255) / 256), (unsigned)B);
+  switch (C) {
+#define CASE(CC)                                                                              \
+  case CC:                                                                                    \
+    hipLaunchKernelGGL((k_fno_pointwise_bwd<CC>), grid, dim3(256), 0, s, dv, pre, W, dpre,    \
+                       dvdir, nvox, act);                                                     \
+    return hipGetLastError();
+    FNO_CHANNELS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t fno_add(float* a, const float* b, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fno_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, n);
+  return hipGetLastError();
+}
+
+hipError_t fno_project(int C, const float* v, const uint16_t* Q1, const uint16_t* c1,
+                       const uint16_t* Q2, const uint16_t* c2, float* out, int Cp, int64_t nvox,
+                       int B, hipStream_t s) {
+  dim3 grid((unsigned)((nvox + 255) / 256), (unsigned)B);
+  const size_t lds = sizeof(float) * ((size_t)Cp * C + Cp + 4 * Cp);
+  switch (C) {
+#define CASE(CC)                                                                              \
+  case CC:                                                                                    \
+    hipLaunchKernelGGL((k_fno_project<CC>), grid, dim3(256), lds, s, v, Q1, c1, Q2, c2, out,  \
+                       Cp, nvox);                                                             \
+    return hipGetLastError();
+    FNO_CHANNELS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t fno_project_bwd(int C, const float* v, const float* dout, const uint16_t* Q1,
+                           const uint16_t* c1, const uint16_t* Q2, float* h, float* dh, float* dv,
+                           int Cp, int64_t nvox, int B, hipStream_t s) {
+  dim3 grid((unsigned)((nvox + 255) / 256), (unsigned)B);
+  const size_t lds = sizeof(float) * ((size_t)Cp * C + Cp + 4 * Cp);
+  switch (C) {
+#define CASE(CC)                                                                              \
+  case CC:                                                                                    \
+    hipLaunchKernelGGL((k_fno_project_bwd<CC>), grid, dim3(256), lds, s, v, dout, Q1, c1, Q2, \
+                       h, dh, dv, Cp, nvox);                                                  \
+    return hipGetLastError();
+    FNO_CHANNELS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+// G[p][q] = sum A[b][p][x] Bm[b][q][x]; `part` must hold nblk*P*Q floats.
+int fno_outer_blocks(int64_t nvox, int B) {
+  const int64_t total = nvox * B;
+  int64_t nb = (total + 8191) / 8192;  // 8192 (voxel, b) pairs per block
+  return (int)std::max<int64_t>(1, std::min<int64_t>(nb, 4096));
+}
+
+hipError_t fno_outer(const float* A, const float* Bm, const uint8_t* Bu8, int P, int Q,
+                     int64_t nvox, int B, float* part, float* out, hipStream_t s) {
+  if (P * Q > 16 * 256) return hipErrorInvalidValue;
+  const int nb = fno_outer_blocks(nvox, B);
+  const int64_t total = nvox * B;
+  int64_t chunk = (total + nb - 1) / nb;
+  chunk = ((chunk + kOuterTile - 1) / kOuterTile) * kOuterTile;
+  const size_t lds = sizeof(float) * (size_t)(P + Q) * kOuterTile;
+  hipLaunchKernelGGL(k_fno_outer, dim3(nb), dim3(256), lds, s, A, Bm, Bu8, P, Q, nvox, B, chunk,
+                     part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fno_sum_parts, dim3((unsigned)((P * Q + 255) / 256)), dim3(256), 0, s, part,
+                     nb, P * Q, out);
+  return hipGetLastError();
+}
+
+hipError_t fno_adam(float* p, uint16_t* pb, const float* g, float* m, float* v, int64_t n,
+                    float lr, float b1, float b2, float eps, float c1, float c2, hipStream_t s) {
+  hipLaunchKernelGGL(k_fno_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, pb, g, m, v,
+                     n, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t fno_to_bf16(const float* p, uint16_t* pb, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fno_to_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, pb, n);
+  return hipGetLastError();
+}
+
+hipError_t fno_mse(const float* out, const float* tgt, float* dout, int64_t n, double inv_count,
+                   double* part, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_fno_mse, dim3(nblk), dim3(256), 0, s, out, tgt, dout, n, inv_count, part);
+  return hipGetLastError();
+}
+
+}  // namespace acm

@@ -990,6 +990,217 @@ static acm_status fft_impl(CellPlan* pl, int nfields, const void* in, void* out,
   return ACM_OK;
 }
 
+
+// --------------------------------------------------------------------- FNO
+// Parameter layout (FP32 master / BF16 copy, complex weights as (re, im)):
+//   Pw[C] Pb[C] | per layer: R[nm][C][C] complex, W[C][C], b[C] | Q1[Cp][C]
+//   c1[Cp] Q2[4][Cp] c2[4],  nm = (2m)^2 m kept modes.
+struct FnoLayout {
+  int C, Cp, m, L, nm;
+  int64_t Pw, Pb, R[16], W[16], b[16], Q1, c1, Q2, c2, total;
+};
+
+static bool fno_layout(const acm_fno_shape* sh, FnoLayout* f) {
+  if (!sh) return false;
+  f->C = sh->channels;
+  f->Cp = sh->hidden;
+  f->m = sh->modes;
+  f->L = sh->layers;
+  if (!(f->C == 4 || f->C == 8 || f->C == 16 || f->C == 32)) return false;
+  if (f->Cp < 1 || f->Cp * f->C > 4096 || f->Cp > 1024) return false;
+  if (f->m < 1 || f->L < 1 || f->L > 16) return false;
+  f->nm = (2 * f->m) * (2 * f->m) * f->m;
+  int64_t o = 0;
+  f->Pw = o;
+  o += f->C;
+  f->Pb = o;
+  o += f->C;
+  for (int l = 0; l < f->L; ++l) {
+    f->R[l] = o;
+    o += 2LL * f->nm * f->C * f->C;
+    f->W[l] = o;
+    o += (int64_t)f->C * f->C;
+    f->b[l] = o;
+    o += f->C;
+  }
+  f->Q1 = o;
+  o += (int64_t)f->Cp * f->C;
+  f->c1 = o;
+  o += f->Cp;
+  f->Q2 = o;
+  o += 4LL * f->Cp;
+  f->c2 = o;
+  o += 4;
+  f->total = o;
+  return true;
+}
+
+// Workspace carve-up (train = 1 keeps every layer's activations for backward).
+struct FnoWs {
+  float* vs[17];
+  float* pre[16];
+  float2* Xm[16];
+  float2* spec;
+  float* kbuf;
+  float* dv;
+  float* dvdir;
+  float* dpre;
+  float* h;
+  float* dh;
+  float2* Fm;
+  float* part;
+  int* midx;
+  float* mw;
+  int64_t bytes;
+};
+
+static int64_t fno_ws_plan(const FnoLayout& f, const Geom& g, int B, int train, char* base, FnoWs* w) {
+  const int64_t nv = g.ntot;
+  const int64_t act = (int64_t)B * f.C * nv * 4;
+  const int64_t xm = (int64_t)B * f.C * f.nm * 8;
+  int64_t o = 0;
+  auto take = [&](int64_t b) {
+    char* p = base ? base + o : nullptr;
+    o += (b + 255) & ~(int64_t)255;
+    return p;
+  };
+  const int nact = train ? f.L + 1 : 2;
+  for (int l = 0; l < nact; ++l) w->vs[l] = (float*)take(act);
+  if (train)
+    for (int l = 0; l < f.L; ++l) w->pre[l] = (float*)take(act);
+  for (int l = 0; l < (train ? f.L : 1); ++l) w->Xm[l] = (float2*)take(xm);
+  w->spec = (float2*)take((int64_t)B * f.C * g.nspec * 8);
+  w->kbuf = (float*)take(act);
+  w->midx = (int*)take(4LL * f.nm);
+  w->mw = (float*)take(4LL * f.nm);
+  if (train) {
+    w->dv = (float*)take(act);
+    w->dvdir = (float*)take(act);
+    w->dpre = (float*)take(act);
+    w->h = (float*)take((int64_t)B * f.Cp * nv * 4);
+    w->dh = (float*)take((int64_t)B * f.Cp * nv * 4);
+    w->Fm = (float2*)take(xm);
+    w->part = (float*)take(4LL * fno_outer_blocks(nv, B) * 4096);
+  }
+  w->bytes = o;
+  return o;
+}
+
+static acm_status fno_check(const acm_fno_shape* sh, const acm_grid* grid, int B, CellPlan** pl,
+                            FnoLayout* f) {
+  if (!fno_layout(sh, f))
+    return fail(ACM_E_INVALID, "fno shape: channels in {4,8,16,32}, hidden*channels <= 4096, modes >= 1, 1 <= layers <= 16");
+  acm_status r = get_plan(grid, ACM_FP32, pl);
+  if (r != ACM_OK) return r;
+  const Geom& g = (*pl)->g;
+  if (g.dim != 3 || g.nx != g.ny || g.ny != g.nz) return fail(ACM_E_INVALID, "fno needs a cubic 3D grid");
+  if (2 * f->m > g.nx) return fail(ACM_E_INVALID, "fno modes must satisfy 2*modes <= n");
+  if (B < 1) return fail(ACM_E_INVALID, "batch >= 1 required");
+  return ACM_OK;
+}
+
+static hipError_t fno_mode_tables(const FnoLayout& f, const Geom& g, FnoWs& w, hipStream_t s) {
+  std::vector<int> mi(f.nm);
+  std::vector<float> mw(f.nm);
+  std::vector<int> idx;
+  for (int k = 0; k < f.m; ++k) idx.push_back(k);
+  for (int k = g.nx - f.m; k < g.nx; ++k) idx.push_back(k);
+  int j = 0;
+  for (int kz : idx)
+    for (int ky : idx)
+      for (int kx = 0; kx < f.m; ++kx, ++j) {
+        mi[j] = (kz * g.ny + ky) * g.xh + kx;
+        mw[j] = (kx == 0 || 2 * kx == g.nx) ? 1.f : 2.f;
+      }
+  hipError_t e = hipMemcpyAsync(w.midx, mi.data(), 4 * mi.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(w.mw, mw.data(), 4 * mw.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // host vectors go out of scope
+  return e;
+}
+
+// Forward real FFT of nf fields (in) into spec; inverse (spec -> out, normalised).
+static hipError_t fno_fft_fwd(const Geom& g, const DevTables<float>& tb, int nf, const float* in,
+                              void* spec, hipStream_t s) {
+  hipError_t e = launch_rows_r2c<float>(g, tb, nf, in, spec, s);
+  if (e == hipSuccess) e = launch_cols<float>(g, tb, 1, -1, nf, spec, s);
+  if (e == hipSuccess) e = launch_cols<float>(g, tb, 2, -1, nf, spec, s);
+  return e;
+}
+static hipError_t fno_fft_inv(const Geom& g, const DevTables<float>& tb, int nf, void* spec,
+                              float* out, hipStream_t s) {
+  hipError_t e = launch_cols<float>(g, tb, 2, +1, nf, spec, s);
+  if (e == hipSuccess) e = launch_cols<float>(g, tb, 1, +1, nf, spec, s);
+  if (e == hipSuccess) e = launch_rows_c2r<float>(g, tb, nf, spec, out, 1.0 / (double)g.ntot, s);
+  return e;
+}
+
+#define FNO_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) return fail(ACM_E_HIP, std::string("fno: ") + #expr + ": " +    \
+                                                     hipGetErrorString(e_));             \
+  } while (0)
+
+static acm_status fno_forward_impl(const FnoLayout& f, CellPlan* pl, int B, const uint16_t* P,
+                                   const uint8_t* H, float* out, FnoWs& w, int train,
+                                   hipStream_t s) {
+  const Geom& g = pl->g;
+  DevTables<float> tb = tables_of<float>(pl);
+  const int64_t nv = g.ntot;
+  const int nf = B * f.C;
+  FNO_TRY(fno_mode_tables(f, g, w, s));
+  FNO_TRY(fno_lift(H, P + f.Pw, P + f.Pb, w.vs[0], f.C, nv, B, s));
+  for (int l = 0; l < f.L; ++l) {
+    float* vin = train ? w.vs[l] : w.vs[l & 1];
+    float* vout = train ? w.vs[l + 1] : w.vs[(l + 1) & 1];
+    float2* Xm = train ? w.Xm[l] : w.Xm[0];
+    FNO_TRY(fno_fft_fwd(g, tb, nf, vin, w.spec, s));
+    FNO_TRY(fno_gather(w.spec, Xm, w.midx, f.nm, g.nspec, nf, s));
+    FNO_TRY(hipMemsetAsync(w.spec, 0, (size_t)nf * g.nspec * 8, s));
+    FNO_TRY(fno_mix(Xm, P + f.R[l], w.spec, w.midx, f.nm, f.C, B, g.nspec, false, s));
+    FNO_TRY(fno_fft_inv(g, tb, nf, w.spec, w.kbuf, s));
+    FNO_TRY(fno_pointwise(f.C, vin, w.kbuf, P + f.W[l], P + f.b[l], train ? w.pre[l] : nullptr,
+                          vout, nv, B, l < f.L - 1 ? 1 : 0, s));
+  }
+  float* vl = train ? w.vs[f.L] : w.vs[f.L & 1];
+  FNO_TRY(fno_project(f.C, vl, P + f.Q1, P + f.c1, P + f.Q2, P + f.c2, out, f.Cp, nv, B, s));
+  return ACM_OK;
+}
+
+static acm_status fno_backward_impl(const FnoLayout& f, CellPlan* pl, int B, const uint16_t* P,
+                                    const uint8_t* H, const float* dout, float* grad, FnoWs& w,
+                                    hipStream_t s) {
+  const Geom& g = pl->g;
+  DevTables<float> tb = tables_of<float>(pl);
+  const int64_t nv = g.ntot;
+  const int nf = B * f.C;
+  const int64_t nact = (int64_t)nf * nv;
+  // projection
+  FNO_TRY(fno_project_bwd(f.C, w.vs[f.L], dout, P + f.Q1, P + f.c1, P + f.Q2, w.h, w.dh, w.dv,
+                          f.Cp, nv, B, s));
+  FNO_TRY(fno_outer(w.dh, w.vs[f.L], nullptr, f.Cp, f.C, nv, B, w.part, grad + f.Q1, s));
+  FNO_TRY(fno_outer(w.dh, nullptr, nullptr, f.Cp, 1, nv, B, w.part, grad + f.c1, s));
+  FNO_TRY(fno_outer(dout, w.h, nullptr, 4, f.Cp, nv, B, w.part, grad + f.Q2, s));
+  FNO_TRY(fno_outer(dout, nullptr, nullptr, 4, 1, nv, B, w.part, grad + f.c2, s));
+  for (int l = f.L - 1; l >= 0; --l) {
+    FNO_TRY(fno_pointwise_bwd(f.C, w.dv, w.pre[l], P + f.W[l], w.dpre, w.dvdir, nv, B,
+                              l < f.L - 1 ? 1 : 0, s));
+    FNO_TRY(fno_outer(w.dpre, w.vs[l], nullptr, f.C, f.C, nv, B, w.part, grad + f.W[l], s));
+    FNO_TRY(fno_outer(w.dpre, nullptr, nullptr, f.C, 1, nv, B, w.part, grad + f.b[l], s));
+    // spectral path: F = FFT(dpre); dR = sum_b (w/N) F conj(X); dv_spec = iFFT(R^H F)
+    FNO_TRY(fno_fft_fwd(g, tb, nf, w.dpre, w.spec, s));
+    FNO_TRY(fno_gather(w.spec, w.Fm, w.midx, f.nm, g.nspec, nf, s));
+    FNO_TRY(fno_dR(w.Fm, w.Xm[l], w.mw, grad + f.R[l], f.nm, f.C, B, (float)(1.0 / (double)nv), s));
+    FNO_TRY(hipMemsetAsync(w.spec, 0, (size_t)nf * g.nspec * 8, s));
+    FNO_TRY(fno_mix(w.Fm, P + f.R[l], w.spec, w.midx, f.nm, f.C, B, g.nspec, true, s));
+    FNO_TRY(fno_fft_inv(g, tb, nf, w.spec, w.dv, s));
+    FNO_TRY(fno_add(w.dv, w.dvdir, nact, s));
+  }
+  FNO_TRY(fno_outer(w.dv, nullptr, H, f.C, 1, nv, B, w.part, grad + f.Pw, s));
+  FNO_TRY(fno_outer(w.dv, nullptr, nullptr, f.C, 1, nv, B, w.part, grad + f.Pb, s));
+  return ACM_OK;
+}
+
 }  // namespace acm
 
 // ===================================================================== C ABI
@@ -1146,6 +1357,106 @@ acm_status acm_effective_props(const acm_grid* grid, int32_t precision, const ui
                               (hipStream_t)stream);
   return props_impl<float>(pl, H, n_flow, u, n_chi, chi, u_transport, nu, Pe, K, D, mass,
                            (hipStream_t)stream);
+}
+
+
+int64_t acm_fno_param_count(const acm_fno_shape* shape) {
+  FnoLayout f;
+  if (!fno_layout(shape, &f)) return -1;
+  return f.total;
+}
+
+int64_t acm_fno_workspace_bytes(const acm_fno_shape* shape, const acm_grid* grid, int32_t batch,
+                                int32_t train) {
+  g_err.clear();
+  FnoLayout f;
+  CellPlan* pl = nullptr;
+  if (fno_check(shape, grid, batch, &pl, &f) != ACM_OK) return -1;
+  FnoWs w;
+  return fno_ws_plan(f, pl->g, batch, train, nullptr, &w);
+}
+
+acm_status acm_fno_forward(const acm_fno_shape* shape, const acm_grid* grid, int32_t batch,
+                           const uint16_t* params_bf16, const uint8_t* H, float* out,
+                           void* workspace, int64_t workspace_bytes, int32_t train,
+                           void* stream) {
+  g_err.clear();
+  if (!params_bf16 || !H || !out || !workspace) return fail(ACM_E_INVALID, "null argument");
+  FnoLayout f;
+  CellPlan* pl = nullptr;
+  acm_status r = fno_check(shape, grid, batch, &pl, &f);
+  if (r != ACM_OK) return r;
+  FnoWs w;
+  if (fno_ws_plan(f, pl->g, batch, train, (char*)workspace, &w) > workspace_bytes)
+    return fail(ACM_E_INVALID, "workspace too small (see acm_fno_workspace_bytes)");
+  hipStream_t s = work_stream(pl->device);
+  if (!s) return fail(ACM_E_HIP, "cannot create work stream");
+  HIP_TRY(join_from((hipStream_t)stream, s));
+  r = fno_forward_impl(f, pl, batch, params_bf16, H, out, w, train ? 1 : 0, s);
+  if (r != ACM_OK) return r;
+  HIP_TRY(hipStreamSynchronize(s));
+  return ACM_OK;
+}
+
+acm_status acm_fno_backward(const acm_fno_shape* shape, const acm_grid* grid, int32_t batch,
+                            const uint16_t* params_bf16, const uint8_t* H, const float* dout,
+                            float* grad, void* workspace, int64_t workspace_bytes, void* stream) {
+  g_err.clear();
+  if (!params_bf16 || !H || !dout || !grad || !workspace) return fail(ACM_E_INVALID, "null argument");
+  FnoLayout f;
+  CellPlan* pl = nullptr;
+  acm_status r = fno_check(shape, grid, batch, &pl, &f);
+  if (r != ACM_OK) return r;
+  FnoWs w;
+  if (fno_ws_plan(f, pl->g, batch, 1, (char*)workspace, &w) > workspace_bytes)
+    return fail(ACM_E_INVALID, "workspace too small (see acm_fno_workspace_bytes with train = 1)");
+  hipStream_t s = work_stream(pl->device);
+  if (!s) return fail(ACM_E_HIP, "cannot create work stream");
+  HIP_TRY(join_from((hipStream_t)stream, s));
+  r = fno_backward_impl(f, pl, batch, params_bf16, H, dout, grad, w, s);
+  if (r != ACM_OK) return r;
+  HIP_TRY(hipStreamSynchronize(s));
+  return ACM_OK;
+}
+
+acm_status acm_fno_adam(int64_t n, float* params, uint16_t* params_bf16, const float* grad,
+                        float* m, float* v, int64_t step, double lr, double beta1, double beta2,
+                        double eps, void* stream) {
+  g_err.clear();
+  if (n < 1 || !params || !params_bf16 || !grad || !m || !v || step < 1)
+    return fail(ACM_E_INVALID, "bad Adam arguments");
+  hipStream_t s = (hipStream_t)stream;
+  const double c1 = 1.0 - pow(beta1, (double)step), c2 = 1.0 - pow(beta2, (double)step);
+  HIP_TRY(fno_adam(params, params_bf16, grad, m, v, n, (float)lr, (float)beta1, (float)beta2,
+                   (float)eps, (float)c1, (float)c2, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return ACM_OK;
+}
+
+acm_status acm_fno_to_bf16(int64_t n, const float* params, uint16_t* params_bf16, void* stream) {
+  g_err.clear();
+  if (n < 1 || !params || !params_bf16) return fail(ACM_E_INVALID, "bad arguments");
+  HIP_TRY(fno_to_bf16(params, params_bf16, n, (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  return ACM_OK;
+}
+
+acm_status acm_fno_mse(int64_t n, const float* out, const float* target, float* dout,
+                       double* loss, void* stream) {
+  g_err.clear();
+  if (n < 1 || !out || !target || !dout) return fail(ACM_E_INVALID, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  const int nb = 256;
+  DevBuf part;
+  HIP_TRY(hipMalloc(&part.p, sizeof(double) * nb));
+  HIP_TRY(fno_mse(out, target, dout, n, 1.0 / (double)n, (double*)part.p, nb, s));
+  std::vector<double> h(nb);
+  HIP_TRY(hipMemcpyAsync(h.data(), part.p, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  double t = 0.0;
+  for (double x : h) t += x;
+  if (loss) *loss = t;
+  return ACM_OK;
 }
 
 }  // extern "C"
