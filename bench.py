@@ -36,7 +36,111 @@ def parse():
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=12, help="oracle iterations in the CPU sample")
+    ap.add_argument("--fixed-iters", type=int, default=0,
+                    help="profiling aid: run exactly this many iterations per solve (eps = 0)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="profiling aid: only run a plain device copy of this many MiB, 10 times")
+    ap.add_argument("--no-transport", action="store_true", help="skip the 500-step transport run")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-cell batch comparison")
+    ap.add_argument("--transport-steps", type=int, default=500)
+    ap.add_argument("--batch-cells", type=int, default=64)
     return ap.parse_args()
+
+
+def transport_section(H, u_flow, log):
+    """Advection-diffusion on the same cell (Section 3.2): flow u(g = e_x)
+    scaled to unit pore-mean speed, Pe = 10, eta = 0.01, A0 = 0.55,
+    B0 = mean_Y(B), backward Euler dt = 2e-3 from chi = 0, per-step eps = 1e-6,
+    for g_chi = e_x, e_y, e_z; D* tensor and solute-mass drift."""
+    import torch
+    from paper_2312_15554_amd.api import acm_effective_props, acm_transport_step
+    args = parse()
+    pore = (H == 0)
+    ubar = torch.stack([(u_flow[c] * pore).sum() / pore.sum() for c in range(3)]).double()
+    un = (u_flow / ubar.norm().float()).contiguous()
+    Pe = 10.0
+    B0 = [Pe * float((un[c] * pore).sum()) / H.numel() for c in range(3)]
+    chis, out = [], dict(steps=args.transport_steps, dt=2e-3, Pe=Pe, B0=B0)
+    iters, secs = [], []
+    # Comparison medium: the smallest A0 of a ladder for which the first time
+    # step converges (Section 4.2: the best value is the smallest that converges).
+    from paper_2312_15554_amd import abi
+    A0 = None
+    for cand in [0.55 * 2 ** k for k in range(8)]:
+        try:
+            r = acm_transport_step(H, un, [1.0, 0.0, 0.0], Pe, eta=0.01, A0=cand, B0=B0, dt=2e-3,
+                                   n_steps=1, eps=1e-6, max_iter=2000)
+        except abi.AcmError as e:
+            log(f"transport A0={cand:g}: {e}")
+            continue
+        if r["stats"]["converged"]:
+            A0 = cand
+            break
+        log(f"transport A0={cand:g}: not converged in 2000 iterations")
+    if A0 is None:
+        raise RuntimeError("no comparison medium in the ladder converged")
+    out["A0"] = A0
+    log(f"transport: comparison medium A0 = {A0:g}")
+    for j in range(3):
+        g = [0.0, 0.0, 0.0]
+        g[j] = 1.0
+        chi = torch.zeros(H.shape, dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = acm_transport_step(H, un, g, Pe, eta=0.01, A0=A0, B0=B0, dt=2e-3,
+                               n_steps=args.transport_steps, eps=1e-6, max_iter=2000, chi=chi)
+        torch.cuda.synchronize()
+        secs.append(time.perf_counter() - t0)
+        iters.append(r["stats"]["iters"])
+        chis.append(chi)
+        log(f"transport g_chi=e{j}: {r['stats']['iters']} LS iterations, {secs[-1]:.2f} s, "
+            f"converged {r['stats']['converged']}")
+    p = acm_effective_props(H, [], chis, u_transport=un, Pe=Pe)
+    n = H.numel()
+    out.update(D=[[float(v) for v in row] for row in p["D"]],
+               mass=[float(m) for m in p["mass"]],
+               mass_drift_rel=[abs(float(p["mass"][j])) / (float(chis[j].abs().double().sum()) / n)
+                               for j in range(3)],
+               ls_iterations=iters, seconds=[round(x, 3) for x in secs],
+               voxel_iters_per_s=sum(iters) * n / sum(secs))
+    return out
+
+
+def batched_section(ncell, log):
+    """64 uneven cells: N from {32, 48, 64, 96, 128}, porosity U[0.3, 0.6]
+    (seeds 1000..), radius N/16, Stokes g = e_x, FP32, eps = 1e-6: one call per
+    cell (plain) against one batched call."""
+    import numpy as np
+    import torch
+    from paper_2312_15554_amd import inputs as I
+    from paper_2312_15554_amd.api import acm_stokes_solve, acm_stokes_solve_batched
+    sizes = [32, 48, 64, 96, 128]
+    Hs = []
+    for k in range(ncell):
+        rng = I.SplitMix64(1000 + k)
+        nn = sizes[min(4, int(rng.uniform() * 5))]
+        por = 0.3 + 0.3 * rng.uniform()
+        Hs.append(torch.from_numpy(I.overlapping_spheres(nn, nn / 16.0, por, seed=1000 + k)).cuda())
+    vox = [H.numel() for H in Hs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it_plain = []
+    for H in Hs:
+        r = acm_stokes_solve(H, (1.0, 0.0, 0.0), eps=1e-6, max_iter=200000, want_q=False)
+        it_plain.append(r["stats"]["iters"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rb = acm_stokes_solve_batched(Hs, [(1.0, 0.0, 0.0)] * ncell, eps=1e-6, max_iter=200000)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    it_b = [st["iters"] for st in rb["stats"]]
+    vi_p = sum(v * i for v, i in zip(vox, it_plain))
+    vi_b = sum(v * i for v, i in zip(vox, it_b))
+    log(f"batched: {ncell} cells, {sum(vox) / 1e6:.1f} M voxels: plain {t1 - t0:.2f} s, batched {t2 - t1:.2f} s")
+    return dict(cells=ncell, voxels=sum(vox), sizes=[H.shape[0] for H in Hs],
+                plain_seconds=round(t1 - t0, 3), batched_seconds=round(t2 - t1, 3),
+                plain_voxel_iters_per_s=vi_p / (t1 - t0), batched_voxel_iters_per_s=vi_b / (t2 - t1),
+                iterations_equal=it_plain == it_b, speedup=(t1 - t0) / (t2 - t1))
 
 
 def kernel_bytes(kind: str, n: int, d: int, nsolid: int, real_bytes: int = 4) -> float:
@@ -72,6 +176,15 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_probe_mib:
+        # a plain copy of known size: calibrates the HBM byte counters
+        a = torch.ones(args.copy_probe_mib * (1 << 18), dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": a.numel() * 4, "launches": 10}))
+        return
     n, d = args.n, 3
     H_np = I.overlapping_spheres(n, 8.0 * n / 128.0, 0.40, seed=1)
     nsolid = int(H_np.sum())
@@ -84,11 +197,15 @@ def main():
     def step():
         its, secs = [], []
         for g, u in zip(dirs, us):
-            r = acm_stokes_solve(H, g, penalty=pen, eps=args.eps, max_iter=200000, u=u,
-                                 want_q=False)
+            if args.fixed_iters:
+                r = acm_stokes_solve(H, g, penalty=pen, eps=0.0, max_iter=args.fixed_iters, u=u,
+                                     want_q=False)
+            else:
+                r = acm_stokes_solve(H, g, penalty=pen, eps=args.eps, max_iter=200000, u=u,
+                                     want_q=False)
             its.append(r["stats"]["iters"])
             secs.append(r["stats"]["seconds"])
-            if not r["stats"]["converged"]:
+            if not args.fixed_iters and not r["stats"]["converged"]:
                 raise RuntimeError(f"solve did not converge: {r['stats']}")
         K = acm_effective_props(H, us, nu=1.0)["K"]
         return its, secs, K
@@ -112,8 +229,8 @@ def main():
     its, secs, K = results[-1]
 
     # ---- roofline: profiled solve (eager launches, HIP events per kernel)
-    rp = acm_stokes_solve(H, dirs[0], penalty=pen, eps=args.eps, max_iter=200000, u=us[0],
-                          want_q=False, profile=True)
+    rp = acm_stokes_solve(H, dirs[0], penalty=pen, eps=0.0 if args.fixed_iters else args.eps,
+                          max_iter=args.fixed_iters or 200000, u=us[0], want_q=False, profile=True)
     km, kc = rp["stats"]["kernel_ms"], rp["stats"]["kernel_calls"]
     share = {k: km[k] for k in km if kc[k] > 0}
     dom = max(share, key=share.get)
@@ -141,6 +258,13 @@ def main():
                    sample=f"{args.cpu_iters} ADMM iterations of the FP64 oracle on the same "
                           f"{n}^3 cell, g = e_x ({tc1 - tc0:.1f} s; scipy.fft workers={threads})")
 
+    transport = None
+    if not args.no_transport and not args.fixed_iters:
+        transport = transport_section(H, us[0], log)
+    batched = None
+    if not args.no_batched and not args.fixed_iters:
+        batched = batched_section(args.batch_cells, log)
+
     out = {
         "metric": "voxel-iters/s & time-to-1e-6 residual: plain vs batched+FNO warm start",
         "value": total_vi / wall,
@@ -166,6 +290,8 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None},
         "cpu_baseline": cpu,
+        "transport": transport,
+        "batched": batched,
     }
     print(json.dumps(out))
 

@@ -170,6 +170,9 @@ acm_status acm_stokes_solve_batched(int32_t ncell, const acm_grid* grids, const 
  *   u    device flow field (dim components, as passed: no normalisation)
  *   chi  inout device scalar field: initial value on entry, result on exit.
  *   A0 > 0; B0: dim entries (host).
+ * The LS iteration contracts only for a large enough comparison medium A0
+ * (Section 3.2); ACM_E_DIVERGED is returned as soon as r_1 becomes non-finite
+ * or grows a millionfold over its smallest value within a time step.
  */
 acm_status acm_transport_step(const acm_grid* grid, const uint8_t* H, const void* u,
                               const double* g_chi, double Pe, double diffusivity, double eta,

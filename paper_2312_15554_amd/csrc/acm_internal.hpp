@@ -68,6 +68,7 @@ struct TransportCtl {
   double Pe, eta, diff;
   double calF;          // Pe * ubar . g  (multiplied by (1-H) per voxel)
   double r1, r2;
+  double r1_min;        // smallest r_1 of the current time step (divergence test)
   int64_t iter;         // iterations in the current time step
   int64_t total_iter;
   int64_t max_iter;

@@ -32,7 +32,9 @@ struct SlabCfg {
   static constexpr int P2 = XH + 1;  // row pitch in complex values (even: rows 16B-aligned)
   static constexpr int TPPY = Plan<NY>::TPP;
   static constexpr int TPPX = Plan<M>::TPP;
-  static constexpr int NT = 512;
+  // enough column groups to cover the XH columns in two rounds
+  static constexpr int NT0 = ((TPPY * ((XH + 1) / 2) + 63) / 64) * 64;
+  static constexpr int NT = NT0 < 64 ? 64 : (NT0 > 1024 ? 1024 : NT0);
   static constexpr int GY = NT / TPPY;  // column groups per round
   static constexpr int GX = NT / TPPX;  // row groups per round
   static constexpr int LDS_BYTES = NY * P2 * (int)sizeof(cplx<T>);
@@ -57,7 +59,7 @@ __device__ __forceinline__ void slab_cols(cplx<T>* lds, const cplx<T>* __restric
 }
 
 template <typename T, int NX, int NY>
-__global__ __launch_bounds__(512) void k_slab_local(
+__global__ __launch_bounds__((SlabCfg<T, NX, NY>::NT)) void k_slab_local(
     StokesCellArgs one, const StokesCellArgs* __restrict__ many, int ngreen, int64_t ntot,
     int64_t nspec, const cplx<T>* __restrict__ twx, const cplx<T>* __restrict__ twy,
     const cplx<T>* __restrict__ rtw) {
@@ -73,8 +75,8 @@ __global__ __launch_bounds__(512) void k_slab_local(
   double* hist = ca.hist;
   using V = typename Vec4<T>::type;
   extern __shared__ __align__(32) char smem_raw[];
-  __shared__ double red[4 * 8];
-  __shared__ double red7[7 * 8];
+  __shared__ double red[4 * 16];
+  __shared__ double red7[7 * 16];
   __shared__ int s_last;
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   T* ldsr = reinterpret_cast<T*>(smem_raw);
@@ -85,24 +87,8 @@ __global__ __launch_bounds__(512) void k_slab_local(
   const T ka = (T)(bb * al / (bb + al));
   const int z = blockIdx.x, field = blockIdx.y;
 
-  const cplx<T>* src = spec + field * nspec + (int64_t)z * NY * S::XH;
-  for (int v = threadIdx.x; v < NY * S::XH; v += S::NT) {
-    const int y = v / S::XH, k = v - y * S::XH;
-    lds[y * S::P2 + k] = src[v];
-  }
-  __syncthreads();
-  slab_cols<T, NX, NY, +1>(lds, twy);
-  {
-    const int grp = threadIdx.x / S::TPPX, t = threadIdx.x % S::TPPX;
-#pragma unroll 1
-    for (int r0 = 0; r0 < NY; r0 += S::GX) {
-      const int row = r0 + grp;
-      const bool act = grp < S::GX && row < NY;
-      rows_c2r_lds<T, S::M, 1, S::P2>(lds, 0, act ? row : 0, t, act, twx, rtw);
-    }
-  }
-
-  // Steps 2-3 on 4 consecutive voxels per quad; all loads issued up front.
+  // State loads first: they do not depend on the transforms, so their
+  // latency overlaps the spectral-slab load and both FFT phases.
   const int64_t off = field * ntot + (int64_t)z * S::NV;
   V* uq = reinterpret_cast<V*>(u + off);
   V* aq = reinterpret_cast<V*>(a + off);
@@ -124,6 +110,25 @@ __global__ __launch_bounds__(512) void k_slab_local(
     const int q = threadIdx.x + j * S::NT;
     if (hw[j]) ao[j] = aq[q];
   }
+
+  const cplx<T>* src = spec + field * nspec + (int64_t)z * NY * S::XH;
+  for (int v = threadIdx.x; v < NY * S::XH; v += S::NT) {
+    const int y = v / S::XH, k = v - y * S::XH;
+    lds[y * S::P2 + k] = src[v];
+  }
+  __syncthreads();
+  slab_cols<T, NX, NY, +1>(lds, twy);
+  {
+    const int grp = threadIdx.x / S::TPPX, t = threadIdx.x % S::TPPX;
+#pragma unroll 1
+    for (int r0 = 0; r0 < NY; r0 += S::GX) {
+      const int row = r0 + grp;
+      const bool act = grp < S::GX && row < NY;
+      rows_c2r_lds<T, S::M, 1, S::P2>(lds, 0, act ? row : 0, t, act, twx, rtw);
+    }
+  }
+
+  // Steps 2-3 on 4 consecutive voxels per quad.
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int j = 0; j < S::QPT; ++j) {
@@ -181,7 +186,7 @@ __global__ __launch_bounds__(512) void k_slab_local(
 }
 
 template <typename T, int NX, int NY>
-__global__ __launch_bounds__(512) void k_slab_rhs(StokesCellArgs one,
+__global__ __launch_bounds__((SlabCfg<T, NX, NY>::NT)) void k_slab_rhs(StokesCellArgs one,
                                                   const StokesCellArgs* __restrict__ many,
                                                   int64_t ntot, int64_t nspec,
                                                   const cplx<T>* __restrict__ twx,

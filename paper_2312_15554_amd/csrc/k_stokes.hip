@@ -62,6 +62,20 @@ __global__ __launch_bounds__((ColCfg<T, L, NC>::NT)) void k_stokes_green(
     if (f < P) v = spec[c * gg.nspec + (int64_t)i * P + f];
     lds[e] = v;
   }
+  // q-hat and the previous div-hat of this thread's modes, fetched before the
+  // forward transform so that their latency overlaps it
+  constexpr int MPT = (PS + C::NT - 1) / C::NT;
+  cplx<T> qpre[MPT], dpre[MPT];
+#pragma unroll
+  for (int r = 0; r < MPT; ++r) {
+    const int e = threadIdx.x + r * C::NT;
+    const int i = e / C::TX, col = e - i * C::TX;
+    const int f = f0 + col;
+    if (e < PS && f < P) {
+      qpre[r] = qhat[(int64_t)i * P + f];
+      dpre[r] = dhat[(int64_t)i * P + f];
+    }
+  }
   __syncthreads();
   const int t = threadIdx.x / C::TX, colt = threadIdx.x % C::TX;
   const bool act = t < C::TPP && f0 + colt < P;
@@ -70,7 +84,10 @@ __global__ __launch_bounds__((ColCfg<T, L, NC>::NT)) void k_stokes_green(
 
   double acc[3] = {0.0, 0.0, 0.0};
   const T inv_ntot = T(1.0 / (double)gg.ntot);
-  for (int e = threadIdx.x; e < PS; e += C::NT) {
+#pragma unroll
+  for (int r = 0; r < MPT; ++r) {
+    const int e = threadIdx.x + r * C::NT;
+    if (e >= PS) continue;
     const int i = e / C::TX, col = e - i * C::TX;
     const int f = f0 + col;
     if (f >= P) continue;
@@ -94,8 +111,8 @@ __global__ __launch_bounds__((ColCfg<T, L, NC>::NT)) void k_stokes_green(
     }
     const double w = (kx == 0 || 2 * kx == gg.nx) ? 1.0 : 2.0;
     const int64_t mi = (int64_t)i * P + f;
-    const cplx<T> q = qhat[mi];
-    const cplx<T> dp = dhat[mi];
+    const cplx<T> q = qpre[r];
+    const cplx<T> dp = dpre[r];
     cplx<T> R[NC];
     const bool k0 = (kx == 0 && ky == 0 && kz == 0);
 #pragma unroll

@@ -169,7 +169,10 @@ __global__ __launch_bounds__((ColCfg<T, L, D + 1>::NT)) void k_transport_green(
         const int64_t it = ctl->iter + 1;
         ctl->iter = it;
         ctl->total_iter += 1;
-        if (!isfinite(r1) || !isfinite(r2)) {
+        // divergence: non-finite, or r_1 grown a millionfold over its minimum
+        // (the LS iteration contracts only for a large enough comparison medium)
+        if (r1 < ctl->r1_min) ctl->r1_min = r1;
+        if (!isfinite(r1) || !isfinite(r2) || (it > 5 && r1 > 1e6 * ctl->r1_min)) {
           ctl->done = 1;
           ctl->status = -5;
         } else if (r1 <= ctl->sqrt_n1 * ctl->eps && r2 <= ctl->sqrt_n2 * ctl->eps) {

@@ -45,7 +45,7 @@ struct RowCfgN {
 };
 
 // Turn half spectra X[0..M] of row `row` of NF fields into real rows x[0..2M)
-// in place (the row then reads as T[2M]).  The inverse is unnormalised along
+// in place (imaginary parts of X[0] and X[M] are ignored) (the row then reads as T[2M]).  The inverse is unnormalised along
 // x, so the real row equals nx * (inverse DFT of X).  Ends with a barrier.
 template <typename T, int M, int NF = 1, int RP = M + 1>
 __device__ __forceinline__ void rows_c2r_lds(cplx<T>* lds, int fstride, int row, int t,
@@ -59,10 +59,10 @@ __device__ __forceinline__ void rows_c2r_lds(cplx<T>* lds, int fstride, int row,
       for (int fi = 0; fi < NF; ++fi) {
         cplx<T>* r = lds + fi * fstride + row * RP;
         if (k == 0) {
-          cplx<T> x0 = r[0], xm = r[M];
-          cplx<T> S = cadd(x0, cconj(xm));
-          cplx<T> D = csub(x0, cconj(xm));
-          r[0] = cmake<T>(S.x - D.y, S.y + D.x);
+          // DC and Nyquist bins of a real row are real: their imaginary parts
+          // are ignored (the usual inverse real transform)
+          const T x0 = r[0].x, xm = r[M].x;
+          r[0] = cmake<T>(x0 + xm, x0 - xm);
         } else if (2 * k == M) {
           r[k] = cscale(cconj(r[k]), T(2));
         } else {

@@ -853,6 +853,7 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
     if (!steady) HIP_TRY(hipMemcpyAsync(chat_m, chat, one_b, hipMemcpyDeviceToDevice, s));
     c.iter = 0;
     c.total_iter = total;
+    c.r1_min = INFINITY;
     c.done = 0;
     c.status = 1;
     c.counter = 0;

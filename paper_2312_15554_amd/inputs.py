@@ -37,8 +37,9 @@ class SplitMix64:
         return (self.next_u64() >> 11) * (1.0 / (1 << 53))
 
 
-def _stamp_ball(H: np.ndarray, centre, radius: float) -> None:
-    """Mark voxels whose centre is within `radius` (unit-cell units) of `centre`.
+def _stamp_ball(H: np.ndarray, centre, radius: float) -> int:
+    """Mark voxels whose centre is within `radius` (unit-cell units) of `centre`;
+    returns how many voxels became solid.
 
     H has numpy axis order [z][y][x] (3D) or [y][x] (2D); `centre` is given
     in (x, y[, z]) order.
@@ -66,8 +67,10 @@ def _stamp_ball(H: np.ndarray, centre, radius: float) -> None:
     inside = d2 <= radius * radius + 1e-15
     sel = np.ix_(*[by_ax[a][0] for a in range(nd)])
     sub = H[sel]
+    added = int(np.count_nonzero(inside & (sub == 0)))
     sub[inside] = 1
     H[sel] = sub
+    return added
 
 
 def centred_disc(n: int, radius: float = 0.2) -> np.ndarray:
@@ -106,8 +109,7 @@ def overlapping_spheres(n, radius_vox: float, porosity: float, seed: int,
     solid = 0
     for _ in range(max_spheres):
         centre = tuple(rng.uniform() for _ in range(nd))
-        _stamp_ball(H, centre, r)
-        solid = int(H.sum(dtype=np.int64))
+        solid += _stamp_ball(H, centre, r)
         if 1.0 - solid / total <= porosity:
             break
     return H
