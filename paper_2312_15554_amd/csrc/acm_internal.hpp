@@ -87,7 +87,8 @@ struct StokesCellArgs {
   void* u;             // real [d][ntot]
   void* a;             // real [d][ntot]
   const uint8_t* H;    // uint8 [ntot]
-  double* part;        // green partials [3*ngreen] then local partials [4*nlocal]
+  double* part;        // green partials [3*ngreen]
+  double* lpart;       // local partials [4*nlocal]
   StokesCtl* ctl;
   double* hist;        // may be null
 };
@@ -142,9 +143,12 @@ hipError_t launch_cols_batched(const Geom& g, const DevTables<T>& tb, int axis, 
 
 // Stokes ADMM passes.  `one` is used when `many` is null (single cell);
 // otherwise cell i = blockIdx.z reads many[i] and ncells cells are launched.
+// `variant` (0, 1, 2) picks the tile width (see ColCfg); *nblocks receives
+// the number of workgroups per cell (= partial-sum records written).
 template <typename T>
 hipError_t launch_stokes_green(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
-                               const StokesCellArgs* many, int ncells, hipStream_t s);
+                               const StokesCellArgs* many, int ncells, int variant, int* nblocks,
+                               hipStream_t s);
 template <typename T>
 hipError_t launch_stokes_local(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
                                const StokesCellArgs* many, int ncells, int green_blocks,
@@ -223,7 +227,7 @@ hipError_t fno_mse(const float* out, const float* tgt, float* dout, int64_t n, d
                    double* part, int nblk, hipStream_t s);
 
 // Grid-size helpers used by the host to size partial-sum buffers.
-int stokes_green_blocks(const Geom& g, int precision_bytes);
+int stokes_green_blocks(const Geom& g, int precision_bytes, int variant);
 int stokes_local_blocks(const Geom& g, int precision_bytes);
 
 }  // namespace acm

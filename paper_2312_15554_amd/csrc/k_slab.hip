@@ -70,7 +70,7 @@ __global__ __launch_bounds__((SlabCfg<T, NX, NY>::NT)) void k_slab_local(
   T* __restrict__ a = reinterpret_cast<T*>(ca.a);
   const uint8_t* __restrict__ H = ca.H;
   const double* __restrict__ gpart = ca.part;
-  double* __restrict__ lpart = ca.part + 3 * (int64_t)ngreen;
+  double* __restrict__ lpart = ca.lpart;
   StokesCtl* ctl = ca.ctl;
   double* hist = ca.hist;
   using V = typename Vec4<T>::type;

@@ -30,13 +30,13 @@ struct GreenGeom {
   int64_t ntot;
 };
 
-template <typename T, int L, int NC>
-__global__ __launch_bounds__((ColCfg<T, L, NC>::NT)) void k_stokes_green(
+template <typename T, int L, int NC, int VAR>
+__global__ __launch_bounds__((ColCfg<T, L, NC, VAR>::NT)) void k_stokes_green(
     StokesCellArgs one, const StokesCellArgs* __restrict__ many, GreenGeom gg,
     const cplx<T>* __restrict__ tw, const T* __restrict__ sx, const T* __restrict__ lx,
     const T* __restrict__ sy, const T* __restrict__ ly, const T* __restrict__ sz,
     const T* __restrict__ lz) {
-  using C = ColCfg<T, L, NC>;
+  using C = ColCfg<T, L, NC, VAR>;
   const StokesCellArgs ca = many ? many[blockIdx.z] : one;
   cplx<T>* __restrict__ spec = reinterpret_cast<cplx<T>*>(ca.spec);
   cplx<T>* __restrict__ qhat = reinterpret_cast<cplx<T>*>(ca.qhat);
@@ -52,7 +52,8 @@ __global__ __launch_bounds__((ColCfg<T, L, NC>::NT)) void k_stokes_green(
   const T bpen = (T)ctl->psi[2];
   const T nu = (T)ctl->nu;
   const int P = gg.plane;
-  const int f0 = blockIdx.x * C::TX;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int f0 = tile * C::TX;
 
   for (int e = threadIdx.x; e < NC * PS; e += C::NT) {
     const int c = e / PS, rem = e - c * PS;
@@ -163,9 +164,9 @@ __global__ __launch_bounds__((ColCfg<T, L, NC>::NT)) void k_stokes_green(
   }
   block_sum<3>(acc, red);
   if (threadIdx.x == 0) {
-    partials[blockIdx.x * 3 + 0] = acc[0];
-    partials[blockIdx.x * 3 + 1] = acc[1];
-    partials[blockIdx.x * 3 + 2] = acc[2];
+    partials[tile * 3 + 0] = acc[0];
+    partials[tile * 3 + 1] = acc[1];
+    partials[tile * 3 + 2] = acc[2];
   }
 }
 
@@ -180,7 +181,7 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_stokes_local(
   T* __restrict__ a = reinterpret_cast<T*>(ca.a);
   const uint8_t* __restrict__ H = ca.H;
   const double* __restrict__ gpart = ca.part;
-  double* __restrict__ lpart = ca.part + 3 * (int64_t)ngreen;
+  double* __restrict__ lpart = ca.lpart;
   StokesCtl* ctl = ca.ctl;
   double* hist = ca.hist;
   constexpr int NX = 2 * M;
@@ -281,17 +282,26 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_stokes_rhs(
 }
 
 // ------------------------------------------------------------------ launchers
-template <int L, typename T>
+template <int L, typename T, int VAR>
 static int green_blocks_for(const Geom& g) {
-  if (g.dim == 3) return (int)((g.plane + ColCfg<T, L, 3>::TX - 1) / ColCfg<T, L, 3>::TX);
-  return (int)((g.plane + ColCfg<T, L, 2>::TX - 1) / ColCfg<T, L, 2>::TX);
+  if (g.dim == 3)
+    return (int)((g.plane + ColCfg<T, L, 3, VAR>::TX - 1) / ColCfg<T, L, 3, VAR>::TX);
+  return (int)((g.plane + ColCfg<T, L, 2, VAR>::TX - 1) / ColCfg<T, L, 2, VAR>::TX);
 }
 
-int stokes_green_blocks(const Geom& g, int prec_bytes) {
+template <int L, typename T>
+static int green_blocks_var(const Geom& g, int variant) {
+  if (variant == 1) return green_blocks_for<L, T, 1>(g);
+  if (variant == 2) return green_blocks_for<L, T, 2>(g);
+  return green_blocks_for<L, T, 0>(g);
+}
+
+int stokes_green_blocks(const Geom& g, int prec_bytes, int variant) {
   switch (g.last_n) {
-#define CASE(LL) \
-  case LL:       \
-    return prec_bytes == 8 ? green_blocks_for<LL, double>(g) : green_blocks_for<LL, float>(g);
+#define CASE(LL)                                                                                \
+  case LL:                                                                                      \
+    return prec_bytes == 8 ? green_blocks_var<LL, double>(g, variant)                           \
+                           : green_blocks_var<LL, float>(g, variant);
     ACM_COL_LENGTHS(CASE)
 #undef CASE
     default:
@@ -313,33 +323,41 @@ int stokes_local_blocks(const Geom& g, int prec_bytes) {
   }
 }
 
-template <typename T>
-hipError_t launch_stokes_green(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
-                               const StokesCellArgs* many, int ncells, hipStream_t s) {
+template <typename T, int LL, int NC, int VAR>
+static hipError_t green_launch(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
+                               const StokesCellArgs* many, int ncells, int* nblocks,
+                               hipStream_t s) {
+  using C = ColCfg<T, LL, NC, VAR>;
   const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
   const T* rt = tb.rtab;
   GreenGeom gg{g.dim, g.nx, g.xh, (int)g.plane, g.nspec, g.ntot};
   const cplx<T>* tw = ct + (g.dim == 3 ? tb.off.tw_z : tb.off.tw_y);
-  const T* szp = rt + tb.off.sz;
-  const T* lzp = rt + tb.off.lz;
+  const int nb = (int)((g.plane + C::TX - 1) / C::TX);
+  if (nblocks) *nblocks = nb;
+  hipLaunchKernelGGL((k_stokes_green<T, LL, NC, VAR>), dim3(nb, 1, ncells), dim3(C::NT),
+                     C::LDS_BYTES, s, one, many, gg, tw, rt + tb.off.sx, rt + tb.off.lx,
+                     rt + tb.off.sy, rt + tb.off.ly, rt + tb.off.sz, rt + tb.off.lz);
+  return hipGetLastError();
+}
+
+template <typename T, int LL, int NC>
+static hipError_t green_var(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
+                            const StokesCellArgs* many, int ncells, int variant, int* nblocks,
+                            hipStream_t s) {
+  if (variant == 1) return green_launch<T, LL, NC, 1>(g, tb, one, many, ncells, nblocks, s);
+  if (variant == 2) return green_launch<T, LL, NC, 2>(g, tb, one, many, ncells, nblocks, s);
+  return green_launch<T, LL, NC, 0>(g, tb, one, many, ncells, nblocks, s);
+}
+
+template <typename T>
+hipError_t launch_stokes_green(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
+                               const StokesCellArgs* many, int ncells, int variant, int* nblocks,
+                               hipStream_t s) {
   switch (g.last_n) {
-#define CASE(LL)                                                                              \
-  case LL: {                                                                                  \
-    if (g.dim == 3) {                                                                         \
-      using C = ColCfg<T, LL, 3>;                                                             \
-      const int nb = (int)((g.plane + C::TX - 1) / C::TX);                                    \
-      hipLaunchKernelGGL((k_stokes_green<T, LL, 3>), dim3(nb, 1, ncells), dim3(C::NT),         \
-                         C::LDS_BYTES, s, one, many, gg, tw, rt + tb.off.sx, rt + tb.off.lx,   \
-                         rt + tb.off.sy, rt + tb.off.ly, szp, lzp);                           \
-    } else {                                                                                  \
-      using C = ColCfg<T, LL, 2>;                                                             \
-      const int nb = (int)((g.plane + C::TX - 1) / C::TX);                                    \
-      hipLaunchKernelGGL((k_stokes_green<T, LL, 2>), dim3(nb, 1, ncells), dim3(C::NT),         \
-                         C::LDS_BYTES, s, one, many, gg, tw, rt + tb.off.sx, rt + tb.off.lx,   \
-                         rt + tb.off.sy, rt + tb.off.ly, szp, lzp);                           \
-    }                                                                                         \
-    return hipGetLastError();                                                                 \
-  }
+#define CASE(LL)                                                                     \
+  case LL:                                                                           \
+    if (g.dim == 3) return green_var<T, LL, 3>(g, tb, one, many, ncells, variant, nblocks, s); \
+    return green_var<T, LL, 2>(g, tb, one, many, ncells, variant, nblocks, s);
     ACM_COL_LENGTHS(CASE)
 #undef CASE
     default:
@@ -392,7 +410,7 @@ hipError_t launch_stokes_rhs(const Geom& g, const DevTables<T>& tb, const Stokes
 #define INST(T)                                                                                \
   template hipError_t launch_stokes_green<T>(const Geom&, const DevTables<T>&,                 \
                                              const StokesCellArgs&, const StokesCellArgs*, int, \
-                                             hipStream_t);                                     \
+                                             int, int*, hipStream_t);                          \
   template hipError_t launch_stokes_local<T>(const Geom&, const DevTables<T>&,                 \
                                              const StokesCellArgs&, const StokesCellArgs*, int, \
                                              int, hipStream_t);                                \

@@ -128,15 +128,27 @@ struct ColMap {
   int ncols;
 };
 
+// Block -> tile map that keeps runs of consecutive tiles on one XCD (blocks
+// are dealt to the 8 XCDs round-robin): neighbouring tiles then share an L2.
+__device__ __forceinline__ int xcd_tile(int bid, int nb) {
+  const int full = (nb / 8) * 8;
+  if (bid >= full) return bid;
+  return (bid % 8) * (nb / 8) + bid / 8;
+}
+
 __device__ __forceinline__ int col_base(const ColMap& m, int f) {
   return (f / m.inner) * m.outer + (f % m.inner);
 }
 
-template <typename T, int L, int NCOMP>
+// VAR selects the tile width for the autotuner: 0 = default (about 256
+// threads), 1 = half of it, 2 = twice it (each capped by LDS).
+template <typename T, int L, int NCOMP, int VAR = 0>
 struct ColCfg {
   static constexpr int TPP = Plan<L>::TPP;
-  static constexpr int TX_THREADS = cmax(1, 256 / TPP);
-  static constexpr int TX_LDS = cmax(1, (56 * 1024) / (NCOMP * L * (int)sizeof(cplx<T>)));
+  static constexpr int TX_BASE = cmax(1, 256 / TPP);
+  static constexpr int TX_THREADS = cmax(1, VAR == 1 ? TX_BASE / 2
+                                            : (VAR == 2 ? cmin(TX_BASE * 2, 1024 / TPP) : TX_BASE));
+  static constexpr int TX_LDS = cmax(1, ((VAR == 2 ? 100 : 56) * 1024) / (NCOMP * L * (int)sizeof(cplx<T>)));
   static constexpr int TX = cmin(TX_THREADS, TX_LDS);
   // block size padded to whole wavefronts; threads with t >= TPP stay idle
   static constexpr int NT = ((TPP * TX + 63) / 64) * 64;

@@ -5,6 +5,8 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <stdlib.h>
+
 #include <chrono>
 #include <map>
 #include <memory>
@@ -43,8 +45,9 @@ struct CellPlan {
   void* ctab = nullptr;
   void* rtab = nullptr;
   TableOffsets off{};
-  int green_blocks = 0;
+  int green_blocks = 0;  // largest green-pass grid over the tile variants
   int local_blocks = 0;
+  int green_var = -1;    // tile variant picked by the autotuner (-1: not yet)
   ~CellPlan() {
     if (ctab) (void)hipFree(ctab);
     if (rtab) (void)hipFree(rtab);
@@ -173,7 +176,8 @@ static acm_status get_plan(const acm_grid* grid, int precision, CellPlan** out) 
     if (e == hipSuccess) e = upload<float>(r, &p->rtab);
   }
   if (e != hipSuccess) return fail(ACM_E_HIP, std::string("table upload: ") + hipGetErrorString(e));
-  p->green_blocks = stokes_green_blocks(g, p->prec);
+  p->green_blocks = 0;
+  for (int v = 0; v < 3; ++v) p->green_blocks = std::max(p->green_blocks, stokes_green_blocks(g, p->prec, v));
   p->local_blocks = stokes_local_blocks(g, p->prec);
   *out = p.get();
   g_plans[key] = std::move(p);
@@ -284,7 +288,10 @@ struct StokesGroup {
   CellPlan* pl = nullptr;
   std::vector<int> cells;  // indices into the call's cell list
   bool slab = false;
-  int ngreen = 0, nlocal = 0;
+  int green_var = 0;     // tile variant of the green pass
+  int ngreen = 0;        // green workgroups per cell for that variant
+  int ngreen_max = 0;    // partial-buffer capacity (largest variant)
+  int nlocal = 0;
   size_t spec_b = 0, one_b = 0, a_b = 0, part_b = 0, cell_b = 0;
   DevBuf ws;
   DevBuf dargs_buf, dcols_buf;
@@ -314,7 +321,7 @@ static hipError_t enqueue_iteration(StokesGroup<T>& G, hipStream_t s, Profiler* 
     return r;
   };
   prof->begin(KK_GREEN, &ev0);
-  e = launch_stokes_green<T>(g, tb, one, many, n, s);
+  e = launch_stokes_green<T>(g, tb, one, many, n, G.green_var, nullptr, s);
   if (e != hipSuccess) return e;
   prof->end(KK_GREEN, ev0);
   if (G.slab) {
@@ -379,7 +386,9 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
     G.spec_b = cb * (size_t)g.nspec * d;
     G.one_b = cb * (size_t)g.nspec;
     G.a_b = sizeof(T) * (size_t)g.ntot * d;
-    G.ngreen = G.pl->green_blocks;
+    G.ngreen_max = G.pl->green_blocks;
+    G.green_var = G.pl->green_var >= 0 ? G.pl->green_var : 0;
+    G.ngreen = stokes_green_blocks(g, G.pl->prec, G.green_var);
     bool aligned = true;
     for (int i : G.cells)
       aligned = aligned && ((uintptr_t)cells[i].u % 32 == 0) && ((uintptr_t)cells[i].H % 16 == 0);
@@ -392,7 +401,7 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
       G.slab = slab_supported<T>(g) && aligned;
     }
     G.nlocal = std::max(G.pl->local_blocks, slab_local_blocks<T>(g));
-    G.part_b = sizeof(double) * (size_t)(3 * G.ngreen + 4 * G.nlocal);
+    G.part_b = sizeof(double) * (size_t)(3 * G.ngreen_max + 4 * G.nlocal);
     G.cell_b = al256(G.spec_b) + 2 * al256(G.one_b) + al256(G.a_b) + al256(G.part_b);
     HIP_TRY(hipMalloc(&G.ws.p, G.cell_b * G.cells.size()));
     for (size_t k = 0; k < G.cells.size(); ++k) {
@@ -404,6 +413,7 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
       A.dhat = (char*)A.qhat + al256(G.one_b);
       A.a = (char*)A.dhat + al256(G.one_b);
       A.part = (double*)((char*)A.a + al256(G.a_b));
+      A.lpart = A.part + 3 * (size_t)G.ngreen_max;
       A.u = cells[i].u;
       A.H = cells[i].H;
       A.ctl = dctl + i;
@@ -517,6 +527,83 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
       if (p) (void)hipHostFree(p);
     }
   } hf{hctl};
+
+  // ---- tile-width autotuning of the green pass: the first iterations of the
+  // first solve of a plan run eagerly, one variant at a time, with HIP events
+  // around the green launch; the fastest variant is kept for this plan.  Every
+  // variant computes the same values (only the number of pencils per
+  // workgroup changes), so the iterates do not depend on the choice.
+  {
+    const char* force = getenv("ACM_GREEN_VARIANT");
+    for (auto& Gp : groups) {
+      StokesGroup<T>& G = *Gp;
+      const Geom& g = G.pl->g;
+      if (force) {
+        G.green_var = std::max(0, std::min(2, atoi(force)));
+      } else if (G.pl->green_var < 0 && g.ntot >= (int64_t)64 * 64 * 64 && o.max_iter >= 64) {
+        DevTables<T> tb = tables_of<T>(G.pl);
+        const int n = (int)G.cells.size();
+        float best = 1e30f;
+        int bestv = 0;
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        for (int v = 0; v < 3; ++v) {
+          G.green_var = v;
+          G.ngreen = stokes_green_blocks(g, G.pl->prec, v);
+          float tot = 0.f;
+          for (int rep = 0; rep < 3; ++rep) {
+            Profiler off;
+            hipError_t e = hipEventRecord(e0, s);
+            if (e == hipSuccess)
+              e = launch_stokes_green<T>(g, tb, G.hargs[0], n > 1 ? G.dargs() : nullptr, n, v, nullptr, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            // finish the iteration with the same variant (the local pass reads
+            // the green partials of this variant)
+            if (e == hipSuccess) {
+              StokesGroup<T>* gp = &G;
+              const bool slab = gp->slab;
+              StokesCellArgs one = G.hargs[0];
+              const StokesCellArgs* many = n > 1 ? G.dargs() : nullptr;
+              if (slab) {
+                e = launch_slab_local<T>(g, tb, one, many, n, G.ngreen, s);
+                if (e == hipSuccess) e = launch_slab_rhs<T>(g, tb, one, many, n, s);
+              } else {
+                if (g.dim == 3)
+                  e = n > 1 ? launch_cols_batched<T>(g, tb, 1, +1, g.dim, G.dcols(), n, s)
+                            : launch_cols<T>(g, tb, 1, +1, g.dim, one.spec, s, &one.ctl->done);
+                if (e == hipSuccess) e = launch_stokes_local<T>(g, tb, one, many, n, G.ngreen, s);
+                if (e == hipSuccess) e = launch_stokes_rhs<T>(g, tb, one, many, n, s);
+                if (e == hipSuccess && g.dim == 3)
+                  e = n > 1 ? launch_cols_batched<T>(g, tb, 1, -1, g.dim, G.dcols(), n, s)
+                            : launch_cols<T>(g, tb, 1, -1, g.dim, one.spec, s, &one.ctl->done);
+              }
+            }
+            if (e != hipSuccess) {
+              (void)hipEventDestroy(e0);
+              (void)hipEventDestroy(e1);
+              return fail(ACM_E_HIP, std::string("autotune: ") + hipGetErrorString(e));
+            }
+            if (rep > 0) tot += ms;  // the first launch of a variant warms caches
+          }
+          if (tot < best) {
+            best = tot;
+            bestv = v;
+          }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        G.pl->green_var = bestv;
+        G.green_var = bestv;
+      } else if (G.pl->green_var >= 0) {
+        G.green_var = G.pl->green_var;
+      }
+      G.ngreen = stokes_green_blocks(g, G.pl->prec, G.green_var);
+    }
+  }
 
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
