@@ -43,6 +43,10 @@ def parse():
     ap.add_argument("--no-transport", action="store_true", help="skip the 500-step transport run")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-cell batch comparison")
     ap.add_argument("--transport-steps", type=int, default=500)
+    ap.add_argument("--fno", action="store_true", help="train the FNO warm start and compare solves")
+    ap.add_argument("--fno-train", type=int, default=256, help="64^3 training solves")
+    ap.add_argument("--fno-epochs", type=int, default=6)
+    ap.add_argument("--fno-test", type=int, default=2, help="256^3 test cells")
     ap.add_argument("--batch-cells", type=int, default=64)
     return ap.parse_args()
 
@@ -104,6 +108,35 @@ def transport_section(H, u_flow, log):
                ls_iterations=iters, seconds=[round(x, 3) for x in secs],
                voxel_iters_per_s=sum(iters) * n / sum(secs))
     return out
+
+
+def fno_section(args, log):
+    """FNO warm start: train on method-generated 64^3 solves (r = 4 voxels,
+    porosity U[0.35, 0.50], seeds 10000..), apply to 256^3 cells (r = 16,
+    seeds 20000..) and compare plain vs warm-started ADMM to the same eps."""
+    import torch
+    from paper_2312_15554_amd import warmstart as W
+    from paper_2312_15554_amd.fno import FNO
+    cells = W.make_cells(64, args.fno_train, 10000, 4.0, 0.35, 0.50)
+    H, Y, info = W.generate_dataset(cells, eps=1e-6, log=log)
+    norm = W.Normaliser(Y)
+    net = FNO(channels=32, hidden=128, modes=12, layers=4, seed=0)
+    ntr = max(1, int(0.9 * len(cells)))
+    tr = W.train(net, H[:ntr], norm.encode(Y[:ntr]), epochs=args.fno_epochs, batch=8, lr=2e-3,
+                 lr_final=2e-4, log=log)
+    err_hold = W.relative_error(net, norm, H[ntr:], Y[ntr:]) if ntr < len(cells) else None
+    del H, Y
+    torch.cuda.empty_cache()
+    tests = []
+    for i, c in enumerate(W.make_cells(256, args.fno_test, 20000, 16.0, 0.35, 0.50)):
+        r = W.solve_plain_and_warm(net, norm, torch.from_numpy(c).cuda(), eps=1e-6)
+        log(f"fno test cell {i}: {r}")
+        tests.append(r)
+    return dict(train_cells=len(cells), data_seconds=round(info["seconds"], 2),
+                train_seconds=round(tr["seconds"], 2), train_steps=tr["steps"],
+                final_loss=tr["loss"][-1], holdout_rel_err=err_hold, tests=tests,
+                iters_saved=[t["plain_iters"] - t["warm_iters"] for t in tests],
+                time_ratio_warm_over_plain=[t["warm_s"] / t["plain_s"] for t in tests])
 
 
 def batched_section(ncell, log):
@@ -265,6 +298,8 @@ def main():
     if not args.no_batched and not args.fixed_iters:
         batched = batched_section(args.batch_cells, log)
 
+    fno = fno_section(args, log) if args.fno and not args.fixed_iters else None
+
     out = {
         "metric": "voxel-iters/s & time-to-1e-6 residual: plain vs batched+FNO warm start",
         "value": total_vi / wall,
@@ -292,6 +327,7 @@ def main():
         "cpu_baseline": cpu,
         "transport": transport,
         "batched": batched,
+        "fno_warm_start": fno,
     }
     print(json.dumps(out))
 

@@ -553,7 +553,6 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
           G.ngreen = stokes_green_blocks(g, G.pl->prec, v);
           float tot = 0.f;
           for (int rep = 0; rep < 3; ++rep) {
-            Profiler off;
             hipError_t e = hipEventRecord(e0, s);
             if (e == hipSuccess)
               e = launch_stokes_green<T>(g, tb, G.hargs[0], n > 1 ? G.dargs() : nullptr, n, v, nullptr, s);
@@ -564,8 +563,7 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
             // finish the iteration with the same variant (the local pass reads
             // the green partials of this variant)
             if (e == hipSuccess) {
-              StokesGroup<T>* gp = &G;
-              const bool slab = gp->slab;
+              const bool slab = G.slab;
               StokesCellArgs one = G.hargs[0];
               const StokesCellArgs* many = n > 1 ? G.dargs() : nullptr;
               if (slab) {
