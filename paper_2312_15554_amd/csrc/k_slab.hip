@@ -93,7 +93,9 @@ __global__ __launch_bounds__((SlabCfg<T, NX, NY>::NT)) void k_slab_local(
   V* uq = reinterpret_cast<V*>(u + off);
   V* aq = reinterpret_cast<V*>(a + off);
   const uint32_t* hq = reinterpret_cast<const uint32_t*>(H + (int64_t)z * S::NV);
-  V up[S::QPT];
+  // a is exactly zero in the pore (it is only ever written in the solid), so
+  // it is loaded unconditionally: no load waits on the value of H.
+  V up[S::QPT], ao[S::QPT];
   uint32_t hw[S::QPT];
 #pragma unroll
   for (int j = 0; j < S::QPT; ++j) {
@@ -102,13 +104,8 @@ __global__ __launch_bounds__((SlabCfg<T, NX, NY>::NT)) void k_slab_local(
     if (S::FULL || q < S::NQ) {
       up[j] = uq[q];
       hw[j] = hq[q];
+      ao[j] = aq[q];
     }
-  }
-  V ao[S::QPT];
-#pragma unroll
-  for (int j = 0; j < S::QPT; ++j) {
-    const int q = threadIdx.x + j * S::NT;
-    if (hw[j]) ao[j] = aq[q];
   }
 
   const cplx<T>* src = spec + field * nspec + (int64_t)z * NY * S::XH;
@@ -211,7 +208,9 @@ __global__ __launch_bounds__((SlabCfg<T, NX, NY>::NT)) void k_slab_rhs(StokesCel
   const V* uq = reinterpret_cast<const V*>(u + off);
   const V* aq = reinterpret_cast<const V*>(a + off);
   const uint32_t* hq = reinterpret_cast<const uint32_t*>(H + (int64_t)z * S::NV);
-  V uv[S::QPT];
+  // a vanishes in the pore, so r = (H ? b c : b) u - a needs no branch on H
+  // and every load is issued at once.
+  V uv[S::QPT], av[S::QPT];
   uint32_t hw[S::QPT];
 #pragma unroll
   for (int j = 0; j < S::QPT; ++j) {
@@ -220,13 +219,8 @@ __global__ __launch_bounds__((SlabCfg<T, NX, NY>::NT)) void k_slab_rhs(StokesCel
     if (S::FULL || q < S::NQ) {
       uv[j] = uq[q];
       hw[j] = hq[q];
+      av[j] = aq[q];
     }
-  }
-  V av[S::QPT];
-#pragma unroll
-  for (int j = 0; j < S::QPT; ++j) {
-    const int q = threadIdx.x + j * S::NT;
-    if (hw[j]) av[j] = aq[q];
   }
 #pragma unroll
   for (int j = 0; j < S::QPT; ++j) {
@@ -235,17 +229,10 @@ __global__ __launch_bounds__((SlabCfg<T, NX, NY>::NT)) void k_slab_rhs(StokesCel
     const int v = 4 * q;
     const int y = v / NX, x = v - y * NX;
     V r;
-    if (hw[j]) {
-      r.x = (hw[j] & 0xffu) ? bcp * uv[j].x - av[j].x : bb * uv[j].x;
-      r.y = (hw[j] & 0xff00u) ? bcp * uv[j].y - av[j].y : bb * uv[j].y;
-      r.z = (hw[j] & 0xff0000u) ? bcp * uv[j].z - av[j].z : bb * uv[j].z;
-      r.w = (hw[j] & 0xff000000u) ? bcp * uv[j].w - av[j].w : bb * uv[j].w;
-    } else {
-      r.x = bb * uv[j].x;
-      r.y = bb * uv[j].y;
-      r.z = bb * uv[j].z;
-      r.w = bb * uv[j].w;
-    }
+    r.x = ((hw[j] & 0xffu) ? bcp : bb) * uv[j].x - av[j].x;
+    r.y = ((hw[j] & 0xff00u) ? bcp : bb) * uv[j].y - av[j].y;
+    r.z = ((hw[j] & 0xff0000u) ? bcp : bb) * uv[j].z - av[j].z;
+    r.w = ((hw[j] & 0xff000000u) ? bcp : bb) * uv[j].w - av[j].w;
     *reinterpret_cast<V*>(ldsr + y * 2 * S::P2 + x) = r;
   }
   __syncthreads();

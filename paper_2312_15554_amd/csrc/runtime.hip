@@ -541,54 +541,30 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
       if (force) {
         G.green_var = std::max(0, std::min(2, atoi(force)));
       } else if (G.pl->green_var < 0 && g.ntot >= (int64_t)64 * 64 * 64 && o.max_iter >= 64) {
-        DevTables<T> tb = tables_of<T>(G.pl);
-        const int n = (int)G.cells.size();
         float best = 1e30f;
         int bestv = 0;
         hipEvent_t e0, e1;
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
+        Profiler off;
         for (int v = 0; v < 3; ++v) {
           G.green_var = v;
           G.ngreen = stokes_green_blocks(g, G.pl->prec, v);
-          float tot = 0.f;
-          for (int rep = 0; rep < 3; ++rep) {
-            hipError_t e = hipEventRecord(e0, s);
-            if (e == hipSuccess)
-              e = launch_stokes_green<T>(g, tb, G.hargs[0], n > 1 ? G.dargs() : nullptr, n, v, nullptr, s);
-            if (e == hipSuccess) e = hipEventRecord(e1, s);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            // finish the iteration with the same variant (the local pass reads
-            // the green partials of this variant)
-            if (e == hipSuccess) {
-              const bool slab = G.slab;
-              StokesCellArgs one = G.hargs[0];
-              const StokesCellArgs* many = n > 1 ? G.dargs() : nullptr;
-              if (slab) {
-                e = launch_slab_local<T>(g, tb, one, many, n, G.ngreen, s);
-                if (e == hipSuccess) e = launch_slab_rhs<T>(g, tb, one, many, n, s);
-              } else {
-                if (g.dim == 3)
-                  e = n > 1 ? launch_cols_batched<T>(g, tb, 1, +1, g.dim, G.dcols(), n, s)
-                            : launch_cols<T>(g, tb, 1, +1, g.dim, one.spec, s, &one.ctl->done);
-                if (e == hipSuccess) e = launch_stokes_local<T>(g, tb, one, many, n, G.ngreen, s);
-                if (e == hipSuccess) e = launch_stokes_rhs<T>(g, tb, one, many, n, s);
-                if (e == hipSuccess && g.dim == 3)
-                  e = n > 1 ? launch_cols_batched<T>(g, tb, 1, -1, g.dim, G.dcols(), n, s)
-                            : launch_cols<T>(g, tb, 1, -1, g.dim, one.spec, s, &one.ctl->done);
-              }
-            }
-            if (e != hipSuccess) {
-              (void)hipEventDestroy(e0);
-              (void)hipEventDestroy(e1);
-              return fail(ACM_E_HIP, std::string("autotune: ") + hipGetErrorString(e));
-            }
-            if (rep > 0) tot += ms;  // the first launch of a variant warms caches
+          // one warm-up iteration, then 4 timed iterations back to back
+          hipError_t e = enqueue_iteration<T>(G, s, &off);
+          if (e == hipSuccess) e = hipEventRecord(e0, s);
+          for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) e = enqueue_iteration<T>(G, s, &off);
+          if (e == hipSuccess) e = hipEventRecord(e1, s);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (e != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return fail(ACM_E_HIP, std::string("autotune: ") + hipGetErrorString(e));
           }
-          if (tot < best) {
-            best = tot;
+          if (ms < best) {
+            best = ms;
             bestv = v;
           }
         }
