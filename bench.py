@@ -193,6 +193,57 @@ def kernel_bytes(kind: str, n: int, d: int, nsolid: int, real_bytes: int = 4) ->
     return float("nan")
 
 
+COUNTER_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                               "stokes3d_128_hbm_counters.md")
+KERNEL_SYMBOL = {"local": "k_slab_local", "rhs": "k_slab_rhs", "green": "k_stokes_green"}
+
+
+def kernel_source_hash() -> str:
+    """SHA-256 over the kernel sources (csrc/*.hip, *.hpp in name order)."""
+    import hashlib
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2312_15554_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic(kind: str):
+    """HBM bytes per launch of `kind` from the committed rocprofv3 counter
+    summary: FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by the
+    ratio known bytes / counter reading of a plain device copy.  None when the
+    summary is missing, lacks the kernel, or was taken on other kernel sources."""
+    try:
+        text = open(COUNTER_SUMMARY).read()
+    except OSError:
+        return None
+    meta = {}
+    rows = {}
+    for line in text.splitlines():
+        line = line.strip()
+        for key in ("source-sha256", "fetch-scale", "write-scale"):
+            if line.startswith(key + ":"):
+                meta[key] = line.split(":", 1)[1].strip().strip("`")
+        if line.startswith("| `acm::"):
+            cells = [c.strip().strip("`") for c in line.strip("|").split("|")]
+            try:
+                rows[cells[0]] = (float(cells[1]), float(cells[2]))
+            except (ValueError, IndexError):
+                pass
+    if meta.get("source-sha256") != kernel_source_hash():
+        return None
+    sym = KERNEL_SYMBOL.get(kind)
+    hits = [v for k, v in rows.items() if sym and k.startswith(f"acm::{sym}<float")]
+    if len(hits) != 1 or "fetch-scale" not in meta or "write-scale" not in meta:
+        return None
+    fetch_kib, write_kib = hits[0]
+    return round(fetch_kib * 1024 * float(meta["fetch-scale"]) +
+                 write_kib * 1024 * float(meta["write-scale"]))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -323,7 +374,7 @@ def main():
         "kernels": per_kernel,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+                     "traffic": counter_traffic(dom)},
         "cpu_baseline": cpu,
         "transport": transport,
         "batched": batched,

@@ -77,6 +77,17 @@ typedef struct {
   int32_t pass_mode;    /* Stokes 3D: 0 automatic, 1 separate x and y passes,
                            2 fused xy-slab passes (needs nx == ny <= 128 and
                            16-byte aligned u and H; otherwise ACM_E_INVALID) */
+  int32_t green_variant; /* Stokes: kernel of the last-axis (green) pass. 0 automatic:
+                           the first solve of a grid times every variant over a few
+                           iterations and keeps the fastest for that grid; 1-3 force
+                           the LDS-staged kernel with the default, half and double
+                           pencil count per workgroup; 4-5 force the register-resident
+                           kernel with the default and half pencil count (lengths with
+                           a radix-3 factor use the LDS-staged kernel instead); 6-7
+                           force the LDS-staged kernel with one thread group per
+                           field during the transforms (default and half pencil
+                           count).  All variants compute the same iterates up to
+                           rounding. */
 } acm_opts;
 
 /* Kernel kinds reported in acm_stats.kernel_ms (with opts.profile = 1). */
@@ -112,7 +123,7 @@ void acm_default_opts(acm_opts* o);
  * the next call on the same thread. */
 const char* acm_last_error(void);
 
-/* ABI version (incremented on any signature or struct change): 2. */
+/* ABI version (incremented on any signature or struct change): 3. */
 int32_t acm_version(void);
 
 /*

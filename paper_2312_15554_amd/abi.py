@@ -30,7 +30,8 @@ class acm_penalty(C.Structure):
 class acm_opts(C.Structure):
     _fields_ = [("eps", C.c_double), ("max_iter", C.c_int64), ("precision", C.c_int32),
                 ("check_every", C.c_int32), ("warm_start", C.c_int32), ("use_graph", C.c_int32),
-                ("profile", C.c_int32), ("history_cap", C.c_int32), ("pass_mode", C.c_int32)]
+                ("profile", C.c_int32), ("history_cap", C.c_int32), ("pass_mode", C.c_int32),
+                ("green_variant", C.c_int32)]
 
 
 class acm_stats(C.Structure):
@@ -85,6 +86,9 @@ SIGNATURES = {
 _lib = None
 
 
+ABI_VERSION = 3  # must equal acm_version() of the loaded library
+
+
 def load(path: str = LIB_PATH):
     """Load libacm.so and declare its entry points.  Raises if it is missing."""
     global _lib
@@ -99,6 +103,9 @@ def load(path: str = LIB_PATH):
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
+    if lib.acm_version() != ABI_VERSION:
+        raise RuntimeError(f"{path} has ABI version {lib.acm_version()}, these bindings expect "
+                           f"{ABI_VERSION}: rebuild the library")
     _lib = lib
     return lib
 

@@ -143,8 +143,13 @@ hipError_t launch_cols_batched(const Geom& g, const DevTables<T>& tb, int axis, 
 
 // Stokes ADMM passes.  `one` is used when `many` is null (single cell);
 // otherwise cell i = blockIdx.z reads many[i] and ncells cells are launched.
-// `variant` (0, 1, 2) picks the tile width (see ColCfg); *nblocks receives
+// `variant` 0, 1, 2: LDS-staged kernel with tile width per ColCfg; 3, 4:
+// register-resident kernel with the tile widths of 0 and 1; 5, 6: LDS-staged
+// kernel with one thread group per field during the transforms, tile widths
+// of 0 and 1 (kGreenVariants in all); *nblocks receives
 // the number of workgroups per cell (= partial-sum records written).
+constexpr int kGreenVariants = 7;
+
 template <typename T>
 hipError_t launch_stokes_green(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
                                const StokesCellArgs* many, int ncells, int variant, int* nblocks,

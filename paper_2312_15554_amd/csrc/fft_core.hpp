@@ -301,6 +301,106 @@ struct PencilFFT {
   }
 };
 
+
+// ---------------------------------------------------------------------------
+// Register-resident pencil FFT.  Thread t of a pencil group (TPP threads)
+// holds the EPT = L / TPP elements i = t + m TPP (m in [0, EPT)) of each of
+// NP pencils in v[p][m] before AND after the transform: the first stage reads
+// exactly that set (its radix is EPT) and the last stage writes exactly that
+// set back, so data enter and leave through registers and LDS is only used to
+// exchange between stages.  Valid when every stage's butterfly count is a
+// multiple of TPP (all plans without a radix-3 stage).
+// ---------------------------------------------------------------------------
+template <int L>
+struct RegPlanOk {
+  static constexpr bool value() {
+    for (int s = 0; s < Plan<L>::nst; ++s)
+      if ((L / Plan<L>::radix(s)) % Plan<L>::TPP != 0) return false;
+    return true;
+  }
+};
+
+template <typename T, int L, int NP, int SIGN>
+struct RegFFT {
+  using PL = Plan<L>;
+  static constexpr int TPP = PL::TPP;
+  static constexpr int EPT = L / TPP;
+  static_assert(RegPlanOk<L>::value(), "register FFT needs TPP | L/R for every stage");
+
+  // LDS exchange buffer: pencil p element i at lds[p*pstride + i*estride].
+  template <int S>
+  __device__ static void stage(int t, bool active, cplx<T> (&v)[NP][EPT], cplx<T>* lds,
+                               int pstride, int estride, const cplx<T>* __restrict__ tw) {
+    constexpr int R = PL::radix(S);
+    constexpr int NS = PL::ns(S);
+    constexpr int NB = L / R;
+    constexpr int PER = NB / TPP;
+    constexpr bool FIRST = (S == 0);
+    constexpr bool LAST = (S == PL::nst - 1);
+    cplx<T> w[NP][PER][R];
+    if (active) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int j = t + q * TPP;
+        const int k = j % NS;
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            if constexpr (FIRST)
+              w[p][q][r] = v[p][r];  // element t + r TPP
+            else
+              w[p][q][r] = lds[p * pstride + (j + r * NB) * estride];
+          }
+        if constexpr (NS > 1) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            cplx<T> tt = tw[PL::twoff(S) + k * (R - 1) + (r - 1)];
+            if (SIGN > 0) tt.y = -tt.y;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) w[p][q][r] = cmul(w[p][q][r], tt);
+          }
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p) Dft<R, SIGN, T>::run(w[p][q]);
+      }
+    }
+    if constexpr (LAST) {
+      // outputs at j + r NB = t + (q + r PER) TPP: the natural set again
+      if (active) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int p = 0; p < NP; ++p) v[p][q + r * PER] = w[p][q][r];
+      }
+    } else {
+      if constexpr (!FIRST) __syncthreads();  // everyone has read the buffer
+      if (active) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          const int j = t + q * TPP;
+          const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+          for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[p * pstride + (base + r * NS) * estride] = w[p][q][r];
+        }
+      }
+      __syncthreads();
+      stage<S + 1>(t, active, v, lds, pstride, estride, tw);
+    }
+  }
+
+  // The whole workgroup calls run() together; it contains workgroup barriers
+  // (and ends with none: the caller synchronises before reusing `lds`).
+  __device__ static void run(int t, bool active, cplx<T> (&v)[NP][EPT], cplx<T>* lds,
+                             int pstride, int estride, const cplx<T>* __restrict__ tw) {
+    stage<0>(t, active, v, lds, pstride, estride, tw);
+  }
+};
+
 // Workgroup-wide FP64 sum of NV values per thread.  Returns the totals in
 // thread 0 (valid only there).  `red` must hold NV * (blockDim/64) doubles.
 template <int NV>

@@ -32,8 +32,17 @@ struct SlabCfg {
   static constexpr int P2 = XH + 1;  // row pitch in complex values (even: rows 16B-aligned)
   static constexpr int TPPY = Plan<NY>::TPP;
   static constexpr int TPPX = Plan<M>::TPP;
-  // enough column groups to cover the XH columns in two rounds
-  static constexpr int NT0 = ((TPPY * ((XH + 1) / 2) + 63) / 64) * 64;
+  // NT_EVEN: workgroup of TPPY * M/2 threads (XH columns in three rounds, the
+  // last one column) instead of enough threads for two rounds; measured
+  // faster at 128^2, where 512 threads leave room for two workgroups per CU.
+  // PF: state loads issued before the slab load (2: u, H and a; 1: u and H,
+  // a after the column transforms; 0: each quad's state is loaded in the
+  // pointwise loop, which keeps the fewest registers live; measured fastest).
+  // UNR: unroll of the pointwise loop (with PF = 0 its loads sit in it).
+  static constexpr bool NT_EVEN = (NX == 128);
+  static constexpr int PF = 0;
+  static constexpr int NT0 = NT_EVEN ? ((TPPY * (M / 2) + 63) / 64) * 64
+                                     : ((TPPY * ((XH + 1) / 2) + 63) / 64) * 64;
   static constexpr int NT = NT0 < 64 ? 64 : (NT0 > 1024 ? 1024 : NT0);
   static constexpr int GY = NT / TPPY;  // column groups per round
   static constexpr int GX = NT / TPPX;  // row groups per round
@@ -42,6 +51,12 @@ struct SlabCfg {
   static constexpr int NQ = NV / 4;                       // quads per slab
   static constexpr int QPT = (NQ + NT - 1) / NT;          // quads per thread
   static constexpr bool FULL = (NQ % NT) == 0;
+  static constexpr int UNR = QPT;
+  // Waves per SIMD that let as many workgroups reside per CU as LDS allows
+  // (CDNA: 4 SIMDs and 160 KB of LDS per CU; at most 4 workgroups counted):
+  // the minimum occupancy requested from the register allocator.
+  static constexpr int BLK_LDS = (160 * 1024) / (LDS_BYTES + 1024);
+  static constexpr int WPE = cmax(1, cmin(8, (cmin(BLK_LDS, 4) * (NT / 64) + 3) / 4));
 };
 
 // y transform of all XH columns of the slab held in LDS ([y][k], pitch P2).
@@ -59,7 +74,8 @@ __device__ __forceinline__ void slab_cols(cplx<T>* lds, const cplx<T>* __restric
 }
 
 template <typename T, int NX, int NY>
-__global__ __launch_bounds__((SlabCfg<T, NX, NY>::NT)) void k_slab_local(
+__global__ __launch_bounds__((SlabCfg<T, NX, NY>::NT))
+__attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_local(
     StokesCellArgs one, const StokesCellArgs* __restrict__ many, int ngreen, int64_t ntot,
     int64_t nspec, const cplx<T>* __restrict__ twx, const cplx<T>* __restrict__ twy,
     const cplx<T>* __restrict__ rtw) {
@@ -101,10 +117,10 @@ __global__ __launch_bounds__((SlabCfg<T, NX, NY>::NT)) void k_slab_local(
   for (int j = 0; j < S::QPT; ++j) {
     const int q = threadIdx.x + j * S::NT;
     hw[j] = 0u;
-    if (S::FULL || q < S::NQ) {
+    if (S::PF >= 1 && (S::FULL || q < S::NQ)) {
       up[j] = uq[q];
       hw[j] = hq[q];
-      ao[j] = aq[q];
+      if constexpr (S::PF == 2) ao[j] = aq[q];
     }
   }
 
@@ -115,6 +131,15 @@ __global__ __launch_bounds__((SlabCfg<T, NX, NY>::NT)) void k_slab_local(
   }
   __syncthreads();
   slab_cols<T, NX, NY, +1>(lds, twy);
+  if constexpr (S::PF == 1) {
+    // a is issued here: its latency overlaps the row transforms, and fewer
+    // registers stay live across the column transforms
+#pragma unroll
+    for (int j = 0; j < S::QPT; ++j) {
+      const int q = threadIdx.x + j * S::NT;
+      if (S::FULL || q < S::NQ) ao[j] = aq[q];
+    }
+  }
   {
     const int grp = threadIdx.x / S::TPPX, t = threadIdx.x % S::TPPX;
 #pragma unroll 1
@@ -127,26 +152,37 @@ __global__ __launch_bounds__((SlabCfg<T, NX, NY>::NT)) void k_slab_local(
 
   // Steps 2-3 on 4 consecutive voxels per quad.
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
+#pragma unroll S::UNR
   for (int j = 0; j < S::QPT; ++j) {
     const int q = threadIdx.x + j * S::NT;
     if (!S::FULL && q >= S::NQ) continue;
     const int v = 4 * q;
     const int y = v / NX, x = v - y * NX;
+    V upj, aoj;
+    uint32_t hwj;
+    if constexpr (S::PF == 0) {
+      upj = uq[q];
+      hwj = hq[q];
+      aoj = aq[q];
+    } else {
+      upj = up[j];
+      hwj = hw[j];
+      aoj = ao[j];
+    }
     const V un = *reinterpret_cast<const V*>(ldsr + y * 2 * S::P2 + x);
     const T unv[4] = {un.x, un.y, un.z, un.w};
-    const T upv[4] = {up[j].x, up[j].y, up[j].z, up[j].w};
+    const T upv[4] = {upj.x, upj.y, upj.z, upj.w};
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const double du = (double)unv[e] - (double)upv[e];
       acc[3] += du * du;
     }
     uq[q] = un;
-    if (hw[j]) {
-      T aov[4] = {ao[j].x, ao[j].y, ao[j].z, ao[j].w};
+    if (hwj) {
+      T aov[4] = {aoj.x, aoj.y, aoj.z, aoj.w};
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        if ((hw[j] >> (8 * e)) & 0xffu) {
+        if ((hwj >> (8 * e)) & 0xffu) {
           const T an = aov[e] + ka * unv[e];
           aov[e] = an;
           const T dd = cc * unv[e] - cp * upv[e];
@@ -183,7 +219,8 @@ __global__ __launch_bounds__((SlabCfg<T, NX, NY>::NT)) void k_slab_local(
 }
 
 template <typename T, int NX, int NY>
-__global__ __launch_bounds__((SlabCfg<T, NX, NY>::NT)) void k_slab_rhs(StokesCellArgs one,
+__global__ __launch_bounds__((SlabCfg<T, NX, NY>::NT))
+__attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_rhs(StokesCellArgs one,
                                                   const StokesCellArgs* __restrict__ many,
                                                   int64_t ntot, int64_t nspec,
                                                   const cplx<T>* __restrict__ twx,

@@ -30,13 +30,13 @@ struct GreenGeom {
   int64_t ntot;
 };
 
-template <typename T, int L, int NC, int VAR>
-__global__ __launch_bounds__((ColCfg<T, L, NC, VAR>::NT)) void k_stokes_green(
+template <typename T, int L, int NC, int VAR, int SPL>
+__global__ __launch_bounds__((ColCfg<T, L, NC, VAR, SPL>::NT)) void k_stokes_green(
     StokesCellArgs one, const StokesCellArgs* __restrict__ many, GreenGeom gg,
     const cplx<T>* __restrict__ tw, const T* __restrict__ sx, const T* __restrict__ lx,
     const T* __restrict__ sy, const T* __restrict__ ly, const T* __restrict__ sz,
     const T* __restrict__ lz) {
-  using C = ColCfg<T, L, NC, VAR>;
+  using C = ColCfg<T, L, NC, VAR, SPL>;
   const StokesCellArgs ca = many ? many[blockIdx.z] : one;
   cplx<T>* __restrict__ spec = reinterpret_cast<cplx<T>*>(ca.spec);
   cplx<T>* __restrict__ qhat = reinterpret_cast<cplx<T>*>(ca.qhat);
@@ -78,9 +78,16 @@ __global__ __launch_bounds__((ColCfg<T, L, NC, VAR>::NT)) void k_stokes_green(
     }
   }
   __syncthreads();
-  const int t = threadIdx.x / C::TX, colt = threadIdx.x % C::TX;
-  const bool act = t < C::TPP && f0 + colt < P;
-  PencilFFT<T, L, NC, -1>::run_lds(t, act, lds + colt, PS, C::TX, tw);
+  // transform threads: (field, t, column) with SPL, else (t, column) over all fields
+  const int fc = SPL ? threadIdx.x / (C::TPP * C::TX) : 0;
+  const int tr = SPL ? threadIdx.x % (C::TPP * C::TX) : threadIdx.x;
+  const int t = tr / C::TX, colt = tr % C::TX;
+  const bool act = fc < NC && t < C::TPP && f0 + colt < P;
+  cplx<T>* const pen = lds + (act ? fc : 0) * PS + colt;
+  if constexpr (SPL)
+    PencilFFT<T, L, 1, -1>::run_lds(t, act, pen, PS, C::TX, tw);
+  else
+    PencilFFT<T, L, NC, -1>::run_lds(t, act, pen, PS, C::TX, tw);
   __syncthreads();
 
   double acc[3] = {0.0, 0.0, 0.0};
@@ -154,7 +161,10 @@ __global__ __launch_bounds__((ColCfg<T, L, NC, VAR>::NT)) void k_stokes_green(
     acc[2] += w * ((double)qn.x * qn.x + (double)qn.y * qn.y);
   }
   __syncthreads();
-  PencilFFT<T, L, NC, 1>::run_lds(t, act, lds + colt, PS, C::TX, tw);
+  if constexpr (SPL)
+    PencilFFT<T, L, 1, 1>::run_lds(t, act, pen, PS, C::TX, tw);
+  else
+    PencilFFT<T, L, NC, 1>::run_lds(t, act, pen, PS, C::TX, tw);
   __syncthreads();
   for (int e = threadIdx.x; e < NC * PS; e += C::NT) {
     const int c = e / PS, rem = e - c * PS;
@@ -281,6 +291,137 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_stokes_rhs(
   for (int v = threadIdx.x; v < nr * (M + 1); v += C::NT) dst[v] = lds[v];
 }
 
+
+// Register-resident variant of the green pass (lengths whose plan allows the
+// register FFT): every thread loads the pencil elements it owns straight from
+// global memory, the forward transform, the per-mode operator and the inverse
+// transform run on registers (LDS only between transform stages), and the
+// results are stored straight back.
+template <typename T, int L, int NC, int VAR>
+__global__ __launch_bounds__((ColCfg<T, L, NC, VAR>::NT)) void k_stokes_green_reg(
+    StokesCellArgs one, const StokesCellArgs* __restrict__ many, GreenGeom gg,
+    const cplx<T>* __restrict__ tw, const T* __restrict__ sx, const T* __restrict__ lx,
+    const T* __restrict__ sy, const T* __restrict__ ly, const T* __restrict__ sz,
+    const T* __restrict__ lz) {
+  using C = ColCfg<T, L, NC, VAR>;
+  constexpr int PS = L * C::TX;
+  constexpr int TPP = C::TPP;
+  constexpr int EPT = L / TPP;
+  const StokesCellArgs ca = many ? many[blockIdx.z] : one;
+  cplx<T>* __restrict__ spec = reinterpret_cast<cplx<T>*>(ca.spec);
+  cplx<T>* __restrict__ qhat = reinterpret_cast<cplx<T>*>(ca.qhat);
+  cplx<T>* __restrict__ dhat = reinterpret_cast<cplx<T>*>(ca.dhat);
+  double* __restrict__ partials = ca.part;
+  const StokesCtl* __restrict__ ctl = ca.ctl;
+  extern __shared__ __align__(16) char smem_raw[];
+  __shared__ double red[3 * 16];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  if (ctl->done) return;
+  const T beta = (T)ctl->psi[1];
+  const T bpen = (T)ctl->psi[2];
+  const T nu = (T)ctl->nu;
+  const int P = gg.plane;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int f0 = tile * C::TX;
+  const int t = threadIdx.x / C::TX, col = threadIdx.x % C::TX;
+  const int f = f0 + col;
+  const bool act = t < TPP && f < P;
+
+  cplx<T> v[NC][EPT], qv[EPT], dv[EPT];
+  if (act) {
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+      const int64_t mi = (int64_t)(t + m * TPP) * P + f;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[c][m] = spec[c * gg.nspec + mi];
+      qv[m] = qhat[mi];
+      dv[m] = dhat[mi];
+    }
+  }
+  RegFFT<T, L, NC, -1>::run(t, act, v, lds + col, PS, C::TX, tw);
+
+  double acc[3] = {0.0, 0.0, 0.0};
+  const T inv_ntot = T(1.0 / (double)gg.ntot);
+  if (act) {
+    int kx, ky;
+    if (NC == 3) {
+      kx = f % gg.xh;
+      ky = f / gg.xh;
+    } else {
+      kx = f;
+      ky = 0;
+    }
+    const double w = (kx == 0 || 2 * kx == gg.nx) ? 1.0 : 2.0;
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+      const int i = t + m * TPP;  // index along the transformed (last) axis
+      const int kz = NC == 3 ? i : 0;
+      if (NC != 3) ky = i;
+      T s[NC];
+      s[0] = sx[kx];
+      s[1] = sy[ky];
+      T Lk = lx[kx] + ly[ky];
+      if constexpr (NC == 3) {
+        s[2] = sz[kz];
+        Lk += lz[kz];
+      }
+      const cplx<T> q = qv[m];
+      const cplx<T> dp = dv[m];
+      const bool k0 = (kx == 0 && ky == 0 && kz == 0);
+      cplx<T> R[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        cplx<T> r = v[c][m];
+        r.x += s[c] * q.y;
+        r.y -= s[c] * q.x;
+        if (k0) r.x += (T)((double)gg.ntot * ctl->g[c]);
+        R[c] = r;
+      }
+      const T c0 = nu * Lk + bpen;
+      cplx<T> sr = cmake<T>(T(0), T(0));
+      T ss = T(0);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        sr.x += s[c] * R[c].x;
+        sr.y += s[c] * R[c].y;
+        ss += s[c] * s[c];
+      }
+      const T inv_den = T(1) / (c0 + beta * ss);
+      const cplx<T> coef = cscale(sr, beta * inv_den);
+      const T inv_c0 = T(1) / c0;
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        v[c][m] = cscale(cmake<T>((R[c].x - s[c] * coef.x) * inv_c0, (R[c].y - s[c] * coef.y) * inv_c0),
+                         inv_ntot);
+      const cplx<T> dl = cmake<T>(-sr.y * inv_den, sr.x * inv_den);
+      const cplx<T> qn = cmake<T>(q.x - beta * dl.x, q.y - beta * dl.y);
+      const int64_t mi = (int64_t)i * P + f;
+      qhat[mi] = qn;
+      dhat[mi] = dl;
+      const double ddx = (double)dl.x - (double)dp.x, ddy = (double)dl.y - (double)dp.y;
+      acc[0] += w * ((double)dl.x * dl.x + (double)dl.y * dl.y);
+      acc[1] += w * (ddx * ddx + ddy * ddy);
+      acc[2] += w * ((double)qn.x * qn.x + (double)qn.y * qn.y);
+    }
+  }
+  __syncthreads();  // the forward transform's last LDS reads are complete
+  RegFFT<T, L, NC, 1>::run(t, act, v, lds + col, PS, C::TX, tw);
+  if (act) {
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+      const int64_t mi = (int64_t)(t + m * TPP) * P + f;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) spec[c * gg.nspec + mi] = v[c][m];
+    }
+  }
+  block_sum<3>(acc, red);
+  if (threadIdx.x == 0) {
+    partials[tile * 3 + 0] = acc[0];
+    partials[tile * 3 + 1] = acc[1];
+    partials[tile * 3 + 2] = acc[2];
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 template <int L, typename T, int VAR>
 static int green_blocks_for(const Geom& g) {
@@ -291,6 +432,10 @@ static int green_blocks_for(const Geom& g) {
 
 template <int L, typename T>
 static int green_blocks_var(const Geom& g, int variant) {
+  // register-resident (3, 4) and field-split (5, 6) kernels use the tile
+  // widths of variants 0 and 1
+  if (variant == 3 || variant == 5) variant = 0;
+  if (variant == 4 || variant == 6) variant = 1;
   if (variant == 1) return green_blocks_for<L, T, 1>(g);
   if (variant == 2) return green_blocks_for<L, T, 2>(g);
   return green_blocks_for<L, T, 0>(g);
@@ -323,20 +468,25 @@ int stokes_local_blocks(const Geom& g, int prec_bytes) {
   }
 }
 
-template <typename T, int LL, int NC, int VAR>
+template <typename T, int LL, int NC, int VAR, bool REG, int SPL = 0>
 static hipError_t green_launch(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
                                const StokesCellArgs* many, int ncells, int* nblocks,
                                hipStream_t s) {
-  using C = ColCfg<T, LL, NC, VAR>;
+  using C = ColCfg<T, LL, NC, VAR, SPL>;
   const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
   const T* rt = tb.rtab;
   GreenGeom gg{g.dim, g.nx, g.xh, (int)g.plane, g.nspec, g.ntot};
   const cplx<T>* tw = ct + (g.dim == 3 ? tb.off.tw_z : tb.off.tw_y);
   const int nb = (int)((g.plane + C::TX - 1) / C::TX);
   if (nblocks) *nblocks = nb;
-  hipLaunchKernelGGL((k_stokes_green<T, LL, NC, VAR>), dim3(nb, 1, ncells), dim3(C::NT),
-                     C::LDS_BYTES, s, one, many, gg, tw, rt + tb.off.sx, rt + tb.off.lx,
-                     rt + tb.off.sy, rt + tb.off.ly, rt + tb.off.sz, rt + tb.off.lz);
+  if constexpr (REG)
+    hipLaunchKernelGGL((k_stokes_green_reg<T, LL, NC, VAR>), dim3(nb, 1, ncells), dim3(C::NT),
+                       C::LDS_BYTES, s, one, many, gg, tw, rt + tb.off.sx, rt + tb.off.lx,
+                       rt + tb.off.sy, rt + tb.off.ly, rt + tb.off.sz, rt + tb.off.lz);
+  else
+    hipLaunchKernelGGL((k_stokes_green<T, LL, NC, VAR, SPL>), dim3(nb, 1, ncells), dim3(C::NT),
+                       C::LDS_BYTES, s, one, many, gg, tw, rt + tb.off.sx, rt + tb.off.lx,
+                       rt + tb.off.sy, rt + tb.off.ly, rt + tb.off.sz, rt + tb.off.lz);
   return hipGetLastError();
 }
 
@@ -344,9 +494,19 @@ template <typename T, int LL, int NC>
 static hipError_t green_var(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
                             const StokesCellArgs* many, int ncells, int variant, int* nblocks,
                             hipStream_t s) {
-  if (variant == 1) return green_launch<T, LL, NC, 1>(g, tb, one, many, ncells, nblocks, s);
-  if (variant == 2) return green_launch<T, LL, NC, 2>(g, tb, one, many, ncells, nblocks, s);
-  return green_launch<T, LL, NC, 0>(g, tb, one, many, ncells, nblocks, s);
+  constexpr bool reg_ok = RegPlanOk<LL>::value();
+  if (variant == 3 || variant == 4) {
+    if constexpr (reg_ok) {
+      if (variant == 3) return green_launch<T, LL, NC, 0, true>(g, tb, one, many, ncells, nblocks, s);
+      return green_launch<T, LL, NC, 1, true>(g, tb, one, many, ncells, nblocks, s);
+    }
+    variant -= 3;  // radix-3 plans: LDS-staged kernel of the same tile width
+  }
+  if (variant == 5) return green_launch<T, LL, NC, 0, false, 1>(g, tb, one, many, ncells, nblocks, s);
+  if (variant == 6) return green_launch<T, LL, NC, 1, false, 1>(g, tb, one, many, ncells, nblocks, s);
+  if (variant == 1) return green_launch<T, LL, NC, 1, false>(g, tb, one, many, ncells, nblocks, s);
+  if (variant == 2) return green_launch<T, LL, NC, 2, false>(g, tb, one, many, ncells, nblocks, s);
+  return green_launch<T, LL, NC, 0, false>(g, tb, one, many, ncells, nblocks, s);
 }
 
 template <typename T>

@@ -141,8 +141,10 @@ __device__ __forceinline__ int col_base(const ColMap& m, int f) {
 }
 
 // VAR selects the tile width for the autotuner: 0 = default (about 256
-// threads), 1 = half of it, 2 = twice it (each capped by LDS).
-template <typename T, int L, int NCOMP, int VAR = 0>
+// threads), 1 = half of it, 2 = twice it (each capped by LDS).  SPL = 1 gives
+// every field its own threads during the transforms (NCOMP times as many
+// threads, each transforming one pencil: fewer registers per thread).
+template <typename T, int L, int NCOMP, int VAR = 0, int SPL = 0>
 struct ColCfg {
   static constexpr int TPP = Plan<L>::TPP;
   static constexpr int TX_BASE = cmax(1, 256 / TPP);
@@ -151,7 +153,8 @@ struct ColCfg {
   static constexpr int TX_LDS = cmax(1, ((VAR == 2 ? 100 : 56) * 1024) / (NCOMP * L * (int)sizeof(cplx<T>)));
   static constexpr int TX = cmin(TX_THREADS, TX_LDS);
   // block size padded to whole wavefronts; threads with t >= TPP stay idle
-  static constexpr int NT = ((TPP * TX + 63) / 64) * 64;
+  static constexpr int NT = (((SPL ? NCOMP : 1) * TPP * TX + 63) / 64) * 64;
+  static_assert(NT <= 1024, "workgroup too large");
   static constexpr int LDS_BYTES = NCOMP * L * TX * (int)sizeof(cplx<T>);
 };
 

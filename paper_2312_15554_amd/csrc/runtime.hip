@@ -177,7 +177,8 @@ static acm_status get_plan(const acm_grid* grid, int precision, CellPlan** out) 
   }
   if (e != hipSuccess) return fail(ACM_E_HIP, std::string("table upload: ") + hipGetErrorString(e));
   p->green_blocks = 0;
-  for (int v = 0; v < 3; ++v) p->green_blocks = std::max(p->green_blocks, stokes_green_blocks(g, p->prec, v));
+  for (int v = 0; v < kGreenVariants; ++v)
+    p->green_blocks = std::max(p->green_blocks, stokes_green_blocks(g, p->prec, v));
   p->local_blocks = stokes_local_blocks(g, p->prec);
   *out = p.get();
   g_plans[key] = std::move(p);
@@ -528,18 +529,19 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
     }
   } hf{hctl};
 
-  // ---- tile-width autotuning of the green pass: the first iterations of the
-  // first solve of a plan run eagerly, one variant at a time, with HIP events
-  // around the green launch; the fastest variant is kept for this plan.  Every
-  // variant computes the same values (only the number of pencils per
-  // workgroup changes), so the iterates do not depend on the choice.
+  // ---- autotuning of the green pass: the first iterations of the first solve
+  // of a plan run eagerly, one kernel variant at a time (tile widths of the
+  // LDS-staged kernel, then of the register-resident one), with HIP events
+  // around whole iterations; the fastest variant is kept for this plan.  The
+  // variants apply the same arithmetic in the same order (up to the
+  // compiler's contraction choices), so the choice changes iterates only at
+  // the rounding level.
   {
-    const char* force = getenv("ACM_GREEN_VARIANT");
     for (auto& Gp : groups) {
       StokesGroup<T>& G = *Gp;
       const Geom& g = G.pl->g;
-      if (force) {
-        G.green_var = std::max(0, std::min(2, atoi(force)));
+      if (o.green_variant > 0) {
+        G.green_var = o.green_variant - 1;
       } else if (G.pl->green_var < 0 && g.ntot >= (int64_t)64 * 64 * 64 && o.max_iter >= 64) {
         float best = 1e30f;
         int bestv = 0;
@@ -547,7 +549,7 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
         Profiler off;
-        for (int v = 0; v < 3; ++v) {
+        for (int v = 0; v < kGreenVariants; ++v) {
           G.green_var = v;
           G.ngreen = stokes_green_blocks(g, G.pl->prec, v);
           // one warm-up iteration, then 4 timed iterations back to back
@@ -746,6 +748,8 @@ static acm_status check_penalty_opts(const acm_penalty& P, const acm_opts& O, do
   if (!(nu > 0.0) || !isfinite(nu)) return fail(ACM_E_INVALID, "nu must be positive");
   if (!(O.eps >= 0.0) || O.max_iter < 1) return fail(ACM_E_INVALID, "eps >= 0 and max_iter >= 1 required");
   if (O.pass_mode < 0 || O.pass_mode > 2) return fail(ACM_E_INVALID, "pass_mode must be 0, 1 or 2");
+  if (O.green_variant < 0 || O.green_variant > kGreenVariants)
+    return fail(ACM_E_INVALID, "green_variant must be in [0, " + std::to_string(kGreenVariants) + "]");
   for (int k = 0; k < 3; ++k)
     if (!(P.phi[k] >= 1.0) || !(P.tau[k] > 0.0))
       return fail(ACM_E_INVALID, "phi >= 1 and tau > 0 required");
@@ -1291,7 +1295,7 @@ void acm_default_opts(acm_opts* o) {
 
 const char* acm_last_error(void) { return g_err.c_str(); }
 
-int32_t acm_version(void) { return 2; }
+int32_t acm_version(void) { return 3; }
 
 acm_status acm_stokes_solve(const acm_grid* grid, const uint8_t* H, const double* g_p, double nu,
                             const acm_penalty* pen, const acm_opts* opts, void* u, void* q,

@@ -29,3 +29,5 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, n), n
     from paper_2312_15554_amd import abi
     assert set(abi.SIGNATURES) == set(_declared())
+    lib.acm_version.restype = ctypes.c_int32
+    assert lib.acm_version() == abi.ABI_VERSION

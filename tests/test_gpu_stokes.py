@@ -67,6 +67,36 @@ def test_fused_and_separate_passes_match_oracle(shape, dtype, pass_mode):
         assert abs(r["stats"]["r_d"][k] - o["r_d"][k]) <= tol * 100 * o["r_d"][k] + 1e-12
 
 
+_VARIANT_ORACLE = {}
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("shape", [(16, 16), (32, 24, 16), (24, 16, 16), (64, 16, 8), (128, 8, 8)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("green_variant", [1, 2, 3, 4, 5, 6, 7])
+def test_green_variants_match_oracle(shape, dtype, green_variant):
+    """Every kernel variant of the last-axis pass (LDS-staged, register-
+    resident and field-split, each pencil count per workgroup) reproduces the
+    oracle's iterates; a last axis of 24 exercises the radix-3 fallback."""
+    require_gpu()
+    print(f"green variant parity shape={shape} dtype={dtype} variant={green_variant}", flush=True)
+    H = I.random_mask(shape, 23, 0.4)
+    g = (0.3, 1.0, -0.6)[:len(shape)]
+    M = 25
+    pen = dict(alpha=35.0, beta=45.0, b=15.0, adaptive=0)
+    r = _solve(H, g, dtype=dtype, penalty=pen, eps=0.0, max_iter=M, green_variant=green_variant)
+    if shape not in _VARIANT_ORACLE:
+        _VARIANT_ORACLE[shape] = O.stokes_admm(H, g, alpha=35.0, beta=45.0, b=15.0, adaptive=False,
+                                               eps=0.0, max_iter=M)
+    o = _VARIANT_ORACLE[shape]
+    tol = 1e-11 if dtype == torch.float64 else 2e-5
+    assert r["stats"]["iters"] == M
+    assert np.abs(host(r["u"]) - o["u"]).max() < tol * np.abs(o["u"]).max()
+    assert np.abs(host(r["q"]) - o["q"]).max() < tol * 10 * np.abs(o["q"]).max()
+    for k in range(3):
+        assert abs(r["stats"]["r_d"][k] - o["r_d"][k]) <= tol * 100 * o["r_d"][k] + 1e-12
+
+
 @pytest.mark.gpu
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_poiseuille_closed_form(dtype):
