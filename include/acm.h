@@ -76,7 +76,12 @@ typedef struct {
   int32_t history_cap;  /* > 0: keep the residuals of the last history_cap iterations */
   int32_t pass_mode;    /* Stokes 3D: 0 automatic, 1 separate x and y passes,
                            2 fused xy-slab passes (needs nx == ny <= 128 and
-                           16-byte aligned u and H; otherwise ACM_E_INVALID) */
+                           16-byte aligned u and H; otherwise ACM_E_INVALID),
+                           3 fused xy-slab passes with the local and rhs passes
+                           in one launch joined by a device-wide gate (needs, in
+                           addition, a single cell whose nz * 3 workgroups are
+                           all resident at once; otherwise ACM_E_INVALID).
+                           Automatic picks 2 where it applies, else 1. */
   int32_t green_variant; /* Stokes: kernel of the last-axis (green) pass. 0 automatic:
                            the first solve of a grid times every variant over a few
                            iterations and keeps the fastest for that grid; 1-3 force

@@ -52,11 +52,23 @@ struct StokesCtl {
   int32_t adaptive;
   uint32_t counter;   // workgroups of the local pass that have finished
   int32_t hist_cap;   // capacity of the residual history ring (entries)
+  uint32_t gate;      // fused slab pass: generations of its device-wide gate
+  int32_t fault;      // non-zero: a fused-pass gate wait exceeded its bound
   int32_t pad_;
 };
 
 // One history record per iteration: rp[3], rd[3], tp[3], td[3], psi[3].
 constexpr int kHistDoubles = 15;
+
+// Kernel timing in the profiling mode: when the calling thread's
+// launch_events() holds two events, the next kernel launched through
+// ACM_LAUNCH records the start and end of its own execution in them (the
+// dispatch's timestamps, no stream commands in between) and clears them.
+struct LaunchEvents {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
+LaunchEvents& launch_events();
 
 // Control block for one Lippmann-Schwinger solve (one time step at a time).
 struct TransportCtl {
@@ -199,6 +211,16 @@ hipError_t launch_slab_local(const Geom& g, const DevTables<T>& tb, const Stokes
 template <typename T>
 hipError_t launch_slab_rhs(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
                            const StokesCellArgs* many, int ncells, hipStream_t s);
+// Local and rhs slab passes of one cell in a single launch: every workgroup
+// runs the local pass, waits at a device-wide gate that the last one opens
+// after Step 4, then runs the rhs pass on the slab still held in LDS.  Valid
+// only when all nz * dim workgroups can be resident at once on the current
+// device: slab_fused_capacity() returns how many can (0 if unsupported).
+template <typename T>
+int slab_fused_capacity(const Geom& g);
+template <typename T>
+hipError_t launch_slab_fused(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
+                             int green_blocks, hipStream_t s);
 
 // FNO kernels (k_fno.hip).
 hipError_t fno_lift(const uint8_t* H, const uint16_t* Pw, const uint16_t* Pb, float* v, int C,

@@ -106,7 +106,7 @@ hipError_t launch_rows_r2c(const Geom& g, const DevTables<T>& tb, int nfields, c
   case M: {                                                                                \
     using C = RowCfg<T, M>;                                                                \
     dim3 grid((unsigned)((g.nrows + C::RB - 1) / C::RB), (unsigned)nfields);               \
-    hipLaunchKernelGGL((k_rows_r2c<T, M>), grid, dim3(C::NT), C::LDS_BYTES, s, in,          \
+    ACM_LAUNCH((k_rows_r2c<T, M>), grid, dim3(C::NT), C::LDS_BYTES, s, in,          \
                        reinterpret_cast<cplx<T>*>(out), (int)g.nrows, g.ntot, g.nspec,      \
                        ct + tb.off.tw_x, ct + tb.off.rtw);                                  \
     return hipGetLastError();                                                              \
@@ -127,7 +127,7 @@ hipError_t launch_rows_c2r(const Geom& g, const DevTables<T>& tb, int nfields, c
   case M: {                                                                                \
     using C = RowCfg<T, M>;                                                                \
     dim3 grid((unsigned)((g.nrows + C::RB - 1) / C::RB), (unsigned)nfields);               \
-    hipLaunchKernelGGL((k_rows_c2r<T, M>), grid, dim3(C::NT), C::LDS_BYTES, s,              \
+    ACM_LAUNCH((k_rows_c2r<T, M>), grid, dim3(C::NT), C::LDS_BYTES, s,              \
                        reinterpret_cast<const cplx<T>*>(in), out, (int)g.nrows, g.ntot,     \
                        g.nspec, (T)scale, ct + tb.off.tw_x, ct + tb.off.rtw);               \
     return hipGetLastError();                                                              \
@@ -171,10 +171,10 @@ static hipError_t cols_impl(const Geom& g, const DevTables<T>& tb, int axis, int
     dim3 grid((unsigned)((m.ncols + C::TX - 1) / C::TX), (unsigned)nfields,                 \
               (unsigned)ncells);                                                            \
     if (sign < 0)                                                                           \
-      hipLaunchKernelGGL((k_cols<T, LL, -1>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many, \
+      ACM_LAUNCH((k_cols<T, LL, -1>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many, \
                          g.nspec, m, tw);                                                   \
     else                                                                                    \
-      hipLaunchKernelGGL((k_cols<T, LL, 1>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many,  \
+      ACM_LAUNCH((k_cols<T, LL, 1>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many,  \
                          g.nspec, m, tw);                                                   \
     return hipGetLastError();                                                               \
   }

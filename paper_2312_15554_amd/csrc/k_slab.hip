@@ -73,7 +73,38 @@ __device__ __forceinline__ void slab_cols(cplx<T>* lds, const cplx<T>* __restric
   }
 }
 
+// Forward half of the rhs pass on a real slab held in LDS (rows of pitch
+// 2 P2 reals): x transforms of the rows, y transforms of the columns, store.
 template <typename T, int NX, int NY>
+__device__ __forceinline__ void slab_forward_store(cplx<T>* lds, cplx<T>* __restrict__ dst,
+                                                   const cplx<T>* __restrict__ twx,
+                                                   const cplx<T>* __restrict__ twy,
+                                                   const cplx<T>* __restrict__ rtw) {
+  using S = SlabCfg<T, NX, NY>;
+  {
+    const int grp = threadIdx.x / S::TPPX, t = threadIdx.x % S::TPPX;
+#pragma unroll 1
+    for (int r0 = 0; r0 < NY; r0 += S::GX) {
+      const int row = r0 + grp;
+      const bool act = grp < S::GX && row < NY;
+      rows_r2c_lds<T, S::M, 1, S::P2>(lds, 0, act ? row : 0, t, act, twx, rtw);
+    }
+  }
+  slab_cols<T, NX, NY, -1>(lds, twy);
+  for (int v = threadIdx.x; v < NY * S::XH; v += S::NT) {
+    const int y = v / S::XH, k = v - y * S::XH;
+    dst[v] = lds[y * S::P2 + k];
+  }
+}
+
+// Bound on the polls of the fused pass's gate (each poll sleeps briefly): a
+// wait that long means the workgroups were not all resident, and the pass
+// then gives up (ctl->fault) instead of hanging.
+constexpr uint32_t kGatePolls = 1u << 22;
+
+// Local pass (FUSED = false), or local and rhs passes of one cell in one
+// launch (FUSED = true, a single cell, every workgroup resident).
+template <typename T, int NX, int NY, bool FUSED>
 __global__ __launch_bounds__((SlabCfg<T, NX, NY>::NT))
 __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_local(
     StokesCellArgs one, const StokesCellArgs* __restrict__ many, int ngreen, int64_t ntot,
@@ -81,7 +112,7 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_local(
     const cplx<T>* __restrict__ rtw) {
   using S = SlabCfg<T, NX, NY>;
   const StokesCellArgs ca = many ? many[blockIdx.z] : one;
-  const cplx<T>* __restrict__ spec = reinterpret_cast<const cplx<T>*>(ca.spec);
+  cplx<T>* __restrict__ spec = reinterpret_cast<cplx<T>*>(ca.spec);
   T* __restrict__ u = reinterpret_cast<T*>(ca.u);
   T* __restrict__ a = reinterpret_cast<T*>(ca.a);
   const uint8_t* __restrict__ H = ca.H;
@@ -93,18 +124,17 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_local(
   extern __shared__ __align__(32) char smem_raw[];
   __shared__ double red[4 * 16];
   __shared__ double red7[7 * 16];
-  __shared__ int s_last;
+  __shared__ int s_last, s_go;
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   T* ldsr = reinterpret_cast<T*>(smem_raw);
   if (ctl->done) return;
+  const uint32_t gate0 = FUSED ? ctl->gate : 0u;  // read before this workgroup arrives
   const double al = ctl->psi[0], bb = ctl->psi[2];
   const T cc = (T)(bb / (bb + al));
   const T cp = (T)ctl->c_prev;
   const T ka = (T)(bb * al / (bb + al));
   const int z = blockIdx.x, field = blockIdx.y;
 
-  // State loads first: they do not depend on the transforms, so their
-  // latency overlaps the spectral-slab load and both FFT phases.
   const int64_t off = field * ntot + (int64_t)z * S::NV;
   V* uq = reinterpret_cast<V*>(u + off);
   V* aq = reinterpret_cast<V*>(a + off);
@@ -124,10 +154,10 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_local(
     }
   }
 
-  const cplx<T>* src = spec + field * nspec + (int64_t)z * NY * S::XH;
+  cplx<T>* slab = spec + field * nspec + (int64_t)z * NY * S::XH;
   for (int v = threadIdx.x; v < NY * S::XH; v += S::NT) {
     const int y = v / S::XH, k = v - y * S::XH;
-    lds[y * S::P2 + k] = src[v];
+    lds[y * S::P2 + k] = slab[v];
   }
   __syncthreads();
   slab_cols<T, NX, NY, +1>(lds, twy);
@@ -150,7 +180,8 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_local(
     }
   }
 
-  // Steps 2-3 on 4 consecutive voxels per quad.
+  // Steps 2-3 on 4 consecutive voxels per quad.  The fused pass keeps the new
+  // a and the solid flags of its quads for the rhs half (u stays in LDS).
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll S::UNR
   for (int j = 0; j < S::QPT; ++j) {
@@ -191,12 +222,15 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_local(
           acc[2] += (double)an * an;
         }
       }
-      V w;
-      w.x = aov[0];
-      w.y = aov[1];
-      w.z = aov[2];
-      w.w = aov[3];
-      aq[q] = w;
+      aoj.x = aov[0];
+      aoj.y = aov[1];
+      aoj.z = aov[2];
+      aoj.w = aov[3];
+      aq[q] = aoj;
+    }
+    if constexpr (FUSED) {
+      ao[j] = aoj;
+      hw[j] = hwj;
     }
   }
   block_sum<4>(acc, red);
@@ -215,6 +249,57 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_local(
   if (s_last) {
     __threadfence();
     stokes_finalize(ctl, gpart, ngreen, lpart, nblk, ntot, hist, red7);
+  }
+  if constexpr (FUSED) {
+    // ---- device-wide gate: the last workgroup opens it after Step 4
+    if (threadIdx.x == 0) {
+      int go = 1;
+      if (s_last) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(&ctl->gate, gate0 + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        uint32_t polls = 0;
+        while (__hip_atomic_load(&ctl->gate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gate0) {
+          __builtin_amdgcn_s_sleep(2);
+          if (++polls == kGatePolls) {
+            go = 0;
+            break;
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+      if (!go) {
+        __hip_atomic_store(&ctl->fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctl->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else if (__hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        go = 0;  // converged (or stopped) at this iteration: no next rhs
+      }
+      s_go = go;
+    }
+    __syncthreads();
+    if (!s_go) return;
+    // ---- rhs half: r = b^{n+1} ut^{n+1} - a^{n+1} on the slab in LDS
+    const double bnew = __hip_atomic_load(&ctl->psi[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const double cprev = __hip_atomic_load(&ctl->c_prev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const T b1 = (T)bnew;
+    const T bcp = (T)(bnew * cprev);
+#pragma unroll
+    for (int j = 0; j < S::QPT; ++j) {
+      const int q = threadIdx.x + j * S::NT;
+      if (!S::FULL && q >= S::NQ) continue;
+      const int v = 4 * q;
+      const int y = v / NX, x = v - y * NX;
+      V* cell = reinterpret_cast<V*>(ldsr + y * 2 * S::P2 + x);
+      const V un = *cell;
+      V r;
+      r.x = ((hw[j] & 0xffu) ? bcp : b1) * un.x - ao[j].x;
+      r.y = ((hw[j] & 0xff00u) ? bcp : b1) * un.y - ao[j].y;
+      r.z = ((hw[j] & 0xff0000u) ? bcp : b1) * un.z - ao[j].z;
+      r.w = ((hw[j] & 0xff000000u) ? bcp : b1) * un.w - ao[j].w;
+      *cell = r;
+    }
+    __syncthreads();
+    slab_forward_store<T, NX, NY>(lds, slab, twx, twy, rtw);
   }
 }
 
@@ -273,21 +358,7 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_rhs(St
     *reinterpret_cast<V*>(ldsr + y * 2 * S::P2 + x) = r;
   }
   __syncthreads();
-  {
-    const int grp = threadIdx.x / S::TPPX, t = threadIdx.x % S::TPPX;
-#pragma unroll 1
-    for (int r0 = 0; r0 < NY; r0 += S::GX) {
-      const int row = r0 + grp;
-      const bool act = grp < S::GX && row < NY;
-      rows_r2c_lds<T, S::M, 1, S::P2>(lds, 0, act ? row : 0, t, act, twx, rtw);
-    }
-  }
-  slab_cols<T, NX, NY, -1>(lds, twy);
-  cplx<T>* dst = spec + field * nspec + (int64_t)z * NY * S::XH;
-  for (int v = threadIdx.x; v < NY * S::XH; v += S::NT) {
-    const int y = v / S::XH, k = v - y * S::XH;
-    dst[v] = lds[y * S::P2 + k];
-  }
+  slab_forward_store<T, NX, NY>(lds, spec + field * nspec + (int64_t)z * NY * S::XH, twx, twy, rtw);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -323,7 +394,7 @@ hipError_t launch_slab_local(const Geom& g, const DevTables<T>& tb, const Stokes
 #define CASE(N)                                                                                \
   case N: {                                                                                    \
     using S = SlabCfg<T, N, N>;                                                                \
-    hipLaunchKernelGGL((k_slab_local<T, N, N>), grid, dim3(S::NT), S::LDS_BYTES, s, one, many,  \
+    ACM_LAUNCH((k_slab_local<T, N, N, false>), grid, dim3(S::NT), S::LDS_BYTES, s, one, many,  \
                        green_blocks, g.ntot, g.nspec, ct + tb.off.tw_x, ct + tb.off.tw_y,      \
                        ct + tb.off.rtw);                                                       \
     return hipGetLastError();                                                                  \
@@ -344,8 +415,54 @@ hipError_t launch_slab_rhs(const Geom& g, const DevTables<T>& tb, const StokesCe
 #define CASE(N)                                                                                \
   case N: {                                                                                    \
     using S = SlabCfg<T, N, N>;                                                                \
-    hipLaunchKernelGGL((k_slab_rhs<T, N, N>), grid, dim3(S::NT), S::LDS_BYTES, s, one, many,    \
+    ACM_LAUNCH((k_slab_rhs<T, N, N>), grid, dim3(S::NT), S::LDS_BYTES, s, one, many,    \
                        g.ntot, g.nspec, ct + tb.off.tw_x, ct + tb.off.tw_y, ct + tb.off.rtw);  \
+    return hipGetLastError();                                                                  \
+  }
+    ACM_SLAB_LENGTHS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+int slab_fused_capacity(const Geom& g) {
+  if (!slab_supported<T>(g)) return 0;
+  int dev = 0, ncu = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (g.nx) {
+#define CASE(N)                                                                                \
+  case N: {                                                                                    \
+    using S = SlabCfg<T, N, N>;                                                                \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(                                          \
+        &per_cu, reinterpret_cast<const void*>(&k_slab_local<T, N, N, true>), S::NT,           \
+        S::LDS_BYTES);                                                                         \
+    break;                                                                                     \
+  }
+    ACM_SLAB_LENGTHS(CASE)
+#undef CASE
+    default:
+      return 0;
+  }
+  if (e != hipSuccess) return 0;
+  return per_cu * ncu;
+}
+
+template <typename T>
+hipError_t launch_slab_fused(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
+                             int green_blocks, hipStream_t s) {
+  const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
+  dim3 grid((unsigned)g.nz, (unsigned)g.dim, 1u);
+  switch (g.nx) {
+#define CASE(N)                                                                                \
+  case N: {                                                                                    \
+    using S = SlabCfg<T, N, N>;                                                                \
+    ACM_LAUNCH((k_slab_local<T, N, N, true>), grid, dim3(S::NT), S::LDS_BYTES, s, one,  \
+                       nullptr, green_blocks, g.ntot, g.nspec, ct + tb.off.tw_x,               \
+                       ct + tb.off.tw_y, ct + tb.off.rtw);                                     \
     return hipGetLastError();                                                                  \
   }
     ACM_SLAB_LENGTHS(CASE)
@@ -357,6 +474,9 @@ hipError_t launch_slab_rhs(const Geom& g, const DevTables<T>& tb, const StokesCe
 
 #define INST(T)                                                                                \
   template bool slab_supported<T>(const Geom&);                                                \
+  template int slab_fused_capacity<T>(const Geom&);                                            \
+  template hipError_t launch_slab_fused<T>(const Geom&, const DevTables<T>&,                   \
+                                           const StokesCellArgs&, int, hipStream_t);           \
   template int slab_local_blocks<T>(const Geom&);                                              \
   template hipError_t launch_slab_local<T>(const Geom&, const DevTables<T>&,                   \
                                            const StokesCellArgs&, const StokesCellArgs*, int,   \

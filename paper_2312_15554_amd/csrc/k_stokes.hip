@@ -480,11 +480,11 @@ static hipError_t green_launch(const Geom& g, const DevTables<T>& tb, const Stok
   const int nb = (int)((g.plane + C::TX - 1) / C::TX);
   if (nblocks) *nblocks = nb;
   if constexpr (REG)
-    hipLaunchKernelGGL((k_stokes_green_reg<T, LL, NC, VAR>), dim3(nb, 1, ncells), dim3(C::NT),
+    ACM_LAUNCH((k_stokes_green_reg<T, LL, NC, VAR>), dim3(nb, 1, ncells), dim3(C::NT),
                        C::LDS_BYTES, s, one, many, gg, tw, rt + tb.off.sx, rt + tb.off.lx,
                        rt + tb.off.sy, rt + tb.off.ly, rt + tb.off.sz, rt + tb.off.lz);
   else
-    hipLaunchKernelGGL((k_stokes_green<T, LL, NC, VAR, SPL>), dim3(nb, 1, ncells), dim3(C::NT),
+    ACM_LAUNCH((k_stokes_green<T, LL, NC, VAR, SPL>), dim3(nb, 1, ncells), dim3(C::NT),
                        C::LDS_BYTES, s, one, many, gg, tw, rt + tb.off.sx, rt + tb.off.lx,
                        rt + tb.off.sy, rt + tb.off.ly, rt + tb.off.sz, rt + tb.off.lz);
   return hipGetLastError();
@@ -535,7 +535,7 @@ hipError_t launch_stokes_local(const Geom& g, const DevTables<T>& tb, const Stok
   case M: {                                                                                   \
     using C = RowCfg<T, M>;                                                                   \
     dim3 grid((unsigned)((g.nrows + C::RB - 1) / C::RB), (unsigned)g.dim, (unsigned)ncells);  \
-    hipLaunchKernelGGL((k_stokes_local<T, M>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many,  \
+    ACM_LAUNCH((k_stokes_local<T, M>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many,  \
                        green_blocks, (int)g.nrows, g.ntot, g.nspec, ct + tb.off.tw_x,         \
                        ct + tb.off.rtw);                                                      \
     return hipGetLastError();                                                                 \
@@ -556,7 +556,7 @@ hipError_t launch_stokes_rhs(const Geom& g, const DevTables<T>& tb, const Stokes
   case M: {                                                                                   \
     using C = RowCfg<T, M>;                                                                   \
     dim3 grid((unsigned)((g.nrows + C::RB - 1) / C::RB), (unsigned)g.dim, (unsigned)ncells);  \
-    hipLaunchKernelGGL((k_stokes_rhs<T, M>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many,    \
+    ACM_LAUNCH((k_stokes_rhs<T, M>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many,    \
                        (int)g.nrows, g.ntot, g.nspec, ct + tb.off.tw_x, ct + tb.off.rtw);     \
     return hipGetLastError();                                                                 \
   }

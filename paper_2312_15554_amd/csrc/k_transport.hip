@@ -271,7 +271,7 @@ hipError_t launch_transport_green(const Geom& g, const DevTables<T>& tb, int mod
   {                                                                                          \
     using C = ColCfg<T, LL, DD + 1>;                                                         \
     const int nb = (int)((g.plane + C::TX - 1) / C::TX);                                     \
-    hipLaunchKernelGGL((k_transport_green<T, LL, DD, MM>), dim3(nb), dim3(C::NT),            \
+    ACM_LAUNCH((k_transport_green<T, LL, DD, MM>), dim3(nb), dim3(C::NT),            \
                        C::LDS_BYTES, s, sp, cp, cm, partials, ctl, gg, tw, rt + tb.off.sx,    \
                        rt + tb.off.lx, rt + tb.off.sy, rt + tb.off.ly, rt + tb.off.sz,       \
                        rt + tb.off.lz);                                                      \
@@ -304,7 +304,7 @@ hipError_t launch_transport_local(const Geom& g, const DevTables<T>& tb, void* s
   {                                                                                           \
     using C = RowCfgN<T, MM, DD + 1>;                                                         \
     dim3 grid((unsigned)((g.nrows + C::RB - 1) / C::RB));                                     \
-    hipLaunchKernelGGL((k_transport_local<T, MM, DD>), grid, dim3(C::NT), C::LDS_BYTES, s, sp, \
+    ACM_LAUNCH((k_transport_local<T, MM, DD>), grid, dim3(C::NT), C::LDS_BYTES, s, sp, \
                        u, H, ctl, (int)g.nrows, g.ntot, g.nspec, ct + tb.off.tw_x,            \
                        ct + tb.off.rtw);                                                      \
   }

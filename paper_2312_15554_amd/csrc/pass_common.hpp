@@ -2,10 +2,27 @@
 // x rows held in LDS, and the column (strided pencil) tile mapping used by the
 // y and z passes.
 #pragma once
+#include <hip/hip_ext.h>
+
 #include "acm_internal.hpp"
 #include "fft_core.hpp"
 
 namespace acm {
+
+// Kernel launch used by every pass: in the profiling mode (launch_events()
+// armed) the dispatch itself records its start and end; otherwise a plain
+// launch.
+#define ACM_LAUNCH(KERNEL, GRID, BLOCK, SHMEM, STREAM, ...)                                      \
+  do {                                                                                           \
+    ::acm::LaunchEvents& le_ = ::acm::launch_events();                                           \
+    if (le_.start) {                                                                             \
+      hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, le_.start, le_.stop, 0,          \
+                            __VA_ARGS__);                                                        \
+      le_ = ::acm::LaunchEvents{};                                                               \
+    } else {                                                                                     \
+      hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);                      \
+    }                                                                                            \
+  } while (0)
 
 // Supported lengths.  Row kernels take the complex half length M = nx/2,
 // column kernels the full axis length.

@@ -203,24 +203,45 @@ struct DevBuf {
 };
 
 // Timing of eager launches with HIP events, per kernel kind.
+LaunchEvents& launch_events() {
+  static thread_local LaunchEvents e;
+  return e;
+}
+
+// Per-kind kernel times of the profiling mode.  begin() arms launch_events()
+// with a fresh event pair, so the next ACM_LAUNCH times its own kernel; end()
+// keeps the pair if that launch consumed it.
 struct Profiler {
   bool on = false;
   hipStream_t s = nullptr;
   double ms[KK_COUNT] = {0};
   int64_t calls[KK_COUNT] = {0};
   std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> ev;
+  hipEvent_t armed_stop = nullptr;
   void begin(int kind, hipEvent_t* a) {
-    if (!on) return;
-    (void)hipEventCreate(a);
-    (void)hipEventRecord(*a, s);
     (void)kind;
+    *a = nullptr;
+    if (!on) return;
+    hipEvent_t b = nullptr;
+    if (hipEventCreate(a) != hipSuccess) return;
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(*a);
+      *a = nullptr;
+      return;
+    }
+    armed_stop = b;
+    launch_events() = LaunchEvents{*a, b};
   }
   void end(int kind, hipEvent_t a) {
-    if (!on) return;
-    hipEvent_t b;
-    (void)hipEventCreate(&b);
-    (void)hipEventRecord(b, s);
-    ev.emplace_back(kind, a, b);
+    if (!on || !a) return;
+    LaunchEvents& le = launch_events();
+    if (le.start == a) {  // not consumed: the launch did not go through ACM_LAUNCH
+      (void)hipEventDestroy(le.start);
+      (void)hipEventDestroy(le.stop);
+      le = LaunchEvents{};
+      return;
+    }
+    ev.emplace_back(kind, a, armed_stop);
   }
   void collect() {
     for (auto& x : ev) {
@@ -289,6 +310,7 @@ struct StokesGroup {
   CellPlan* pl = nullptr;
   std::vector<int> cells;  // indices into the call's cell list
   bool slab = false;
+  bool fused = false;    // slab local + rhs in one launch (single resident cell)
   int green_var = 0;     // tile variant of the green pass
   int ngreen = 0;        // green workgroups per cell for that variant
   int ngreen_max = 0;    // partial-buffer capacity (largest variant)
@@ -325,6 +347,13 @@ static hipError_t enqueue_iteration(StokesGroup<T>& G, hipStream_t s, Profiler* 
   e = launch_stokes_green<T>(g, tb, one, many, n, G.green_var, nullptr, s);
   if (e != hipSuccess) return e;
   prof->end(KK_GREEN, ev0);
+  if (G.fused) {
+    prof->begin(KK_LOCAL, &ev0);
+    e = launch_slab_fused<T>(g, tb, one, G.ngreen, s);
+    if (e != hipSuccess) return e;
+    prof->end(KK_LOCAL, ev0);
+    return hipSuccess;
+  }
   if (G.slab) {
     prof->begin(KK_LOCAL, &ev0);
     e = launch_slab_local<T>(g, tb, one, many, n, G.ngreen, s);
@@ -393,12 +422,20 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
     bool aligned = true;
     for (int i : G.cells)
       aligned = aligned && ((uintptr_t)cells[i].u % 32 == 0) && ((uintptr_t)cells[i].H % 16 == 0);
-    if (o.pass_mode == 2) {
+    if (o.pass_mode == 2 || o.pass_mode == 3) {
       if (!(slab_supported<T>(g) && aligned))
         return fail(ACM_E_INVALID,
                     "fused xy passes need a 3D cell with nx == ny <= 128 and aligned u, H");
+      const bool one_cell = groups.size() == 1 && G.cells.size() == 1;
+      if (o.pass_mode == 3 && !(one_cell && slab_fused_capacity<T>(g) >= g.nz * g.dim))
+        return fail(ACM_E_INVALID,
+                    "the single-launch slab pass needs one cell whose nz * 3 workgroups are all "
+                    "resident on the device at once");
       G.slab = true;
+      G.fused = o.pass_mode == 3;
     } else if (o.pass_mode == 0) {
+      // the single-launch structure is not chosen automatically: its
+      // device-wide gate has measured slower than the launch boundary
       G.slab = slab_supported<T>(g) && aligned;
     }
     G.nlocal = std::max(G.pl->local_blocks, slab_local_blocks<T>(g));
@@ -692,6 +729,10 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
   }
   HIP_TRY(hipStreamSynchronize(s));
   const double total_s = std::chrono::duration<double>(t1 - t0).count();
+  for (int i = 0; i < ncell; ++i)
+    if (hctl[i].fault)
+      return fail(ACM_E_HIP, "the single-launch slab pass gave up waiting at its device-wide gate "
+                             "(its workgroups were not all resident)");
   int worst = 0;
   for (int i = 0; i < ncell; ++i) {
     const StokesCtl& c = hctl[i];
@@ -747,7 +788,7 @@ static acm_status check_stokes_cell(const acm_grid* grid, const uint8_t* H, cons
 static acm_status check_penalty_opts(const acm_penalty& P, const acm_opts& O, double nu) {
   if (!(nu > 0.0) || !isfinite(nu)) return fail(ACM_E_INVALID, "nu must be positive");
   if (!(O.eps >= 0.0) || O.max_iter < 1) return fail(ACM_E_INVALID, "eps >= 0 and max_iter >= 1 required");
-  if (O.pass_mode < 0 || O.pass_mode > 2) return fail(ACM_E_INVALID, "pass_mode must be 0, 1 or 2");
+  if (O.pass_mode < 0 || O.pass_mode > 3) return fail(ACM_E_INVALID, "pass_mode must be 0, 1, 2 or 3");
   if (O.green_variant < 0 || O.green_variant > kGreenVariants)
     return fail(ACM_E_INVALID, "green_variant must be in [0, " + std::to_string(kGreenVariants) + "]");
   for (int k = 0; k < 3; ++k)

@@ -48,10 +48,11 @@ def test_fixed_penalty_iterates_match_oracle(shape, dtype):
 @pytest.mark.gpu
 @pytest.mark.parametrize("shape", SLAB_SHAPES)
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("pass_mode", [1, 2])
+@pytest.mark.parametrize("pass_mode", [1, 2, 3])
 def test_fused_and_separate_passes_match_oracle(shape, dtype, pass_mode):
-    """Both 3D pass structures (separate x/y passes and fused xy slabs)
-    reproduce the oracle's iterates with fixed penalties."""
+    """All 3D pass structures (separate x/y passes, fused xy slabs, and fused
+    slabs with local and rhs in one launch) reproduce the oracle's iterates
+    with fixed penalties."""
     require_gpu()
     print(f"pass parity shape={shape} dtype={dtype} mode={pass_mode}", flush=True)
     H = I.overlapping_spheres(shape, shape[-1] / 16.0, 0.5, seed=5)
@@ -201,7 +202,8 @@ def test_c1_model_cell_matches_oracle(dtype):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("shape,pass_mode", [((16, 16), 0), ((16, 32, 32), 1), ((16, 32, 32), 2)])
+@pytest.mark.parametrize("shape,pass_mode", [((16, 16), 0), ((16, 32, 32), 1), ((16, 32, 32), 2),
+                                              ((16, 32, 32), 3)])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_warm_start_iterates_match_oracle(shape, pass_mode, dtype):
     """Warm start (u0 = (1-H) u_in, q0 = q_in, a0 = lambda0 = H (g - grad q0 +
@@ -222,3 +224,75 @@ def test_warm_start_iterates_match_oracle(shape, pass_mode, dtype):
     tol = 1e-11 if dtype == torch.float64 else 3e-5
     assert np.abs(host(r["u"]) - o["u"]).max() < tol * np.abs(o["u"]).max()
     assert np.abs(host(r["q"]) - o["q"]).max() < tol * 10 * np.abs(o["q"]).max()
+
+
+@pytest.mark.gpu
+def test_single_launch_slab_pass_equals_two_launches_at_full_size():
+    """128^3 overlapping-sphere cell (porosity 0.40, the timed workload), FP32,
+    adaptive penalties: 120 iterations with local and rhs in one launch give
+    the same iterates, residuals and penalties as the two-launch slab path."""
+    require_gpu()
+    n = 128
+    print("single-launch vs two-launch slab passes, 128^3", flush=True)
+    H = dev(I.overlapping_spheres(n, 8.0, 0.40, seed=1))
+    kw = dict(penalty=dict(tau=(5.0, 10.0, 5.0)), eps=0.0, max_iter=120, want_q=True)
+    r2 = _solve_dev(H, (1.0, 0.0, 0.0), pass_mode=2, **kw)
+    r3 = _solve_dev(H, (1.0, 0.0, 0.0), pass_mode=3, **kw)
+    assert r2["stats"]["iters"] == r3["stats"]["iters"] == 120
+    assert r2["stats"]["psi"] == r3["stats"]["psi"]
+    for k in range(3):
+        assert abs(r2["stats"]["r_p"][k] - r3["stats"]["r_p"][k]) <= 1e-6 * r2["stats"]["r_p"][k]
+        assert abs(r2["stats"]["r_d"][k] - r3["stats"]["r_d"][k]) <= 1e-6 * r2["stats"]["r_d"][k]
+    du = (r2["u"] - r3["u"]).abs().max().item()
+    assert du <= 1e-6 * r2["u"].abs().max().item()
+    dq = (r2["q"] - r3["q"]).abs().max().item()
+    assert dq <= 1e-6 * r2["q"].abs().max().item()
+
+
+@pytest.mark.gpu
+def test_single_launch_slab_pass_rejects_batches():
+    """pass_mode 3 needs a single resident cell: a batch of two is refused."""
+    require_gpu()
+    from paper_2312_15554_amd import abi
+    from paper_2312_15554_amd.api import acm_stokes_solve_batched
+    Hs = [dev(I.overlapping_spheres(32, 2.0, 0.5, seed=s)) for s in (3, 4)]
+    with pytest.raises(abi.AcmError) as e:
+        acm_stokes_solve_batched(Hs, [(1.0, 0.0, 0.0)] * 2, eps=1e-5, max_iter=100, pass_mode=3)
+    assert e.value.status == abi.ACM_E_INVALID
+
+
+def _solve_dev(H, g, **kw):
+    from paper_2312_15554_amd.api import acm_stokes_solve
+    return acm_stokes_solve(H, g, **kw)
+
+
+@pytest.mark.gpu
+def test_full_size_converged_solve_satisfies_its_residuals():
+    """The timed workload (128^3 overlapping spheres, porosity 0.40, FP32,
+    eps = 1e-6, random-geometry penalty schedule, default pass structure)
+    converges, and the residuals the device reports are those of the returned
+    fields recomputed on the host with the oracle's operators: the central
+    divergence (r_p[1]) and the solid velocity scaled by b/(b+alpha) (r_p[0]),
+    both within the tolerances; K from acm_effective_props equals the oracle's
+    Darcy average of the same field."""
+    require_gpu()
+    from paper_2312_15554_amd.api import acm_effective_props
+    n = 128
+    print("full-size converged solve, 128^3", flush=True)
+    H_np = I.overlapping_spheres(n, 8.0, 0.40, seed=1)
+    H = dev(H_np)
+    r = _solve_dev(H, (1.0, 0.0, 0.0), penalty=dict(tau=(5.0, 10.0, 5.0)), eps=1e-6,
+                   max_iter=20000, want_q=False)
+    st = r["stats"]
+    assert st["converged"] and 1500 < st["iters"] < 5000
+    u = host(r["u"]).astype(np.float64)
+    div = np.sqrt(np.sum(O.central_div(u) ** 2))
+    assert abs(div - st["r_p"][1]) <= 2e-2 * st["r_p"][1] + 1e-7
+    assert div <= 1.05 * st["tol_p"][1]
+    al, b = st["psi"][0], st["psi"][2]
+    solid = np.sqrt(np.sum((u * H_np[None]) ** 2)) * b / (b + al)
+    assert abs(solid - st["r_p"][0]) <= 1e-3 * st["r_p"][0]
+    assert solid <= 1.001 * st["tol_p"][0]
+    K = acm_effective_props(H, [r["u"]], nu=1.0)["K"]
+    Ko = O.permeability_darcy([u])
+    assert np.max(np.abs(np.array(K) - Ko)) <= 1e-9 * np.max(np.abs(Ko))
