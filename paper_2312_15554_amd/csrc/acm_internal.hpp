@@ -33,29 +33,42 @@ struct TableOffsets {
   int nreal;
 };
 
-// Device control block for one ADMM solve.  Written by the host before the
-// first iteration; afterwards only the finalize step (last workgroup of the
-// local pass) changes it.
+// ADMM state that changes every iteration.  A solve keeps two slots: the
+// passes of iteration n read slot n mod 2 and Step 4 of iteration n writes
+// slot (n + 1) mod 2, so no pass ever reads a slot that the same launch is
+// writing.  The parity is a kernel argument.
+struct StokesState {
+  double psi[3];      // alpha, beta, b of the iteration that reads this slot
+  double c_prev;      // b/(b+alpha) of the iteration before it
+  double rp[3], rd[3], tp[3], td[3], mu[3];  // residuals of the iteration that wrote it
+  int64_t iter;       // iterations completed
+  int32_t done;       // sticky: once set in either slot every pass exits at once
+  int32_t status;     // 0 ok, 1 not converged, -5 diverged
+};
+
+// Device control block for one ADMM solve: constant parameters written by the
+// host, the two state slots, and the words of the cross-workgroup protocols.
 struct StokesCtl {
-  double psi[3];      // alpha, beta, b of the current iteration
-  double c_prev;      // b/(b+alpha) of the previous iteration
   double phi[3], tau[3], psi_min[3];
   double eps;
   double sqrt_n[3];   // sqrt(d N), sqrt(N), sqrt(d N)
   double nu;
   double g[3];
-  double rp[3], rd[3], tp[3], td[3], mu[3];
-  int64_t iter;
   int64_t max_iter;
-  int32_t done;
-  int32_t status;     // 0 ok, 1 not converged, -5 diverged
   int32_t adaptive;
-  uint32_t counter;   // workgroups of the local pass that have finished
   int32_t hist_cap;   // capacity of the residual history ring (entries)
-  uint32_t gate;      // fused slab pass: generations of its device-wide gate
-  int32_t fault;      // non-zero: a fused-pass gate wait exceeded its bound
+  int32_t fault;      // non-zero: a single-launch slab pass gave up at its gate
   int32_t pad_;
+  StokesState st[2];
+  // Words that many workgroups hit at once sit on cache lines of their own,
+  // away from the parameters every workgroup reads when it starts.
+  alignas(256) uint32_t counter;  // workgroups of a local pass that have finished
+  alignas(256) uint32_t gate;     // single-launch slab pass: gate generations
 };
+
+__host__ __device__ inline bool stokes_done(const StokesCtl* c) {
+  return (c->st[0].done | c->st[1].done) != 0;
+}
 
 // One history record per iteration: rp[3], rd[3], tp[3], td[3], psi[3].
 constexpr int kHistDoubles = 15;
@@ -86,8 +99,8 @@ struct TransportCtl {
   int64_t max_iter;
   int32_t done;
   int32_t status;
-  uint32_t counter;
   int32_t steady;
+  alignas(256) uint32_t counter;  // on its own cache line (see StokesCtl)
 };
 
 // Per-cell device pointers of one Stokes solve.  Kernels of a batched launch
@@ -108,7 +121,8 @@ struct StokesCellArgs {
 // Per-cell pointers of a column (y or z) transform.
 struct ColCellArgs {
   void* data;
-  const int32_t* skip;  // may be null; when *skip != 0 the cell is skipped
+  const int32_t* skip;   // may be null; when *skip != 0 the cell is skipped
+  const int32_t* skip2;  // a second such flag (the other state slot), may be null
 };
 
 enum KernelKind {
@@ -144,10 +158,12 @@ template <typename T>
 hipError_t launch_rows_c2r(const Geom& g, const DevTables<T>& tb, int nfields, const void* in,
                            T* out, double scale, hipStream_t s);
 // Complex transform along y (axis 1) or z (axis 2) of nfields half spectra, in place.
-// `skip` (may be null): device flag; when non-zero the launch does nothing.
+// `skip`, `skip2` (each may be null): device flags; when either is non-zero the
+// launch does nothing.
 template <typename T>
 hipError_t launch_cols(const Geom& g, const DevTables<T>& tb, int axis, int sign, int nfields,
-                       void* data, hipStream_t s, const int32_t* skip = nullptr);
+                       void* data, hipStream_t s, const int32_t* skip = nullptr,
+                       const int32_t* skip2 = nullptr);
 // Batched form: cells[0..ncells) (device array) with one transform each.
 template <typename T>
 hipError_t launch_cols_batched(const Geom& g, const DevTables<T>& tb, int axis, int sign,
@@ -162,17 +178,21 @@ hipError_t launch_cols_batched(const Geom& g, const DevTables<T>& tb, int axis, 
 // the number of workgroups per cell (= partial-sum records written).
 constexpr int kGreenVariants = 7;
 
+// `par`: parity of the iteration (the state slot its passes read).  The row
+// local pass runs Step 4 in its last workgroup and writes slot par ^ 1; the row
+// rhs pass reads the slot given as `slot` (par ^ 1 within the iteration, the
+// initial slot for the right-hand side of a warm start).
 template <typename T>
 hipError_t launch_stokes_green(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
-                               const StokesCellArgs* many, int ncells, int variant, int* nblocks,
-                               hipStream_t s);
+                               const StokesCellArgs* many, int ncells, int par, int variant,
+                               int* nblocks, hipStream_t s);
 template <typename T>
 hipError_t launch_stokes_local(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
-                               const StokesCellArgs* many, int ncells, int green_blocks,
+                               const StokesCellArgs* many, int ncells, int par, int green_blocks,
                                hipStream_t s);
 template <typename T>
 hipError_t launch_stokes_rhs(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
-                             const StokesCellArgs* many, int ncells, hipStream_t s);
+                             const StokesCellArgs* many, int ncells, int slot, hipStream_t s);
 
 // Lippmann-Schwinger passes.  mode 0: LS update; mode 1: grad chi-hat only.
 template <typename T>
@@ -204,13 +224,17 @@ template <typename T>
 bool slab_supported(const Geom& g);
 template <typename T>
 int slab_local_blocks(const Geom& g);
+// The slab local pass only posts its partial sums; every workgroup of the
+// slab rhs pass then forms Step 4 itself from all partials (the same bits in
+// each), and workgroup 0 stores the new state in slot par ^ 1 (step4 = 1).
+// With step4 = 0 the rhs pass uses slot par as it is (warm-start set-up).
 template <typename T>
 hipError_t launch_slab_local(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
-                             const StokesCellArgs* many, int ncells, int green_blocks,
-                             hipStream_t s);
+                             const StokesCellArgs* many, int ncells, int par, hipStream_t s);
 template <typename T>
 hipError_t launch_slab_rhs(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
-                           const StokesCellArgs* many, int ncells, hipStream_t s);
+                           const StokesCellArgs* many, int ncells, int par, int step4,
+                           int green_blocks, hipStream_t s);
 // Local and rhs slab passes of one cell in a single launch: every workgroup
 // runs the local pass, waits at a device-wide gate that the last one opens
 // after Step 4, then runs the rhs pass on the slab still held in LDS.  Valid
@@ -220,7 +244,7 @@ template <typename T>
 int slab_fused_capacity(const Geom& g);
 template <typename T>
 hipError_t launch_slab_fused(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
-                             int green_blocks, hipStream_t s);
+                             int par, int green_blocks, hipStream_t s);
 
 // FNO kernels (k_fno.hip).
 hipError_t fno_lift(const uint8_t* H, const uint16_t* Pw, const uint16_t* Pb, float* v, int C,

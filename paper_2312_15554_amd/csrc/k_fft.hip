@@ -75,7 +75,7 @@ __global__ __launch_bounds__((ColCfg<T, L, 1>::NT)) void k_cols(ColCellArgs one,
                                                               const cplx<T>* __restrict__ tw) {
   using C = ColCfg<T, L, 1>;
   const ColCellArgs ca = many ? many[blockIdx.z] : one;
-  if (ca.skip != nullptr && *ca.skip) return;
+  if ((ca.skip != nullptr && *ca.skip) || (ca.skip2 != nullptr && *ca.skip2)) return;
   cplx<T>* data = reinterpret_cast<cplx<T>*>(ca.data);
   extern __shared__ __align__(16) char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -187,15 +187,15 @@ static hipError_t cols_impl(const Geom& g, const DevTables<T>& tb, int axis, int
 
 template <typename T>
 hipError_t launch_cols(const Geom& g, const DevTables<T>& tb, int axis, int sign, int nfields,
-                       void* data, hipStream_t s, const int32_t* skip) {
-  ColCellArgs one{data, skip};
+                       void* data, hipStream_t s, const int32_t* skip, const int32_t* skip2) {
+  ColCellArgs one{data, skip, skip2};
   return cols_impl<T>(g, tb, axis, sign, nfields, one, nullptr, 1, s);
 }
 
 template <typename T>
 hipError_t launch_cols_batched(const Geom& g, const DevTables<T>& tb, int axis, int sign,
                                int nfields, const ColCellArgs* cells, int ncells, hipStream_t s) {
-  ColCellArgs one{nullptr, nullptr};
+  ColCellArgs one{nullptr, nullptr, nullptr};
   return cols_impl<T>(g, tb, axis, sign, nfields, one, cells, ncells, s);
 }
 
@@ -205,7 +205,7 @@ hipError_t launch_cols_batched(const Geom& g, const DevTables<T>& tb, int axis, 
   template hipError_t launch_rows_c2r<T>(const Geom&, const DevTables<T>&, int, const void*, \
                                          T*, double, hipStream_t);                           \
   template hipError_t launch_cols<T>(const Geom&, const DevTables<T>&, int, int, int, void*, \
-                                     hipStream_t, const int32_t*);                           \
+                                     hipStream_t, const int32_t*, const int32_t*);           \
   template hipError_t launch_cols_batched<T>(const Geom&, const DevTables<T>&, int, int, int, \
                                              const ColCellArgs*, int, hipStream_t);
 INST(float)

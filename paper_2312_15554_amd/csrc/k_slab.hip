@@ -52,11 +52,16 @@ struct SlabCfg {
   static constexpr int QPT = (NQ + NT - 1) / NT;          // quads per thread
   static constexpr bool FULL = (NQ % NT) == 0;
   static constexpr int UNR = QPT;
+  // loads in flight per thread when the rhs pass sums the partials (its state
+  // loads are already in registers then)
+  static constexpr int SUM_U = 4;
   // Waves per SIMD that let as many workgroups reside per CU as LDS allows
   // (CDNA: 4 SIMDs and 160 KB of LDS per CU; at most 4 workgroups counted):
   // the minimum occupancy requested from the register allocator.
   static constexpr int BLK_LDS = (160 * 1024) / (LDS_BYTES + 1024);
   static constexpr int WPE = cmax(1, cmin(8, (cmin(BLK_LDS, 4) * (NT / 64) + 3) / 4));
+  // the single-launch pass keeps more state in registers: two workgroups
+  static constexpr int WPE_ONE = cmax(1, cmin(8, (cmin(BLK_LDS, 2) * (NT / 64) + 3) / 4));
 };
 
 // y transform of all XH columns of the slab held in LDS ([y][k], pitch P2).
@@ -106,10 +111,11 @@ constexpr uint32_t kGatePolls = 1u << 22;
 // launch (FUSED = true, a single cell, every workgroup resident).
 template <typename T, int NX, int NY, bool FUSED>
 __global__ __launch_bounds__((SlabCfg<T, NX, NY>::NT))
-__attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_local(
-    StokesCellArgs one, const StokesCellArgs* __restrict__ many, int ngreen, int64_t ntot,
-    int64_t nspec, const cplx<T>* __restrict__ twx, const cplx<T>* __restrict__ twy,
-    const cplx<T>* __restrict__ rtw) {
+__attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
+                                          : SlabCfg<T, NX, NY>::WPE))) void k_slab_local(
+    StokesCellArgs one, const StokesCellArgs* __restrict__ many, int par, int ngreen,
+    int64_t ntot, int64_t nspec, const cplx<T>* __restrict__ twx,
+    const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__ rtw) {
   using S = SlabCfg<T, NX, NY>;
   const StokesCellArgs ca = many ? many[blockIdx.z] : one;
   cplx<T>* __restrict__ spec = reinterpret_cast<cplx<T>*>(ca.spec);
@@ -127,11 +133,12 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_local(
   __shared__ int s_last, s_go;
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   T* ldsr = reinterpret_cast<T*>(smem_raw);
-  if (ctl->done) return;
+  if (stokes_done(ctl)) return;
   const uint32_t gate0 = FUSED ? ctl->gate : 0u;  // read before this workgroup arrives
-  const double al = ctl->psi[0], bb = ctl->psi[2];
+  const StokesState& cur = ctl->st[par];
+  const double al = cur.psi[0], bb = cur.psi[2];
   const T cc = (T)(bb / (bb + al));
-  const T cp = (T)ctl->c_prev;
+  const T cp = (T)cur.c_prev;
   const T ka = (T)(bb * al / (bb + al));
   const int z = blockIdx.x, field = blockIdx.y;
 
@@ -236,6 +243,17 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_local(
   block_sum<4>(acc, red);
   const int nblk = gridDim.x * gridDim.y;
   const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+  if constexpr (!FUSED) {
+    // Step 4 is formed by the rhs pass from these partials after the launch
+    // boundary: no cross-workgroup traffic here
+    if (threadIdx.x == 0) {
+      lpart[bid * 4 + 0] = acc[0];
+      lpart[bid * 4 + 1] = acc[1];
+      lpart[bid * 4 + 2] = acc[2];
+      lpart[bid * 4 + 3] = acc[3];
+    }
+    return;
+  }
   if (threadIdx.x == 0) {
     lpart[bid * 4 + 0] = acc[0];
     lpart[bid * 4 + 1] = acc[1];
@@ -248,7 +266,7 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_local(
   __syncthreads();
   if (s_last) {
     __threadfence();
-    stokes_finalize(ctl, gpart, ngreen, lpart, nblk, ntot, hist, red7);
+    stokes_finalize(ctl, par, gpart, ngreen, lpart, nblk, ntot, hist, red7);
   }
   if constexpr (FUSED) {
     // ---- device-wide gate: the last workgroup opens it after Step 4
@@ -260,7 +278,7 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_local(
       } else {
         uint32_t polls = 0;
         while (__hip_atomic_load(&ctl->gate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gate0) {
-          __builtin_amdgcn_s_sleep(2);
+          __builtin_amdgcn_s_sleep(8);
           if (++polls == kGatePolls) {
             go = 0;
             break;
@@ -268,10 +286,11 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_local(
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
+      StokesState* nx = &ctl->st[par ^ 1];
       if (!go) {
         __hip_atomic_store(&ctl->fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&ctl->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      } else if (__hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        __hip_atomic_store(&nx->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else if (__hip_atomic_load(&nx->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
         go = 0;  // converged (or stopped) at this iteration: no next rhs
       }
       s_go = go;
@@ -279,8 +298,9 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_local(
     __syncthreads();
     if (!s_go) return;
     // ---- rhs half: r = b^{n+1} ut^{n+1} - a^{n+1} on the slab in LDS
-    const double bnew = __hip_atomic_load(&ctl->psi[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const double cprev = __hip_atomic_load(&ctl->c_prev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const StokesState* nx = &ctl->st[par ^ 1];
+    const double bnew = __hip_atomic_load(&nx->psi[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const double cprev = __hip_atomic_load(&nx->c_prev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const T b1 = (T)bnew;
     const T bcp = (T)(bnew * cprev);
 #pragma unroll
@@ -305,56 +325,72 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_local(
 
 template <typename T, int NX, int NY>
 __global__ __launch_bounds__((SlabCfg<T, NX, NY>::NT))
-__attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_rhs(StokesCellArgs one,
-                                                  const StokesCellArgs* __restrict__ many,
-                                                  int64_t ntot, int64_t nspec,
-                                                  const cplx<T>* __restrict__ twx,
-                                                  const cplx<T>* __restrict__ twy,
-                                                  const cplx<T>* __restrict__ rtw) {
+__attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_rhs(
+    StokesCellArgs one, const StokesCellArgs* __restrict__ many, int par, int step4, int ngreen,
+    int64_t ntot, int64_t nspec, const cplx<T>* __restrict__ twx,
+    const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__ rtw) {
   using S = SlabCfg<T, NX, NY>;
   const StokesCellArgs ca = many ? many[blockIdx.z] : one;
   cplx<T>* __restrict__ spec = reinterpret_cast<cplx<T>*>(ca.spec);
   const T* __restrict__ u = reinterpret_cast<const T*>(ca.u);
   const T* __restrict__ a = reinterpret_cast<const T*>(ca.a);
   const uint8_t* __restrict__ H = ca.H;
-  const StokesCtl* __restrict__ ctl = ca.ctl;
+  StokesCtl* ctl = ca.ctl;
   using V = typename Vec4<T>::type;
   extern __shared__ __align__(32) char smem_raw[];
+  __shared__ double red7[7 * 16];
+  __shared__ double s_b, s_cp;
+  __shared__ int s_stop;
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   T* ldsr = reinterpret_cast<T*>(smem_raw);
-  if (ctl->done) return;
-  const T bb = (T)ctl->psi[2];
-  const T bcp = (T)(ctl->psi[2] * ctl->c_prev);
+  if (stokes_done(ctl)) return;
   const int z = blockIdx.x, field = blockIdx.y;
   const int64_t off = field * ntot + (int64_t)z * S::NV;
   const V* uq = reinterpret_cast<const V*>(u + off);
   const V* aq = reinterpret_cast<const V*>(a + off);
   const uint32_t* hq = reinterpret_cast<const uint32_t*>(H + (int64_t)z * S::NV);
-  // a vanishes in the pore, so r = (H ? b c : b) u - a needs no branch on H
-  // and every load is issued at once.
-  V uv[S::QPT], av[S::QPT];
-  uint32_t hw[S::QPT];
-#pragma unroll
-  for (int j = 0; j < S::QPT; ++j) {
-    const int q = threadIdx.x + j * S::NT;
-    hw[j] = 0u;
-    if (S::FULL || q < S::NQ) {
-      uv[j] = uq[q];
-      hw[j] = hq[q];
-      av[j] = aq[q];
+  // Step 4 of this iteration, formed from all partial sums by every
+  // workgroup (same order, same bits); workgroup 0 of the cell stores the new
+  // state in the other slot.  Without step4 the current slot is used as is.
+  if (step4) {
+    double tot[7];
+    stokes_sum_partials<S::SUM_U>(ca.part, ngreen, ca.lpart, gridDim.x * gridDim.y, tot, red7);
+    if (threadIdx.x == 0) {
+      const StokesState cur = ctl->st[par];
+      StokesState nx;
+      stokes_step4(ctl, cur, tot, ntot, nx);
+      if (blockIdx.x == 0 && blockIdx.y == 0) {
+        stokes_history(ctl, cur, nx, ca.hist);
+        ctl->st[par ^ 1] = nx;
+      }
+      s_b = nx.psi[2];
+      s_cp = nx.c_prev;
+      s_stop = nx.done;
     }
+  } else if (threadIdx.x == 0) {
+    s_b = ctl->st[par].psi[2];
+    s_cp = ctl->st[par].c_prev;
+    s_stop = 0;
   }
+  __syncthreads();
+  if (s_stop) return;
+  const T bb = (T)s_b;
+  const T bcp = (T)(s_b * s_cp);
+  // a vanishes in the pore, so r = (H ? b c : b) u - a needs no branch on H
+  // and every load of the loop can be issued at once.
 #pragma unroll
   for (int j = 0; j < S::QPT; ++j) {
     const int q = threadIdx.x + j * S::NT;
     if (!S::FULL && q >= S::NQ) continue;
     const int v = 4 * q;
     const int y = v / NX, x = v - y * NX;
+    const V uv = uq[q], av = aq[q];
+    const uint32_t hw = hq[q];
     V r;
-    r.x = ((hw[j] & 0xffu) ? bcp : bb) * uv[j].x - av[j].x;
-    r.y = ((hw[j] & 0xff00u) ? bcp : bb) * uv[j].y - av[j].y;
-    r.z = ((hw[j] & 0xff0000u) ? bcp : bb) * uv[j].z - av[j].z;
-    r.w = ((hw[j] & 0xff000000u) ? bcp : bb) * uv[j].w - av[j].w;
+    r.x = ((hw & 0xffu) ? bcp : bb) * uv.x - av.x;
+    r.y = ((hw & 0xff00u) ? bcp : bb) * uv.y - av.y;
+    r.z = ((hw & 0xff0000u) ? bcp : bb) * uv.z - av.z;
+    r.w = ((hw & 0xff000000u) ? bcp : bb) * uv.w - av.w;
     *reinterpret_cast<V*>(ldsr + y * 2 * S::P2 + x) = r;
   }
   __syncthreads();
@@ -386,8 +422,7 @@ int slab_local_blocks(const Geom& g) {
 
 template <typename T>
 hipError_t launch_slab_local(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
-                             const StokesCellArgs* many, int ncells, int green_blocks,
-                             hipStream_t s) {
+                             const StokesCellArgs* many, int ncells, int par, hipStream_t s) {
   const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
   dim3 grid((unsigned)g.nz, (unsigned)g.dim, (unsigned)ncells);
   switch (g.nx) {
@@ -395,8 +430,7 @@ hipError_t launch_slab_local(const Geom& g, const DevTables<T>& tb, const Stokes
   case N: {                                                                                    \
     using S = SlabCfg<T, N, N>;                                                                \
     ACM_LAUNCH((k_slab_local<T, N, N, false>), grid, dim3(S::NT), S::LDS_BYTES, s, one, many,  \
-                       green_blocks, g.ntot, g.nspec, ct + tb.off.tw_x, ct + tb.off.tw_y,      \
-                       ct + tb.off.rtw);                                                       \
+               par, 0, g.ntot, g.nspec, ct + tb.off.tw_x, ct + tb.off.tw_y, ct + tb.off.rtw);  \
     return hipGetLastError();                                                                  \
   }
     ACM_SLAB_LENGTHS(CASE)
@@ -408,15 +442,17 @@ hipError_t launch_slab_local(const Geom& g, const DevTables<T>& tb, const Stokes
 
 template <typename T>
 hipError_t launch_slab_rhs(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
-                           const StokesCellArgs* many, int ncells, hipStream_t s) {
+                           const StokesCellArgs* many, int ncells, int par, int step4,
+                           int green_blocks, hipStream_t s) {
   const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
   dim3 grid((unsigned)g.nz, (unsigned)g.dim, (unsigned)ncells);
   switch (g.nx) {
 #define CASE(N)                                                                                \
   case N: {                                                                                    \
     using S = SlabCfg<T, N, N>;                                                                \
-    ACM_LAUNCH((k_slab_rhs<T, N, N>), grid, dim3(S::NT), S::LDS_BYTES, s, one, many,    \
-                       g.ntot, g.nspec, ct + tb.off.tw_x, ct + tb.off.tw_y, ct + tb.off.rtw);  \
+    ACM_LAUNCH((k_slab_rhs<T, N, N>), grid, dim3(S::NT), S::LDS_BYTES, s, one, many, par,  \
+               step4, green_blocks, g.ntot, g.nspec, ct + tb.off.tw_x, ct + tb.off.tw_y,       \
+               ct + tb.off.rtw);                                                               \
     return hipGetLastError();                                                                  \
   }
     ACM_SLAB_LENGTHS(CASE)
@@ -453,7 +489,7 @@ int slab_fused_capacity(const Geom& g) {
 
 template <typename T>
 hipError_t launch_slab_fused(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
-                             int green_blocks, hipStream_t s) {
+                             int par, int green_blocks, hipStream_t s) {
   const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
   dim3 grid((unsigned)g.nz, (unsigned)g.dim, 1u);
   switch (g.nx) {
@@ -461,7 +497,7 @@ hipError_t launch_slab_fused(const Geom& g, const DevTables<T>& tb, const Stokes
   case N: {                                                                                    \
     using S = SlabCfg<T, N, N>;                                                                \
     ACM_LAUNCH((k_slab_local<T, N, N, true>), grid, dim3(S::NT), S::LDS_BYTES, s, one,  \
-                       nullptr, green_blocks, g.ntot, g.nspec, ct + tb.off.tw_x,               \
+                       nullptr, par, green_blocks, g.ntot, g.nspec, ct + tb.off.tw_x,          \
                        ct + tb.off.tw_y, ct + tb.off.rtw);                                     \
     return hipGetLastError();                                                                  \
   }
@@ -476,14 +512,14 @@ hipError_t launch_slab_fused(const Geom& g, const DevTables<T>& tb, const Stokes
   template bool slab_supported<T>(const Geom&);                                                \
   template int slab_fused_capacity<T>(const Geom&);                                            \
   template hipError_t launch_slab_fused<T>(const Geom&, const DevTables<T>&,                   \
-                                           const StokesCellArgs&, int, hipStream_t);           \
+                                           const StokesCellArgs&, int, int, hipStream_t);      \
   template int slab_local_blocks<T>(const Geom&);                                              \
   template hipError_t launch_slab_local<T>(const Geom&, const DevTables<T>&,                   \
                                            const StokesCellArgs&, const StokesCellArgs*, int,   \
                                            int, hipStream_t);                                  \
   template hipError_t launch_slab_rhs<T>(const Geom&, const DevTables<T>&,                     \
                                          const StokesCellArgs&, const StokesCellArgs*, int,     \
-                                         hipStream_t);
+                                         int, int, int, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

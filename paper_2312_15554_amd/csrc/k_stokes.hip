@@ -32,7 +32,7 @@ struct GreenGeom {
 
 template <typename T, int L, int NC, int VAR, int SPL>
 __global__ __launch_bounds__((ColCfg<T, L, NC, VAR, SPL>::NT)) void k_stokes_green(
-    StokesCellArgs one, const StokesCellArgs* __restrict__ many, GreenGeom gg,
+    StokesCellArgs one, const StokesCellArgs* __restrict__ many, GreenGeom gg, int par,
     const cplx<T>* __restrict__ tw, const T* __restrict__ sx, const T* __restrict__ lx,
     const T* __restrict__ sy, const T* __restrict__ ly, const T* __restrict__ sz,
     const T* __restrict__ lz) {
@@ -47,9 +47,9 @@ __global__ __launch_bounds__((ColCfg<T, L, NC, VAR, SPL>::NT)) void k_stokes_gre
   extern __shared__ __align__(16) char smem_raw[];
   __shared__ double red[3 * 16];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-  if (ctl->done) return;
-  const T beta = (T)ctl->psi[1];
-  const T bpen = (T)ctl->psi[2];
+  if (stokes_done(ctl)) return;
+  const T beta = (T)ctl->st[par].psi[1];
+  const T bpen = (T)ctl->st[par].psi[2];
   const T nu = (T)ctl->nu;
   const int P = gg.plane;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -182,7 +182,7 @@ __global__ __launch_bounds__((ColCfg<T, L, NC, VAR, SPL>::NT)) void k_stokes_gre
 
 template <typename T, int M>
 __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_stokes_local(
-    StokesCellArgs one, const StokesCellArgs* __restrict__ many, int ngreen, int nrows,
+    StokesCellArgs one, const StokesCellArgs* __restrict__ many, int par, int ngreen, int nrows,
     int64_t ntot, int64_t nspec, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ rtw) {
   using C = RowCfg<T, M>;
   const StokesCellArgs ca = many ? many[blockIdx.z] : one;
@@ -200,10 +200,11 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_stokes_local(
   __shared__ int s_last;
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   T* ldsr = reinterpret_cast<T*>(smem_raw);
-  if (ctl->done) return;
-  const double al = ctl->psi[0], bb = ctl->psi[2];
+  if (stokes_done(ctl)) return;
+  const StokesState& S = ctl->st[par];
+  const double al = S.psi[0], bb = S.psi[2];
   const T cc = (T)(bb / (bb + al));
-  const T cp = (T)ctl->c_prev;
+  const T cp = (T)S.c_prev;
   const T ka = (T)(bb * al / (bb + al));
   const int field = blockIdx.y;
   const int row0 = blockIdx.x * C::RB;
@@ -250,13 +251,13 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_stokes_local(
   __syncthreads();
   if (s_last) {
     __threadfence();
-    stokes_finalize(ctl, gpart, ngreen, lpart, nblk, ntot, hist, red);
+    stokes_finalize(ctl, par, gpart, ngreen, lpart, nblk, ntot, hist, red);
   }
 }
 
 template <typename T, int M>
 __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_stokes_rhs(
-    StokesCellArgs one, const StokesCellArgs* __restrict__ many, int nrows, int64_t ntot,
+    StokesCellArgs one, const StokesCellArgs* __restrict__ many, int slot, int nrows, int64_t ntot,
     int64_t nspec, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ rtw) {
   using C = RowCfg<T, M>;
   const StokesCellArgs ca = many ? many[blockIdx.z] : one;
@@ -269,9 +270,10 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_stokes_rhs(
   extern __shared__ __align__(16) char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   T* ldsr = reinterpret_cast<T*>(smem_raw);
-  if (ctl->done) return;
-  const T bb = (T)ctl->psi[2];
-  const T bcp = (T)(ctl->psi[2] * ctl->c_prev);
+  if (stokes_done(ctl)) return;
+  const StokesState& S = ctl->st[slot];
+  const T bb = (T)S.psi[2];
+  const T bcp = (T)(S.psi[2] * S.c_prev);
   const int field = blockIdx.y;
   const int row0 = blockIdx.x * C::RB;
   const int nr = min(C::RB, nrows - row0);
@@ -299,7 +301,7 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_stokes_rhs(
 // results are stored straight back.
 template <typename T, int L, int NC, int VAR>
 __global__ __launch_bounds__((ColCfg<T, L, NC, VAR>::NT)) void k_stokes_green_reg(
-    StokesCellArgs one, const StokesCellArgs* __restrict__ many, GreenGeom gg,
+    StokesCellArgs one, const StokesCellArgs* __restrict__ many, GreenGeom gg, int par,
     const cplx<T>* __restrict__ tw, const T* __restrict__ sx, const T* __restrict__ lx,
     const T* __restrict__ sy, const T* __restrict__ ly, const T* __restrict__ sz,
     const T* __restrict__ lz) {
@@ -316,9 +318,9 @@ __global__ __launch_bounds__((ColCfg<T, L, NC, VAR>::NT)) void k_stokes_green_re
   extern __shared__ __align__(16) char smem_raw[];
   __shared__ double red[3 * 16];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-  if (ctl->done) return;
-  const T beta = (T)ctl->psi[1];
-  const T bpen = (T)ctl->psi[2];
+  if (stokes_done(ctl)) return;
+  const T beta = (T)ctl->st[par].psi[1];
+  const T bpen = (T)ctl->st[par].psi[2];
   const T nu = (T)ctl->nu;
   const int P = gg.plane;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -470,7 +472,7 @@ int stokes_local_blocks(const Geom& g, int prec_bytes) {
 
 template <typename T, int LL, int NC, int VAR, bool REG, int SPL = 0>
 static hipError_t green_launch(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
-                               const StokesCellArgs* many, int ncells, int* nblocks,
+                               const StokesCellArgs* many, int ncells, int par, int* nblocks,
                                hipStream_t s) {
   using C = ColCfg<T, LL, NC, VAR, SPL>;
   const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
@@ -481,43 +483,43 @@ static hipError_t green_launch(const Geom& g, const DevTables<T>& tb, const Stok
   if (nblocks) *nblocks = nb;
   if constexpr (REG)
     ACM_LAUNCH((k_stokes_green_reg<T, LL, NC, VAR>), dim3(nb, 1, ncells), dim3(C::NT),
-                       C::LDS_BYTES, s, one, many, gg, tw, rt + tb.off.sx, rt + tb.off.lx,
+                       C::LDS_BYTES, s, one, many, gg, par, tw, rt + tb.off.sx, rt + tb.off.lx,
                        rt + tb.off.sy, rt + tb.off.ly, rt + tb.off.sz, rt + tb.off.lz);
   else
     ACM_LAUNCH((k_stokes_green<T, LL, NC, VAR, SPL>), dim3(nb, 1, ncells), dim3(C::NT),
-                       C::LDS_BYTES, s, one, many, gg, tw, rt + tb.off.sx, rt + tb.off.lx,
+                       C::LDS_BYTES, s, one, many, gg, par, tw, rt + tb.off.sx, rt + tb.off.lx,
                        rt + tb.off.sy, rt + tb.off.ly, rt + tb.off.sz, rt + tb.off.lz);
   return hipGetLastError();
 }
 
 template <typename T, int LL, int NC>
 static hipError_t green_var(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
-                            const StokesCellArgs* many, int ncells, int variant, int* nblocks,
-                            hipStream_t s) {
+                            const StokesCellArgs* many, int ncells, int par, int variant,
+                            int* nblocks, hipStream_t s) {
   constexpr bool reg_ok = RegPlanOk<LL>::value();
   if (variant == 3 || variant == 4) {
     if constexpr (reg_ok) {
-      if (variant == 3) return green_launch<T, LL, NC, 0, true>(g, tb, one, many, ncells, nblocks, s);
-      return green_launch<T, LL, NC, 1, true>(g, tb, one, many, ncells, nblocks, s);
+      if (variant == 3) return green_launch<T, LL, NC, 0, true>(g, tb, one, many, ncells, par, nblocks, s);
+      return green_launch<T, LL, NC, 1, true>(g, tb, one, many, ncells, par, nblocks, s);
     }
     variant -= 3;  // radix-3 plans: LDS-staged kernel of the same tile width
   }
-  if (variant == 5) return green_launch<T, LL, NC, 0, false, 1>(g, tb, one, many, ncells, nblocks, s);
-  if (variant == 6) return green_launch<T, LL, NC, 1, false, 1>(g, tb, one, many, ncells, nblocks, s);
-  if (variant == 1) return green_launch<T, LL, NC, 1, false>(g, tb, one, many, ncells, nblocks, s);
-  if (variant == 2) return green_launch<T, LL, NC, 2, false>(g, tb, one, many, ncells, nblocks, s);
-  return green_launch<T, LL, NC, 0, false>(g, tb, one, many, ncells, nblocks, s);
+  if (variant == 5) return green_launch<T, LL, NC, 0, false, 1>(g, tb, one, many, ncells, par, nblocks, s);
+  if (variant == 6) return green_launch<T, LL, NC, 1, false, 1>(g, tb, one, many, ncells, par, nblocks, s);
+  if (variant == 1) return green_launch<T, LL, NC, 1, false>(g, tb, one, many, ncells, par, nblocks, s);
+  if (variant == 2) return green_launch<T, LL, NC, 2, false>(g, tb, one, many, ncells, par, nblocks, s);
+  return green_launch<T, LL, NC, 0, false>(g, tb, one, many, ncells, par, nblocks, s);
 }
 
 template <typename T>
 hipError_t launch_stokes_green(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
-                               const StokesCellArgs* many, int ncells, int variant, int* nblocks,
-                               hipStream_t s) {
+                               const StokesCellArgs* many, int ncells, int par, int variant,
+                               int* nblocks, hipStream_t s) {
   switch (g.last_n) {
 #define CASE(LL)                                                                     \
   case LL:                                                                           \
-    if (g.dim == 3) return green_var<T, LL, 3>(g, tb, one, many, ncells, variant, nblocks, s); \
-    return green_var<T, LL, 2>(g, tb, one, many, ncells, variant, nblocks, s);
+    if (g.dim == 3) return green_var<T, LL, 3>(g, tb, one, many, ncells, par, variant, nblocks, s); \
+    return green_var<T, LL, 2>(g, tb, one, many, ncells, par, variant, nblocks, s);
     ACM_COL_LENGTHS(CASE)
 #undef CASE
     default:
@@ -527,7 +529,7 @@ hipError_t launch_stokes_green(const Geom& g, const DevTables<T>& tb, const Stok
 
 template <typename T>
 hipError_t launch_stokes_local(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
-                               const StokesCellArgs* many, int ncells, int green_blocks,
+                               const StokesCellArgs* many, int ncells, int par, int green_blocks,
                                hipStream_t s) {
   const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
   switch (g.nx / 2) {
@@ -535,7 +537,7 @@ hipError_t launch_stokes_local(const Geom& g, const DevTables<T>& tb, const Stok
   case M: {                                                                                   \
     using C = RowCfg<T, M>;                                                                   \
     dim3 grid((unsigned)((g.nrows + C::RB - 1) / C::RB), (unsigned)g.dim, (unsigned)ncells);  \
-    ACM_LAUNCH((k_stokes_local<T, M>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many,  \
+    ACM_LAUNCH((k_stokes_local<T, M>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many, par,  \
                        green_blocks, (int)g.nrows, g.ntot, g.nspec, ct + tb.off.tw_x,         \
                        ct + tb.off.rtw);                                                      \
     return hipGetLastError();                                                                 \
@@ -549,14 +551,14 @@ hipError_t launch_stokes_local(const Geom& g, const DevTables<T>& tb, const Stok
 
 template <typename T>
 hipError_t launch_stokes_rhs(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
-                             const StokesCellArgs* many, int ncells, hipStream_t s) {
+                             const StokesCellArgs* many, int ncells, int slot, hipStream_t s) {
   const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
   switch (g.nx / 2) {
 #define CASE(M)                                                                               \
   case M: {                                                                                   \
     using C = RowCfg<T, M>;                                                                   \
     dim3 grid((unsigned)((g.nrows + C::RB - 1) / C::RB), (unsigned)g.dim, (unsigned)ncells);  \
-    ACM_LAUNCH((k_stokes_rhs<T, M>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many,    \
+    ACM_LAUNCH((k_stokes_rhs<T, M>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many, slot, \
                        (int)g.nrows, g.ntot, g.nspec, ct + tb.off.tw_x, ct + tb.off.rtw);     \
     return hipGetLastError();                                                                 \
   }
@@ -570,13 +572,13 @@ hipError_t launch_stokes_rhs(const Geom& g, const DevTables<T>& tb, const Stokes
 #define INST(T)                                                                                \
   template hipError_t launch_stokes_green<T>(const Geom&, const DevTables<T>&,                 \
                                              const StokesCellArgs&, const StokesCellArgs*, int, \
-                                             int, int*, hipStream_t);                          \
+                                             int, int, int*, hipStream_t);                     \
   template hipError_t launch_stokes_local<T>(const Geom&, const DevTables<T>&,                 \
                                              const StokesCellArgs&, const StokesCellArgs*, int, \
-                                             int, hipStream_t);                                \
+                                             int, int, hipStream_t);                           \
   template hipError_t launch_stokes_rhs<T>(const Geom&, const DevTables<T>&,                   \
                                            const StokesCellArgs&, const StokesCellArgs*, int,   \
-                                           hipStream_t);
+                                           int, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

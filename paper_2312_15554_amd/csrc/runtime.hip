@@ -304,6 +304,11 @@ static std::vector<hipStream_t> branch_streams(int dev, int n) {
   return std::vector<hipStream_t>(v.begin(), v.begin() + std::min<int>(n, (int)v.size()));
 }
 
+// The state slot written last (the one with more completed iterations).
+static const StokesState& latest_state(const StokesCtl& c) {
+  return c.st[1].iter > c.st[0].iter ? c.st[1] : c.st[0];
+}
+
 // Cells sharing one plan (same grid and precision) are launched together.
 template <typename T>
 struct StokesGroup {
@@ -320,6 +325,7 @@ struct StokesGroup {
   DevBuf dargs_buf, dcols_buf;
   std::vector<StokesCellArgs> hargs;
   std::vector<ColCellArgs> hcols;
+  int par = 0;           // parity of the next iteration (state slot its passes read)
   const StokesCellArgs* dargs() const { return (const StokesCellArgs*)dargs_buf.p; }
   const ColCellArgs* dcols() const { return (const ColCellArgs*)dcols_buf.p; }
 };
@@ -339,39 +345,42 @@ static hipError_t enqueue_iteration(StokesGroup<T>& G, hipStream_t s, Profiler* 
   auto cols = [&](int sign, int kind) -> hipError_t {
     prof->begin(kind, &ev0);
     hipError_t r = n > 1 ? launch_cols_batched<T>(g, tb, 1, sign, d, G.dcols(), n, s)
-                         : launch_cols<T>(g, tb, 1, sign, d, one.spec, s, &one.ctl->done);
+                         : launch_cols<T>(g, tb, 1, sign, d, one.spec, s, &one.ctl->st[0].done,
+                                          &one.ctl->st[1].done);
     prof->end(kind, ev0);
     return r;
   };
   prof->begin(KK_GREEN, &ev0);
-  e = launch_stokes_green<T>(g, tb, one, many, n, G.green_var, nullptr, s);
+  const int par = G.par;
+  G.par ^= 1;
+  e = launch_stokes_green<T>(g, tb, one, many, n, par, G.green_var, nullptr, s);
   if (e != hipSuccess) return e;
   prof->end(KK_GREEN, ev0);
   if (G.fused) {
     prof->begin(KK_LOCAL, &ev0);
-    e = launch_slab_fused<T>(g, tb, one, G.ngreen, s);
+    e = launch_slab_fused<T>(g, tb, one, par, G.ngreen, s);
     if (e != hipSuccess) return e;
     prof->end(KK_LOCAL, ev0);
     return hipSuccess;
   }
   if (G.slab) {
     prof->begin(KK_LOCAL, &ev0);
-    e = launch_slab_local<T>(g, tb, one, many, n, G.ngreen, s);
+    e = launch_slab_local<T>(g, tb, one, many, n, par, s);
     if (e != hipSuccess) return e;
     prof->end(KK_LOCAL, ev0);
     prof->begin(KK_RHS, &ev0);
-    e = launch_slab_rhs<T>(g, tb, one, many, n, s);
+    e = launch_slab_rhs<T>(g, tb, one, many, n, par, 1, G.ngreen, s);
     if (e != hipSuccess) return e;
     prof->end(KK_RHS, ev0);
     return hipSuccess;
   }
   if (d == 3 && (e = cols(+1, KK_YINV)) != hipSuccess) return e;
   prof->begin(KK_LOCAL, &ev0);
-  e = launch_stokes_local<T>(g, tb, one, many, n, G.ngreen, s);
+  e = launch_stokes_local<T>(g, tb, one, many, n, par, G.ngreen, s);
   if (e != hipSuccess) return e;
   prof->end(KK_LOCAL, ev0);
   prof->begin(KK_RHS, &ev0);
-  e = launch_stokes_rhs<T>(g, tb, one, many, n, s);
+  e = launch_stokes_rhs<T>(g, tb, one, many, n, par ^ 1, s);
   if (e != hipSuccess) return e;
   prof->end(KK_RHS, ev0);
   if (d == 3 && (e = cols(-1, KK_YFWD)) != hipSuccess) return e;
@@ -457,7 +466,7 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
       A.ctl = dctl + i;
       A.hist = hist_cap > 0 ? (double*)hist_buf.p : nullptr;
       G.hargs.push_back(A);
-      G.hcols.push_back(ColCellArgs{A.spec, &A.ctl->done});
+      G.hcols.push_back(ColCellArgs{A.spec, &A.ctl->st[0].done, &A.ctl->st[1].done});
     }
     if (G.cells.size() > 1) {
       HIP_TRY(hipMalloc(&G.dargs_buf.p, sizeof(StokesCellArgs) * G.cells.size()));
@@ -484,23 +493,27 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
     StokesCtl& c = hc[i];
     memset(&c, 0, sizeof(c));
     const double p0 = nu * (double)std::max(g.nx, std::max(g.ny, g.nz));
-    c.psi[0] = pen.alpha > 0 ? pen.alpha : p0;
-    c.psi[1] = pen.beta > 0 ? pen.beta : p0;
-    c.psi[2] = pen.b > 0 ? pen.b : p0;
+    StokesState& s0 = c.st[0];
+    s0.psi[0] = pen.alpha > 0 ? pen.alpha : p0;
+    s0.psi[1] = pen.beta > 0 ? pen.beta : p0;
+    s0.psi[2] = pen.b > 0 ? pen.b : p0;
     for (int k = 0; k < 3; ++k) {
       c.phi[k] = pen.phi[k];
       c.tau[k] = pen.tau[k];
-      c.psi_min[k] = pen.psi_min[k] > 0 ? pen.psi_min[k] : 1e-3 * c.psi[k];
+      c.psi_min[k] = pen.psi_min[k] > 0 ? pen.psi_min[k] : 1e-3 * s0.psi[k];
       c.g[k] = k < d ? cells[i].g[k] : 0.0;
     }
-    c.c_prev = 0.0;
+    s0.c_prev = 0.0;
+    s0.iter = 0;
+    s0.done = 0;
+    s0.status = 1;
+    c.st[1] = s0;
     c.eps = o.eps;
     c.sqrt_n[0] = sqrt((double)d * (double)g.ntot);
     c.sqrt_n[1] = sqrt((double)g.ntot);
     c.sqrt_n[2] = c.sqrt_n[0];
     c.nu = nu;
     c.max_iter = o.max_iter;
-    c.status = 1;
     c.adaptive = pen.adaptive;
     c.hist_cap = hist_cap;
   }
@@ -534,9 +547,9 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
         }
         if (e == hipSuccess) {
           if (G.slab) {
-            e = launch_slab_rhs<T>(g, tb, A, nullptr, 1, s);
+            e = launch_slab_rhs<T>(g, tb, A, nullptr, 1, 0, 0, 0, s);
           } else {
-            e = launch_stokes_rhs<T>(g, tb, A, nullptr, 1, s);
+            e = launch_stokes_rhs<T>(g, tb, A, nullptr, 1, 0, s);
             if (e == hipSuccess && g.dim == 3) e = launch_cols<T>(g, tb, 1, -1, g.dim, A.spec, s);
           }
         }
@@ -556,6 +569,9 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
     K = (int)std::min(200.0, std::max(8.0, 3.0e8 / work));
   }
   if (o.max_iter < K) K = (int)std::max<int64_t>(1, o.max_iter);
+  // even, so that every replay of the captured iterations starts on the same
+  // state slot (the passes alternate between the two slots)
+  K += K & 1;
 
   StokesCtl* hctl = nullptr;
   HIP_TRY(hipHostMalloc((void**)&hctl, sizeof(StokesCtl) * ncell, hipHostMallocDefault));
@@ -690,8 +706,9 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
     bool all = true;
     const double now = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     for (int i = 0; i < ncell; ++i) {
-      if (hctl[i].done && t_done[i] < 0) t_done[i] = now;
-      all = all && hctl[i].done;
+      const bool done = stokes_done(&hctl[i]);
+      if (done && t_done[i] < 0) t_done[i] = now;
+      all = all && done;
     }
     if (all) break;
     if (launched > o.max_iter + 2LL * K) break;  // safety net: the device caps iterations itself
@@ -719,7 +736,7 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
     std::vector<double> h((size_t)hist_cap * kHistDoubles);
     HIP_TRY(hipMemcpyAsync(h.data(), hist_buf.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    const int64_t n = hctl[0].iter;
+    const int64_t n = latest_state(hctl[0]).iter;
     const int64_t keep = std::min<int64_t>(n, hist_cap);
     for (int64_t i = 0; i < keep; ++i) {
       const int64_t it = n - keep + i;
@@ -735,7 +752,7 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
                              "(its workgroups were not all resident)");
   int worst = 0;
   for (int i = 0; i < ncell; ++i) {
-    const StokesCtl& c = hctl[i];
+    const StokesState& c = latest_state(hctl[i]);
     if (c.status == -5) worst = -5;
     else if (c.status != 0 && worst == 0) worst = 1;
     if (!stats) continue;

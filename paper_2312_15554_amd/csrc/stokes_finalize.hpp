@@ -1,82 +1,134 @@
 // Step 4 of the ADMM (Section 3.1, eq. constrains with the tolerances of the
 // same section) and the adaptive penalty update (Section 4.1, eq. varying
-// algorithm), run by the last workgroup of the local pass on the device.
+// algorithm), computed on the device from the partial sums of the passes.
 #pragma once
 #include "pass_common.hpp"
 
 namespace acm {
 
-// Step 4 and the penalty update, run by the last workgroup of the local pass.
-__device__ __forceinline__ void stokes_finalize(StokesCtl* ctl, const double* __restrict__ gpart, int ngreen,
-                                const double* __restrict__ lpart, int nlocal, int64_t ntot,
-                                double* hist, double* red) {
-  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (int j = threadIdx.x; j < ngreen; j += blockDim.x) {
-    acc[0] += gpart[j * 3 + 0];
-    acc[1] += gpart[j * 3 + 1];
-    acc[2] += gpart[j * 3 + 2];
+// Totals of the green partials (3 per tile: |div u|^2, |div u - div u_prev|^2,
+// |q|^2, Parseval-weighted) and the local partials (4 per workgroup: |H u|^2,
+// |H (ut - ut_prev)|^2, |a|^2, |u - u_prev|^2) in a fixed order, so every
+// workgroup that forms them gets the same bits.  The whole workgroup calls
+// it; the totals are valid in thread 0.  `red` holds 7 * 16 doubles.
+// U: loads per thread issued together before any is added.
+template <int U = 4>
+__device__ __forceinline__ void stokes_sum_partials(const double* __restrict__ gpart, int ngreen,
+                                                    const double* __restrict__ lpart, int nlocal,
+                                                    double (&acc)[7], double* red) {
+  for (int k = 0; k < 7; ++k) acc[k] = 0.0;
+  for (int j0 = threadIdx.x; j0 < ngreen; j0 += U * blockDim.x) {
+    double v[U][3];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int j = j0 + k * blockDim.x;
+      const bool in = j < ngreen;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) v[k][c] = in ? gpart[j * 3 + c] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[c] += v[k][c];
   }
-  for (int j = threadIdx.x; j < nlocal; j += blockDim.x) {
-    acc[3] += lpart[j * 4 + 0];
-    acc[4] += lpart[j * 4 + 1];
-    acc[5] += lpart[j * 4 + 2];
-    acc[6] += lpart[j * 4 + 3];
+  for (int j0 = threadIdx.x; j0 < nlocal; j0 += U * blockDim.x) {
+    double v[U][4];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int j = j0 + k * blockDim.x;
+      const bool in = j < nlocal;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[k][c] = in ? lpart[j * 4 + c] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[3 + c] += v[k][c];
   }
   block_sum<7>(acc, red);
-  if (threadIdx.x != 0) return;
+}
+
+// Step 4 and the penalty update: the state `nx` that follows `cur` given the
+// totals.  Pure function of its inputs (one thread calls it).
+__device__ __forceinline__ void stokes_step4(const StokesCtl* __restrict__ ctl,
+                                             const StokesState& cur, const double (&tot)[7],
+                                             int64_t ntot, StokesState& nx) {
   const double inv_n = 1.0 / (double)ntot;
-  const double s_div = acc[0] * inv_n, s_ddiv = acc[1] * inv_n, s_q = acc[2] * inv_n;
-  const double s_su2 = acc[3], s_sd = acc[4], s_a2 = acc[5], s_du = acc[6];
-  const double al = ctl->psi[0], be = ctl->psi[1], bb = ctl->psi[2];
+  const double s_div = tot[0] * inv_n, s_ddiv = tot[1] * inv_n, s_q = tot[2] * inv_n;
+  const double s_su2 = tot[3], s_sd = tot[4], s_a2 = tot[5], s_du = tot[6];
+  const double al = cur.psi[0], be = cur.psi[1], bb = cur.psi[2];
   const double cc = bb / (bb + al);
   const double one_m_cc = al / (bb + al);
   const double nsu = sqrt(s_su2);
-  double rp[3] = {cc * nsu, sqrt(s_div), one_m_cc * nsu};
-  double rd[3] = {al * sqrt(s_sd), be * sqrt(s_ddiv), bb * sqrt(s_du)};
-  double mu[3] = {sqrt(s_a2), sqrt(s_q), sqrt(s_a2)};
+  const double rp[3] = {cc * nsu, sqrt(s_div), one_m_cc * nsu};
+  const double rd[3] = {al * sqrt(s_sd), be * sqrt(s_ddiv), bb * sqrt(s_du)};
+  const double mu[3] = {sqrt(s_a2), sqrt(s_q), sqrt(s_a2)};
   const double eps = ctl->eps;
   bool ok = true, finite = true;
   for (int k = 0; k < 3; ++k) {
     const double tp = ctl->sqrt_n[k] * eps + eps * fmax(rp[k], mu[k]);
     const double td = ctl->sqrt_n[k] * eps + eps * mu[k];
-    ctl->rp[k] = rp[k];
-    ctl->rd[k] = rd[k];
-    ctl->tp[k] = tp;
-    ctl->td[k] = td;
-    ctl->mu[k] = mu[k];
+    nx.rp[k] = rp[k];
+    nx.rd[k] = rd[k];
+    nx.tp[k] = tp;
+    nx.td[k] = td;
+    nx.mu[k] = mu[k];
+    nx.psi[k] = cur.psi[k];
     if (!(rp[k] <= tp && rd[k] <= td)) ok = false;
     if (!isfinite(rp[k]) || !isfinite(rd[k])) finite = false;
   }
-  const int64_t it = ctl->iter + 1;
-  ctl->iter = it;
-  if (hist != nullptr && ctl->hist_cap > 0) {
-    double* hrec = hist + ((it - 1) % ctl->hist_cap) * kHistDoubles;
-    for (int k = 0; k < 3; ++k) {
-      hrec[k] = rp[k];
-      hrec[3 + k] = rd[k];
-      hrec[6 + k] = ctl->tp[k];
-      hrec[9 + k] = ctl->td[k];
-      hrec[12 + k] = ctl->psi[k];
-    }
-  }
-  ctl->c_prev = cc;
+  nx.iter = cur.iter + 1;
+  nx.c_prev = cc;
+  nx.done = 0;
+  nx.status = 1;
   if (!finite) {
-    ctl->done = 1;
-    ctl->status = -5;
+    nx.done = 1;
+    nx.status = -5;
   } else if (ok) {
-    ctl->done = 1;
-    ctl->status = 0;
-  } else if (it >= ctl->max_iter) {
-    ctl->done = 1;
-    ctl->status = 1;
+    nx.done = 1;
+    nx.status = 0;
+  } else if (nx.iter >= ctl->max_iter) {
+    nx.done = 1;
+    nx.status = 1;
   } else if (ctl->adaptive) {
     for (int k = 0; k < 3; ++k) {
       if (rp[k] > ctl->tau[k] * rd[k])
-        ctl->psi[k] = ctl->phi[k] * ctl->psi[k];
+        nx.psi[k] = ctl->phi[k] * cur.psi[k];
       else if (rd[k] > ctl->tau[k] * rp[k])
-        ctl->psi[k] = fmax(ctl->psi[k] / ctl->phi[k], ctl->psi_min[k]);
+        nx.psi[k] = fmax(cur.psi[k] / ctl->phi[k], ctl->psi_min[k]);
     }
   }
+}
+
+// One record of the residual history ring: rp, rd, tp, td and the penalties
+// the iteration used.
+__device__ __forceinline__ void stokes_history(const StokesCtl* ctl, const StokesState& cur,
+                                               const StokesState& nx, double* hist) {
+  if (hist == nullptr || ctl->hist_cap <= 0) return;
+  double* hrec = hist + ((nx.iter - 1) % ctl->hist_cap) * kHistDoubles;
+  for (int k = 0; k < 3; ++k) {
+    hrec[k] = nx.rp[k];
+    hrec[3 + k] = nx.rd[k];
+    hrec[6 + k] = nx.tp[k];
+    hrec[9 + k] = nx.td[k];
+    hrec[12 + k] = cur.psi[k];
+  }
+}
+
+// Last-workgroup form (row passes, single-launch slab pass): sums, Step 4,
+// writes slot par ^ 1 and the history, and re-arms the arrival counter.
+__device__ __forceinline__ void stokes_finalize(StokesCtl* ctl, int par,
+                                                const double* __restrict__ gpart, int ngreen,
+                                                const double* __restrict__ lpart, int nlocal,
+                                                int64_t ntot, double* hist, double* red) {
+  double acc[7];
+  stokes_sum_partials(gpart, ngreen, lpart, nlocal, acc, red);
+  if (threadIdx.x != 0) return;
+  const StokesState cur = ctl->st[par];
+  StokesState nx;
+  stokes_step4(ctl, cur, acc, ntot, nx);
+  stokes_history(ctl, cur, nx, hist);
+  ctl->st[par ^ 1] = nx;
   ctl->counter = 0u;
 }
 
