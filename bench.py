@@ -43,7 +43,8 @@ def parse():
     ap.add_argument("--no-transport", action="store_true", help="skip the 500-step transport run")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-cell batch comparison")
     ap.add_argument("--transport-steps", type=int, default=500)
-    ap.add_argument("--fno", action="store_true", help="train the FNO warm start and compare solves")
+    ap.add_argument("--no-fno", action="store_true",
+                    help="skip training the FNO warm start and the warm vs plain comparison")
     ap.add_argument("--fno-train", type=int, default=256, help="64^3 training solves")
     ap.add_argument("--fno-epochs", type=int, default=6)
     ap.add_argument("--fno-test", type=int, default=2, help="256^3 test cells")
@@ -136,14 +137,21 @@ def fno_section(args, log):
     err_hold = W.relative_error(net, norm, H[ntr:], Y[ntr:]) if ntr < len(cells) else None
     del H, Y
     torch.cuda.empty_cache()
-    tests = []
-    for i, c in enumerate(W.make_cells(256, args.fno_test, 20000, 16.0, 0.35, 0.50)):
+    tests, tight = [], []
+    test_cells = W.make_cells(256, args.fno_test, 20000, 16.0, 0.35, 0.50)
+    for i, c in enumerate(test_cells):
         r = W.solve_plain_and_warm(net, norm, torch.from_numpy(c).cuda(), eps=1e-6)
         log(f"fno test cell {i}: {r}")
         tests.append(r)
+    # at eps = 1e-6 both solves stop inside a wide band around the fixed point
+    # (their K can differ by tens of percent at 256^3); one cell again at 1e-7
+    r = W.solve_plain_and_warm(net, norm, torch.from_numpy(test_cells[0]).cuda(), eps=1e-7)
+    log(f"fno test cell 0 at eps 1e-7: {r}")
+    tight.append(r)
     return dict(train_cells=len(cells), data_seconds=round(info["seconds"], 2),
                 train_seconds=round(tr["seconds"], 2), train_steps=tr["steps"],
                 final_loss=tr["loss"][-1], holdout_rel_err=err_hold, tests=tests,
+                tests_eps_1e7=tight,
                 iters_saved=[t["plain_iters"] - t["warm_iters"] for t in tests],
                 time_ratio_warm_over_plain=[t["warm_s"] / t["plain_s"] for t in tests])
 
@@ -332,14 +340,21 @@ def main():
     km, kc = dict(rp["stats"]["kernel_ms"]), dict(rp["stats"]["kernel_calls"])
     if kc["local"] > 0 and kc["rhs"] == 0:  # local and rhs passes in one launch
         km["local+rhs"], kc["local+rhs"] = km.pop("local"), kc.pop("local")
-    share = {k: km[k] for k in km if kc[k] > 0}
+    # Each kernel's events are attached to its own dispatch but still include a
+    # per-launch overhead; the library times an empty kernel the same way
+    # ("other") and that mean is subtracted from every kernel's mean.
+    ovh_ms = km.pop("other") / kc.pop("other") if kc.get("other") else 0.0
+    raw = {k: km[k] / kc[k] for k in km if kc[k] > 0}
+    avg_ms = {k: max(raw[k] - ovh_ms, 1e-6) for k in raw}
+    share = {k: avg_ms[k] * kc[k] for k in avg_ms}
     dom = max(share, key=share.get)
-    avg_s = km[dom] / kc[dom] * 1e-3
+    avg_s = avg_ms[dom] * 1e-3
     algo = kernel_bytes(dom, n, d, nsolid)
     achieved = algo / avg_s / 1e9
-    per_kernel = {k: dict(avg_us=round(km[k] / kc[k] * 1e3, 2), calls=kc[k],
-                          GBps=round(kernel_bytes(k, n, d, nsolid) / (km[k] / kc[k] * 1e-3) / 1e9, 1))
-                  for k in share}
+    per_kernel = {k: dict(avg_us=round(avg_ms[k] * 1e3, 2), avg_us_events=round(raw[k] * 1e3, 2),
+                          calls=kc[k],
+                          GBps=round(kernel_bytes(k, n, d, nsolid) / (avg_ms[k] * 1e-3) / 1e9, 1))
+                  for k in avg_ms}
     iter_us_profiled = 1e3 * sum(km.values()) / max(1, rp["stats"]["iters"])
 
     log(f"profiled solve: dominant kernel {dom}, {per_kernel}")
@@ -387,7 +402,7 @@ def main():
     if not args.no_batched and not args.fixed_iters:
         batched = batched_section(args.batch_cells, log)
 
-    fno = fno_section(args, log) if args.fno and not args.fixed_iters else None
+    fno = fno_section(args, log) if not args.no_fno and not args.fixed_iters else None
 
     out = {
         "metric": "voxel-iters/s & time-to-1e-6 residual: plain vs batched+FNO warm start",
@@ -410,6 +425,7 @@ def main():
         "K": [[float(v) for v in row] for row in K],
         "iter_us_profiled": round(iter_us_profiled, 2),
         "kernels": per_kernel,
+        "event_launch_overhead_us": round(ovh_ms * 1e3, 2),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": counter_traffic(dom)},

@@ -95,16 +95,21 @@ typedef struct {
                            rounding. */
 } acm_opts;
 
-/* Kernel kinds reported in acm_stats.kernel_ms (with opts.profile = 1). */
+/* Kernel kinds reported in acm_stats.kernel_ms (with opts.profile = 1).  Each
+ * kernel is timed by start/stop events attached to its own dispatch; those
+ * include a per-launch overhead of a few microseconds, which ACM_K_OTHER
+ * measures on an empty kernel launched the same way once per iteration. */
 enum {
   ACM_K_GREEN = 0,   /* Stokes: last-axis FFT pair + Step 1 + q update */
-  ACM_K_LOCAL = 1,   /* Stokes: x inverse transform + Steps 2-3 (+ Step 4) */
-  ACM_K_RHS = 2,     /* Stokes: right-hand side of Step 1 + x forward transform */
+  ACM_K_LOCAL = 1,   /* Stokes: x inverse transform + Steps 2-3 (+ Step 4 on the row
+                        path; local and rhs together with pass_mode 3) */
+  ACM_K_RHS = 2,     /* Stokes: (Step 4 on the slab path +) right-hand side of Step 1
+                        + x forward transform */
   ACM_K_YINV = 3,    /* y inverse transform (3D) */
   ACM_K_YFWD = 4,    /* y forward transform (3D) */
   ACM_K_T_GREEN = 5, /* transport: last-axis FFT pair + LS update */
   ACM_K_T_LOCAL = 6, /* transport: x transforms + local residual F */
-  ACM_K_OTHER = 7
+  ACM_K_OTHER = 7    /* Stokes profiling: the empty calibration kernel */
 };
 
 typedef struct {

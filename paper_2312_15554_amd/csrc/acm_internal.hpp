@@ -219,6 +219,9 @@ template <typename T>
 hipError_t launch_warm_init(const Geom& g, const T* u, const T* q, const uint8_t* H, T* a, T* div,
                             double nu, const double* gp, hipStream_t s);
 
+// An empty kernel (profiling: calibrates the per-launch event overhead).
+hipError_t launch_noop(hipStream_t s);
+
 // Fused xy-slab Stokes passes (3D, nx == ny, slab of one field in LDS).
 template <typename T>
 bool slab_supported(const Geom& g);

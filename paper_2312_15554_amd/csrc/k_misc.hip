@@ -190,6 +190,13 @@ int reduction_blocks(const Geom& g) {
   return (int)std::min<int64_t>(kRedBlocks, (g.ntot + kRedThreads - 1) / kRedThreads);
 }
 
+__global__ void k_noop(int) {}
+
+hipError_t launch_noop(hipStream_t s) {
+  ACM_LAUNCH(k_noop, dim3(1), dim3(64), 0, s, 0);
+  return hipGetLastError();
+}
+
 #define INST(T)                                                                              \
   template hipError_t launch_flow_sums<T>(const Geom&, const T*, const uint8_t*, double*,    \
                                           int*, hipStream_t);                                \

@@ -25,11 +25,32 @@ struct Vec4<double> {
   using type = double4;
 };
 
+
+// 4 consecutive reals of an LDS row (8-byte aligned)
+template <typename V, typename T>
+__device__ __forceinline__ V lds_ld4(const T* p) {
+  V v;
+  v.x = p[0];
+  v.y = p[1];
+  v.z = p[2];
+  v.w = p[3];
+  return v;
+}
+template <typename V, typename T>
+__device__ __forceinline__ void lds_st4(T* p, const V& v) {
+  p[0] = v.x;
+  p[1] = v.y;
+  p[2] = v.z;
+  p[3] = v.w;
+}
+
 template <typename T, int NX, int NY>
 struct SlabCfg {
   static constexpr int M = NX / 2;
   static constexpr int XH = M + 1;
-  static constexpr int P2 = XH + 1;  // row pitch in complex values (even: rows 16B-aligned)
+  // row pitch in complex values: odd, so the elements of a column (2 P2 dwords
+  // apart) fall in different LDS banks for the column transforms
+  static constexpr int P2 = XH;
   static constexpr int TPPY = Plan<NY>::TPP;
   static constexpr int TPPX = Plan<M>::TPP;
   // NT_EVEN: workgroup of TPPY * M/2 threads (XH columns in three rounds, the
@@ -207,7 +228,7 @@ __attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
       hwj = hw[j];
       aoj = ao[j];
     }
-    const V un = *reinterpret_cast<const V*>(ldsr + y * 2 * S::P2 + x);
+    const V un = lds_ld4<V>(ldsr + y * 2 * S::P2 + x);
     const T unv[4] = {un.x, un.y, un.z, un.w};
     const T upv[4] = {upj.x, upj.y, upj.z, upj.w};
 #pragma unroll
@@ -309,14 +330,14 @@ __attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
       if (!S::FULL && q >= S::NQ) continue;
       const int v = 4 * q;
       const int y = v / NX, x = v - y * NX;
-      V* cell = reinterpret_cast<V*>(ldsr + y * 2 * S::P2 + x);
-      const V un = *cell;
+      T* cell = ldsr + y * 2 * S::P2 + x;
+      const V un = lds_ld4<V>(cell);
       V r;
       r.x = ((hw[j] & 0xffu) ? bcp : b1) * un.x - ao[j].x;
       r.y = ((hw[j] & 0xff00u) ? bcp : b1) * un.y - ao[j].y;
       r.z = ((hw[j] & 0xff0000u) ? bcp : b1) * un.z - ao[j].z;
       r.w = ((hw[j] & 0xff000000u) ? bcp : b1) * un.w - ao[j].w;
-      *cell = r;
+      lds_st4(cell, r);
     }
     __syncthreads();
     slab_forward_store<T, NX, NY>(lds, slab, twx, twy, rtw);
@@ -391,7 +412,7 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_rhs(
     r.y = ((hw & 0xff00u) ? bcp : bb) * uv.y - av.y;
     r.z = ((hw & 0xff0000u) ? bcp : bb) * uv.z - av.z;
     r.w = ((hw & 0xff000000u) ? bcp : bb) * uv.w - av.w;
-    *reinterpret_cast<V*>(ldsr + y * 2 * S::P2 + x) = r;
+    lds_st4(ldsr + y * 2 * S::P2 + x, r);
   }
   __syncthreads();
   slab_forward_store<T, NX, NY>(lds, spec + field * nspec + (int64_t)z * NY * S::XH, twx, twy, rtw);

@@ -353,6 +353,14 @@ static hipError_t enqueue_iteration(StokesGroup<T>& G, hipStream_t s, Profiler* 
   prof->begin(KK_GREEN, &ev0);
   const int par = G.par;
   G.par ^= 1;
+  if (prof->on) {
+    // an empty kernel timed the same way: the per-launch overhead of the
+    // event timestamps (reported as its own kind)
+    prof->begin(KK_OTHER, &ev0);
+    e = launch_noop(s);
+    if (e != hipSuccess) return e;
+    prof->end(KK_OTHER, ev0);
+  }
   e = launch_stokes_green<T>(g, tb, one, many, n, par, G.green_var, nullptr, s);
   if (e != hipSuccess) return e;
   prof->end(KK_GREEN, ev0);

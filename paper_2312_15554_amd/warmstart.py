@@ -125,4 +125,5 @@ def solve_plain_and_warm(net: FNO, norm: Normaliser, H: torch.Tensor, eps=1e-6, 
     kw = float(rw["u"][0].double().mean())
     return dict(plain_iters=rp["stats"]["iters"], warm_iters=rw["stats"]["iters"],
                 plain_s=t1 - t0, warm_s=t2 - t1, k_plain=kp, k_warm=kw,
+                k_rel_diff=abs(kw - kp) / max(abs(kp), 1e-300),
                 converged=bool(rp["stats"]["converged"] and rw["stats"]["converged"]))
