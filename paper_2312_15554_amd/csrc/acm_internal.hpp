@@ -198,7 +198,13 @@ hipError_t launch_stokes_rhs(const Geom& g, const DevTables<T>& tb, const Stokes
 template <typename T>
 hipError_t launch_transport_green(const Geom& g, const DevTables<T>& tb, int mode, void* spec,
                                   void* chat, const void* chat_m, double* partials,
-                                  TransportCtl* ctl, hipStream_t s);
+                                  TransportCtl* ctl, int nfpart, hipStream_t s);
+// Slab form of the local pass (3D, nx == ny <= 128, u 16-byte aligned): reads
+// grad chi-hat from fields 0..2 and writes tau-hat to fields 0..2 and the
+// three partial spectra of f to fields 3..5 (green then runs with nfpart = 3).
+template <typename T>
+hipError_t launch_transport_slab(const Geom& g, const DevTables<T>& tb, void* spec, const T* u,
+                                 const uint8_t* H, const TransportCtl* ctl, hipStream_t s);
 template <typename T>
 hipError_t launch_transport_local(const Geom& g, const DevTables<T>& tb, void* spec, const T* u,
                                   const uint8_t* H, const TransportCtl* ctl, hipStream_t s);

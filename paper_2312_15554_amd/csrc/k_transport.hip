@@ -13,7 +13,7 @@
 //           sums for r_1 = |chi^{n+1} - chi^n| and r_2 = |grad chi^{n+1} -
 //           grad chi^n|, the last workgroup applies the stopping test, and
 //           grad chi-hat = i s chi-hat is transformed back along the last axis.
-#include "pass_common.hpp"
+#include "slab_common.hpp"
 
 namespace acm {
 
@@ -29,7 +29,7 @@ struct TGreenGeom {
 template <typename T, int L, int D, int MODE>
 __global__ __launch_bounds__((ColCfg<T, L, D + 1>::NT)) void k_transport_green(
     cplx<T>* __restrict__ spec, cplx<T>* __restrict__ chat, const cplx<T>* __restrict__ chat_m,
-    double* __restrict__ partials, TransportCtl* ctl, TGreenGeom gg,
+    double* __restrict__ partials, TransportCtl* ctl, TGreenGeom gg, int nfpart,
     const cplx<T>* __restrict__ tw, const T* __restrict__ sx, const T* __restrict__ lx,
     const T* __restrict__ sy, const T* __restrict__ ly, const T* __restrict__ sz,
     const T* __restrict__ lz) {
@@ -52,7 +52,16 @@ __global__ __launch_bounds__((ColCfg<T, L, D + 1>::NT)) void k_transport_green(
       const int i = rem / C::TX, col = rem - i * C::TX;
       const int f = f0 + col;
       cplx<T> v = cmake<T>(T(0), T(0));
-      if (f < P) v = spec[c * gg.nspec + (int64_t)i * P + f];
+      if (f < P) {
+        v = spec[c * gg.nspec + (int64_t)i * P + f];
+        // f-hat may arrive as nfpart partial spectra (one per field of the
+        // slab pass) in consecutive fields: their sum is f-hat
+        for (int j = 1; c == D && j < nfpart; ++j) {
+          const cplx<T> w = spec[(c + j) * gg.nspec + (int64_t)i * P + f];
+          v.x += w.x;
+          v.y += w.y;
+        }
+      }
       lds[e] = v;
     }
     __syncthreads();
@@ -237,6 +246,86 @@ __global__ __launch_bounds__((RowCfgN<T, M, D + 1>::NT)) void k_transport_local(
   }
 }
 
+// Local pass on xy-slabs (3D cubes whose slab fits in LDS): workgroup (z, c)
+// takes the z-slab of d_c chi back to real space (column then row inverse
+// transforms), forms e_c = d_c chi + g_c, tau_c = (A - A0) e_c and this field's
+// share of f, f_c = calF (1-H) [c = 0 only] - (B_c - B0_c) e_c, and transforms
+// tau_c and f_c forward (rows then columns) into fields c and D + c.  The
+// green pass adds the D partial spectra of f.  Compared with the row pass it
+// saves the separate y passes (2 x 7 half-spectrum round trips per iteration)
+// at the price of D - 1 extra spectra of f written and read.
+template <typename T, int N>
+__global__ __launch_bounds__((SlabCfg<T, N, N>::NT))
+__attribute__((amdgpu_waves_per_eu(SlabCfg<T, N, N>::WPE_ONE))) void k_transport_slab(
+    cplx<T>* __restrict__ spec, const T* __restrict__ u, const uint8_t* __restrict__ H,
+    const TransportCtl* __restrict__ ctl, int64_t ntot, int64_t nspec,
+    const cplx<T>* __restrict__ twx, const cplx<T>* __restrict__ twy,
+    const cplx<T>* __restrict__ rtw) {
+  using S = SlabCfg<T, N, N>;
+  using V = typename Vec4<T>::type;
+  constexpr int D = 3;
+  extern __shared__ __align__(32) char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  T* ldsr = reinterpret_cast<T*>(smem_raw);
+  if (ctl->done) return;
+  const int z = blockIdx.x, c = blockIdx.y;
+  const int64_t soff = (int64_t)z * N * S::XH;
+  slab_load_inverse<T, N, N>(lds, spec + c * nspec + soff, twx, twy, rtw);
+
+  const T gc = (T)ctl->g[c], B0c = (T)ctl->B0[c];
+  const T A0 = (T)ctl->A0, Pe = (T)ctl->Pe, eta = (T)ctl->eta, dif = (T)ctl->diff;
+  const T calF = c == 0 ? (T)ctl->calF : T(0);
+  const int64_t off = (int64_t)z * S::NV;
+  const V* uq = reinterpret_cast<const V*>(u + c * ntot + off);
+  const uint32_t* hq = reinterpret_cast<const uint32_t*>(H + off);
+  V fr[S::QPT];
+#pragma unroll
+  for (int j = 0; j < S::QPT; ++j) {
+    const int q = threadIdx.x + j * S::NT;
+    if (!S::FULL && q >= S::NQ) continue;
+    const int v = 4 * q;
+    const int y = v / N, x = v - y * N;
+    T* cell = ldsr + y * 2 * S::P2 + x;
+    const V ev = lds_ld4<V>(cell);
+    const V uv = uq[q];
+    const uint32_t hw = hq[q];
+    const T e4[4] = {ev.x + gc, ev.y + gc, ev.z + gc, ev.w + gc};
+    const T u4[4] = {uv.x, uv.y, uv.z, uv.w};
+    T tau[4], f[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const bool solid = ((hw >> (8 * k)) & 0xffu) != 0;
+      const T Aa = solid ? eta : dif;
+      const T Bc = solid ? T(0) : Pe * u4[k];
+      f[k] = (solid ? T(0) : calF) - (Bc - B0c) * e4[k];
+      tau[k] = (Aa - A0) * e4[k];
+    }
+    V tv;
+    tv.x = tau[0];
+    tv.y = tau[1];
+    tv.z = tau[2];
+    tv.w = tau[3];
+    lds_st4(cell, tv);
+    fr[j].x = f[0];
+    fr[j].y = f[1];
+    fr[j].z = f[2];
+    fr[j].w = f[3];
+  }
+  __syncthreads();
+  slab_forward_store<T, N, N>(lds, spec + c * nspec + soff, twx, twy, rtw);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < S::QPT; ++j) {
+    const int q = threadIdx.x + j * S::NT;
+    if (!S::FULL && q >= S::NQ) continue;
+    const int v = 4 * q;
+    const int y = v / N, x = v - y * N;
+    lds_st4(ldsr + y * 2 * S::P2 + x, fr[j]);
+  }
+  __syncthreads();
+  slab_forward_store<T, N, N>(lds, spec + (D + c) * nspec + soff, twx, twy, rtw);
+}
+
 // ------------------------------------------------------------------ launchers
 int transport_green_blocks(const Geom& g, int prec_bytes) {
   switch (g.last_n) {
@@ -259,7 +348,7 @@ int transport_green_blocks(const Geom& g, int prec_bytes) {
 template <typename T>
 hipError_t launch_transport_green(const Geom& g, const DevTables<T>& tb, int mode, void* spec,
                                   void* chat, const void* chat_m, double* partials,
-                                  TransportCtl* ctl, hipStream_t s) {
+                                  TransportCtl* ctl, int nfpart, hipStream_t s) {
   const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
   const T* rt = tb.rtab;
   TGreenGeom gg{g.dim, g.nx, g.xh, (int)g.plane, g.nspec, g.ntot};
@@ -272,7 +361,8 @@ hipError_t launch_transport_green(const Geom& g, const DevTables<T>& tb, int mod
     using C = ColCfg<T, LL, DD + 1>;                                                         \
     const int nb = (int)((g.plane + C::TX - 1) / C::TX);                                     \
     ACM_LAUNCH((k_transport_green<T, LL, DD, MM>), dim3(nb), dim3(C::NT),            \
-                       C::LDS_BYTES, s, sp, cp, cm, partials, ctl, gg, tw, rt + tb.off.sx,    \
+                       C::LDS_BYTES, s, sp, cp, cm, partials, ctl, gg, nfpart, tw,             \
+                       rt + tb.off.sx,                                                       \
                        rt + tb.off.lx, rt + tb.off.sy, rt + tb.off.ly, rt + tb.off.sz,       \
                        rt + tb.off.lz);                                                      \
   }
@@ -324,10 +414,35 @@ hipError_t launch_transport_local(const Geom& g, const DevTables<T>& tb, void* s
 #undef LAUNCH_TL
 }
 
+template <typename T>
+hipError_t launch_transport_slab(const Geom& g, const DevTables<T>& tb, void* spec, const T* u,
+                                 const uint8_t* H, const TransportCtl* ctl, hipStream_t s) {
+  const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
+  auto* sp = reinterpret_cast<cplx<T>*>(spec);
+  if (g.dim != 3 || g.nx != g.ny) return hipErrorInvalidValue;
+  dim3 grid((unsigned)g.nz, 3u, 1u);
+  switch (g.nx) {
+#define CASE(NN)                                                                                \
+  case NN: {                                                                                    \
+    using S = SlabCfg<T, NN, NN>;                                                               \
+    ACM_LAUNCH((k_transport_slab<T, NN>), grid, dim3(S::NT), S::LDS_BYTES, s, sp, u, H, ctl,    \
+               g.ntot, g.nspec, ct + tb.off.tw_x, ct + tb.off.tw_y, ct + tb.off.rtw);           \
+    return hipGetLastError();                                                                   \
+  }
+    ACM_SLAB_LENGTHS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
 #define INST(T)                                                                              \
   template hipError_t launch_transport_green<T>(const Geom&, const DevTables<T>&, int, void*, \
                                                 void*, const void*, double*, TransportCtl*,  \
-                                                hipStream_t);                                \
+                                                int, hipStream_t);                           \
+  template hipError_t launch_transport_slab<T>(const Geom&, const DevTables<T>&, void*,       \
+                                               const T*, const uint8_t*, const TransportCtl*, \
+                                               hipStream_t);                                 \
   template hipError_t launch_transport_local<T>(const Geom&, const DevTables<T>&, void*,      \
                                                 const T*, const uint8_t*,                    \
                                                 const TransportCtl*, hipStream_t);

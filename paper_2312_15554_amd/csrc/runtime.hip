@@ -350,7 +350,6 @@ static hipError_t enqueue_iteration(StokesGroup<T>& G, hipStream_t s, Profiler* 
     prof->end(kind, ev0);
     return r;
   };
-  prof->begin(KK_GREEN, &ev0);
   const int par = G.par;
   G.par ^= 1;
   if (prof->on) {
@@ -361,6 +360,7 @@ static hipError_t enqueue_iteration(StokesGroup<T>& G, hipStream_t s, Profiler* 
     if (e != hipSuccess) return e;
     prof->end(KK_OTHER, ev0);
   }
+  prof->begin(KK_GREEN, &ev0);
   e = launch_stokes_green<T>(g, tb, one, many, n, par, G.green_var, nullptr, s);
   if (e != hipSuccess) return e;
   prof->end(KK_GREEN, ev0);
@@ -864,8 +864,13 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
   double ubar_g = 0.0;
   for (int c = 0; c < d; ++c) ubar_g += (fs[1 + c] / fs[0]) * gchi[c];
 
+  // 3D cubes that fit take the slab form of the local pass (no separate y
+  // passes; f arrives as d partial spectra)
+  const bool tslab = d == 3 && slab_supported<T>(g) && ((uintptr_t)u % 16 == 0) &&
+                     ((uintptr_t)H % 4 == 0);
+  const int nfpart = tslab ? d : 1;
   const size_t cb = sizeof(T) * 2;
-  const size_t spec_b = cb * (size_t)g.nspec * (d + 1);
+  const size_t spec_b = cb * (size_t)g.nspec * (d + nfpart);
   const size_t one_b = cb * (size_t)g.nspec;
   const int ngreen = transport_green_blocks(g, pl->prec);
   const size_t part_b = sizeof(double) * 2 * (size_t)ngreen;
@@ -909,7 +914,8 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
     hipError_t e = launch_rows_r2c<T>(g, tb, 1, chi, chat, s);
     if (e == hipSuccess) e = launch_cols<T>(g, tb, 1, -1, 1, chat, s);
     if (e == hipSuccess && d == 3) e = launch_cols<T>(g, tb, 2, -1, 1, chat, s);
-    if (e == hipSuccess) e = launch_transport_green<T>(g, tb, 1, spec, chat, chat_m, part, dctl, s);
+    if (e == hipSuccess)
+      e = launch_transport_green<T>(g, tb, 1, spec, chat, chat_m, part, dctl, 1, s);
     if (e != hipSuccess) return fail(ACM_E_HIP, std::string("set-up: ") + hipGetErrorString(e));
   }
 
@@ -919,6 +925,17 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
   auto one_iter = [&]() -> hipError_t {
     hipError_t e;
     hipEvent_t ev0 = nullptr;
+    if (tslab) {
+      prof.begin(KK_T_LOCAL, &ev0);
+      e = launch_transport_slab<T>(g, tb, spec, u, H, dctl, s);
+      if (e != hipSuccess) return e;
+      prof.end(KK_T_LOCAL, ev0);
+      prof.begin(KK_T_GREEN, &ev0);
+      e = launch_transport_green<T>(g, tb, 0, spec, chat, chat_m, part, dctl, nfpart, s);
+      if (e != hipSuccess) return e;
+      prof.end(KK_T_GREEN, ev0);
+      return hipSuccess;
+    }
     if (d == 3) {
       prof.begin(KK_YINV, &ev0);
       e = launch_cols<T>(g, tb, 1, +1, d, spec, s, &dctl->done);
@@ -936,7 +953,7 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
       prof.end(KK_YFWD, ev0);
     }
     prof.begin(KK_T_GREEN, &ev0);
-    e = launch_transport_green<T>(g, tb, 0, spec, chat, chat_m, part, dctl, s);
+    e = launch_transport_green<T>(g, tb, 0, spec, chat, chat_m, part, dctl, 1, s);
     if (e != hipSuccess) return e;
     prof.end(KK_T_GREEN, ev0);
     return hipSuccess;

@@ -1,0 +1,147 @@
+// Shared pieces of the fused xy-slab passes (Stokes and transport): the slab
+// configuration (workgroup size, LDS pitch, occupancy target), the column
+// transforms of a slab held in LDS, and the forward half (rows, columns,
+// store) that turns a real slab into its half spectrum.
+#pragma once
+#include "pass_common.hpp"
+
+namespace acm {
+
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  using type = float4;
+};
+template <>
+struct Vec4<double> {
+  using type = double4;
+};
+
+
+// 4 consecutive reals of an LDS row (8-byte aligned)
+template <typename V, typename T>
+__device__ __forceinline__ V lds_ld4(const T* p) {
+  V v;
+  v.x = p[0];
+  v.y = p[1];
+  v.z = p[2];
+  v.w = p[3];
+  return v;
+}
+template <typename V, typename T>
+__device__ __forceinline__ void lds_st4(T* p, const V& v) {
+  p[0] = v.x;
+  p[1] = v.y;
+  p[2] = v.z;
+  p[3] = v.w;
+}
+
+template <typename T, int NX, int NY>
+struct SlabCfg {
+  static constexpr int M = NX / 2;
+  static constexpr int XH = M + 1;
+  // row pitch in complex values: odd, so the elements of a column (2 P2 dwords
+  // apart) fall in different LDS banks for the column transforms
+  static constexpr int P2 = XH;
+  static constexpr int TPPY = Plan<NY>::TPP;
+  static constexpr int TPPX = Plan<M>::TPP;
+  // NT_EVEN: workgroup of TPPY * M/2 threads (XH columns in three rounds, the
+  // last one column) instead of enough threads for two rounds; measured
+  // faster at 128^2, where 512 threads leave room for two workgroups per CU.
+  // PF: state loads issued before the slab load (2: u, H and a; 1: u and H,
+  // a after the column transforms; 0: each quad's state is loaded in the
+  // pointwise loop, which keeps the fewest registers live; measured fastest).
+  // UNR: unroll of the pointwise loop (with PF = 0 its loads sit in it).
+  static constexpr bool NT_EVEN = (NX == 128);
+  static constexpr int PF = 0;
+  static constexpr int NT0 = NT_EVEN ? ((TPPY * (M / 2) + 63) / 64) * 64
+                                     : ((TPPY * ((XH + 1) / 2) + 63) / 64) * 64;
+  static constexpr int NT = NT0 < 64 ? 64 : (NT0 > 1024 ? 1024 : NT0);
+  static constexpr int GY = NT / TPPY;  // column groups per round
+  static constexpr int GX = NT / TPPX;  // row groups per round
+  static constexpr int LDS_BYTES = NY * P2 * (int)sizeof(cplx<T>);
+  static constexpr int NV = NX * NY;                     // voxels per slab
+  static constexpr int NQ = NV / 4;                       // quads per slab
+  static constexpr int QPT = (NQ + NT - 1) / NT;          // quads per thread
+  static constexpr bool FULL = (NQ % NT) == 0;
+  static constexpr int UNR = QPT;
+  // loads in flight per thread when the rhs pass sums the partials (its state
+  // loads are already in registers then)
+  static constexpr int SUM_U = 4;
+  // Waves per SIMD that let as many workgroups reside per CU as LDS allows
+  // (CDNA: 4 SIMDs and 160 KB of LDS per CU; at most 4 workgroups counted):
+  // the minimum occupancy requested from the register allocator.
+  static constexpr int BLK_LDS = (160 * 1024) / (LDS_BYTES + 1024);
+  static constexpr int WPE = cmax(1, cmin(8, (cmin(BLK_LDS, 4) * (NT / 64) + 3) / 4));
+  // the single-launch pass keeps more state in registers: two workgroups
+  static constexpr int WPE_ONE = cmax(1, cmin(8, (cmin(BLK_LDS, 2) * (NT / 64) + 3) / 4));
+};
+
+// y transform of all XH columns of the slab held in LDS ([y][k], pitch P2).
+template <typename T, int NX, int NY, int SIGN>
+__device__ __forceinline__ void slab_cols(cplx<T>* lds, const cplx<T>* __restrict__ tw) {
+  using S = SlabCfg<T, NX, NY>;
+  const int grp = threadIdx.x / S::TPPY, t = threadIdx.x % S::TPPY;
+#pragma unroll 1
+  for (int c0 = 0; c0 < S::XH; c0 += S::GY) {
+    const int col = c0 + grp;
+    const bool act = grp < S::GY && col < S::XH;
+    PencilFFT<T, NY, 1, SIGN>::run_lds(t, act, lds + (act ? col : 0), 0, S::P2, tw);
+    __syncthreads();
+  }
+}
+
+// Forward half of the rhs pass on a real slab held in LDS (rows of pitch
+// 2 P2 reals): x transforms of the rows, y transforms of the columns, store.
+template <typename T, int NX, int NY>
+__device__ __forceinline__ void slab_forward_store(cplx<T>* lds, cplx<T>* __restrict__ dst,
+                                                   const cplx<T>* __restrict__ twx,
+                                                   const cplx<T>* __restrict__ twy,
+                                                   const cplx<T>* __restrict__ rtw) {
+  using S = SlabCfg<T, NX, NY>;
+  {
+    const int grp = threadIdx.x / S::TPPX, t = threadIdx.x % S::TPPX;
+#pragma unroll 1
+    for (int r0 = 0; r0 < NY; r0 += S::GX) {
+      const int row = r0 + grp;
+      const bool act = grp < S::GX && row < NY;
+      rows_r2c_lds<T, S::M, 1, S::P2>(lds, 0, act ? row : 0, t, act, twx, rtw);
+    }
+  }
+  slab_cols<T, NX, NY, -1>(lds, twy);
+  for (int v = threadIdx.x; v < NY * S::XH; v += S::NT) {
+    const int y = v / S::XH, k = v - y * S::XH;
+    dst[v] = lds[y * S::P2 + k];
+  }
+}
+
+// Load the half-spectrum slab `src` ([y][k], k < XH) into LDS and take it back
+// to real space: inverse y transforms of the columns, then inverse x
+// transforms of the rows.  Row y of the result starts at real offset
+// y * 2 * P2.  Ends with a barrier.
+template <typename T, int NX, int NY>
+__device__ __forceinline__ void slab_load_inverse(cplx<T>* lds, const cplx<T>* __restrict__ src,
+                                                  const cplx<T>* __restrict__ twx,
+                                                  const cplx<T>* __restrict__ twy,
+                                                  const cplx<T>* __restrict__ rtw) {
+  using S = SlabCfg<T, NX, NY>;
+  for (int v = threadIdx.x; v < NY * S::XH; v += S::NT) {
+    const int y = v / S::XH, k = v - y * S::XH;
+    lds[y * S::P2 + k] = src[v];
+  }
+  __syncthreads();
+  slab_cols<T, NX, NY, +1>(lds, twy);
+  const int grp = threadIdx.x / S::TPPX, t = threadIdx.x % S::TPPX;
+#pragma unroll 1
+  for (int r0 = 0; r0 < NY; r0 += S::GX) {
+    const int row = r0 + grp;
+    const bool act = grp < S::GX && row < NY;
+    rows_c2r_lds<T, S::M, 1, S::P2>(lds, 0, act ? row : 0, t, act, twx, rtw);
+  }
+}
+
+// Square slab lengths compiled for the fused passes.
+#define ACM_SLAB_LENGTHS(X) X(32) X(48) X(64) X(96) X(128)
+
+}  // namespace acm

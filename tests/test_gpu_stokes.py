@@ -296,3 +296,24 @@ def test_full_size_converged_solve_satisfies_its_residuals():
     K = acm_effective_props(H, [r["u"]], nu=1.0)["K"]
     Ko = O.permeability_darcy([u])
     assert np.max(np.abs(np.array(K) - Ko)) <= 1e-9 * np.max(np.abs(Ko))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("shape,pass_mode", [((16, 32, 32), 2), ((16, 32, 32), 1), ((16, 24), 0)])
+def test_profile_mode_times_every_pass_and_changes_nothing(shape, pass_mode):
+    """opts.profile = 1 (eager launches with per-dispatch events) gives the same
+    iterates as the graph path and reports a time for every pass it ran and
+    for the empty calibration kernel."""
+    require_gpu()
+    print(f"profile mode shape={shape} mode={pass_mode}", flush=True)
+    H = I.random_mask(shape, 31, 0.35)
+    g = (1.0, -0.2, 0.4)[:len(shape)]
+    kw = dict(eps=0.0, max_iter=30, pass_mode=pass_mode)
+    r0 = _solve(H, g, **kw)
+    r1 = _solve(H, g, profile=True, **kw)
+    assert torch.equal(r0["u"], r1["u"])
+    st = r1["stats"]
+    kinds = ["green", "local", "rhs", "other"] + (["y_inv", "y_fwd"] if pass_mode == 1 else [])
+    for k in kinds:
+        assert st["kernel_calls"][k] == 30, (k, st["kernel_calls"])
+        assert st["kernel_ms"][k] > 0.0, k

@@ -23,12 +23,15 @@ def _flow(H, g):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("shape", [(16, 16), (16, 24, 32), (16, 16, 16)])
+@pytest.mark.parametrize("shape", [(16, 16), (16, 24, 32), (16, 16, 16), (16, 32, 32), (8, 48, 48),
+                                   (8, 96, 96)])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("dt", [math.inf, 5e-3])
 def test_ls_iterates_match_oracle(shape, dtype, dt):
     """Fixed iteration count (eps = 0): chi of the HIP path equals the
-    oracle's after the same LS iterations (eq. iter / eq. fft_solute)."""
+    oracle's after the same LS iterations (eq. iter / eq. fft_solute).  Cubes
+    in x-y with nx = ny in {32, 48, 96} take the slab form of the local pass,
+    the others the row form with separate y passes."""
     require_gpu()
     from paper_2312_15554_amd.api import acm_transport_step
     print(f"LS parity shape={shape} dtype={dtype} dt={dt}", flush=True)
