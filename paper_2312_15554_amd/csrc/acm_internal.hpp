@@ -84,6 +84,20 @@ struct LaunchEvents {
 LaunchEvents& launch_events();
 
 // Control block for one Lippmann-Schwinger solve (one time step at a time).
+// Per-iteration LS state, two slots chosen by iteration parity (as for the
+// ADMM state): the passes of iteration n read slot n mod 2 and the stop test
+// that follows writes slot (n + 1) mod 2.
+struct TransportState {
+  double r1, r2;
+  double r1_min;        // smallest r_1 of the current time step (divergence test)
+  int64_t iter;         // iterations in the current time step
+  int64_t total_iter;
+  int32_t done;         // sticky: once set in either slot every pass exits
+  int32_t status;
+  int32_t pend;         // slab path: a green pass ran whose partials are not yet judged
+  int32_t pad_;
+};
+
 struct TransportCtl {
   double eps;
   double sqrt_n1, sqrt_n2;
@@ -92,16 +106,46 @@ struct TransportCtl {
   double g[3];
   double Pe, eta, diff;
   double calF;          // Pe * ubar . g  (multiplied by (1-H) per voxel)
-  double r1, r2;
-  double r1_min;        // smallest r_1 of the current time step (divergence test)
-  int64_t iter;         // iterations in the current time step
-  int64_t total_iter;
   int64_t max_iter;
-  int32_t done;
-  int32_t status;
   int32_t steady;
+  int32_t pad_;
+  TransportState st[2];
   alignas(256) uint32_t counter;  // on its own cache line (see StokesCtl)
 };
+
+__host__ __device__ inline bool transport_done(const TransportCtl* c) {
+  return (c->st[0].done | c->st[1].done) != 0;
+}
+
+// Stop test of eq. tol_solute from the Parseval totals of one green pass (the
+// divergence guard included): the state after `cur`.
+__host__ __device__ inline TransportState transport_judge(const TransportCtl* c,
+                                                          const TransportState& cur,
+                                                          double tot0, double tot1,
+                                                          int64_t ntot) {
+  TransportState nx = cur;
+  const double inv_n = 1.0 / (double)ntot;
+  const double r1 = sqrt(tot0 * inv_n), r2 = sqrt(tot1 * inv_n);
+  nx.r1 = r1;
+  nx.r2 = r2;
+  nx.iter = cur.iter + 1;
+  nx.total_iter = cur.total_iter + 1;
+  nx.pend = 0;
+  // divergence: non-finite, or r_1 grown a millionfold over its minimum
+  // (the LS iteration contracts only for a large enough comparison medium)
+  if (r1 < nx.r1_min) nx.r1_min = r1;
+  if (!isfinite(r1) || !isfinite(r2) || (nx.iter > 5 && r1 > 1e6 * nx.r1_min)) {
+    nx.done = 1;
+    nx.status = -5;
+  } else if (r1 <= c->sqrt_n1 * c->eps && r2 <= c->sqrt_n2 * c->eps) {
+    nx.done = 1;
+    nx.status = 0;
+  } else if (nx.iter >= c->max_iter) {
+    nx.done = 1;
+    nx.status = 1;
+  }
+  return nx;
+}
 
 // Per-cell device pointers of one Stokes solve.  Kernels of a batched launch
 // read the entry of their cell (blockIdx.z); a single cell passes it by value.
@@ -195,16 +239,24 @@ hipError_t launch_stokes_rhs(const Geom& g, const DevTables<T>& tb, const Stokes
                              const StokesCellArgs* many, int ncells, int slot, hipStream_t s);
 
 // Lippmann-Schwinger passes.  mode 0: LS update; mode 1: grad chi-hat only.
+// `par`: iteration parity.  judge = 1: the last workgroup applies the stop
+// test (writes slot par ^ 1); judge = 0: only the partial sums are posted and
+// the next slab pass judges them.
 template <typename T>
 hipError_t launch_transport_green(const Geom& g, const DevTables<T>& tb, int mode, void* spec,
                                   void* chat, const void* chat_m, double* partials,
-                                  TransportCtl* ctl, int nfpart, hipStream_t s);
+                                  TransportCtl* ctl, int nfpart, int par, int judge,
+                                  hipStream_t s);
 // Slab form of the local pass (3D, nx == ny <= 128, u 16-byte aligned): reads
 // grad chi-hat from fields 0..2 and writes tau-hat to fields 0..2 and the
 // three partial spectra of f to fields 3..5 (green then runs with nfpart = 3).
+// Every workgroup first judges the pending green pass from its partial sums
+// (slot par; workgroup 0 stores the result in slot par ^ 1), then runs the
+// local pass unless the solve has stopped.
 template <typename T>
 hipError_t launch_transport_slab(const Geom& g, const DevTables<T>& tb, void* spec, const T* u,
-                                 const uint8_t* H, const TransportCtl* ctl, hipStream_t s);
+                                 const uint8_t* H, TransportCtl* ctl, const double* partials,
+                                 int ngreen, int par, hipStream_t s);
 template <typename T>
 hipError_t launch_transport_local(const Geom& g, const DevTables<T>& tb, void* spec, const T* u,
                                   const uint8_t* H, const TransportCtl* ctl, hipStream_t s);

@@ -39,7 +39,7 @@ using TGCfg = ColCfg<T, L, NC, kTGVar, kTGSpl>;
 template <typename T, int L, int D, int MODE>
 __global__ __launch_bounds__((TGCfg<T, L, D + 1>::NT)) void k_transport_green(
     cplx<T>* __restrict__ spec, cplx<T>* __restrict__ chat, const cplx<T>* __restrict__ chat_m,
-    double* __restrict__ partials, TransportCtl* ctl, TGreenGeom gg, int nfpart,
+    double* __restrict__ partials, TransportCtl* ctl, TGreenGeom gg, int nfpart, int par, int judge,
     const cplx<T>* __restrict__ tw, const T* __restrict__ sx, const T* __restrict__ lx,
     const T* __restrict__ sy, const T* __restrict__ ly, const T* __restrict__ sz,
     const T* __restrict__ lz) {
@@ -50,7 +50,7 @@ __global__ __launch_bounds__((TGCfg<T, L, D + 1>::NT)) void k_transport_green(
   __shared__ double red[2 * 16];
   __shared__ int s_last;
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-  if (MODE == 0 && ctl->done) return;
+  if (MODE == 0 && transport_done(ctl)) return;
   const int P = gg.plane;
   const int f0 = blockIdx.x * C::TX;
   // transform threads: (field, t, column) when each field has its own threads
@@ -175,6 +175,14 @@ __global__ __launch_bounds__((TGCfg<T, L, D + 1>::NT)) void k_transport_green(
   }
   if constexpr (MODE == 0) {
     block_sum<2>(acc, red);
+    if (!judge) {
+      // the next slab pass judges these partials after the launch boundary
+      if (threadIdx.x == 0) {
+        partials[blockIdx.x * 2 + 0] = acc[0];
+        partials[blockIdx.x * 2 + 1] = acc[1];
+      }
+      return;
+    }
     if (threadIdx.x == 0) {
       partials[blockIdx.x * 2 + 0] = acc[0];
       partials[blockIdx.x * 2 + 1] = acc[1];
@@ -192,26 +200,7 @@ __global__ __launch_bounds__((TGCfg<T, L, D + 1>::NT)) void k_transport_green(
       }
       block_sum<2>(tot, red);
       if (threadIdx.x == 0) {
-        const double inv_n = 1.0 / (double)gg.ntot;
-        const double r1 = sqrt(tot[0] * inv_n), r2 = sqrt(tot[1] * inv_n);
-        ctl->r1 = r1;
-        ctl->r2 = r2;
-        const int64_t it = ctl->iter + 1;
-        ctl->iter = it;
-        ctl->total_iter += 1;
-        // divergence: non-finite, or r_1 grown a millionfold over its minimum
-        // (the LS iteration contracts only for a large enough comparison medium)
-        if (r1 < ctl->r1_min) ctl->r1_min = r1;
-        if (!isfinite(r1) || !isfinite(r2) || (it > 5 && r1 > 1e6 * ctl->r1_min)) {
-          ctl->done = 1;
-          ctl->status = -5;
-        } else if (r1 <= ctl->sqrt_n1 * ctl->eps && r2 <= ctl->sqrt_n2 * ctl->eps) {
-          ctl->done = 1;
-          ctl->status = 0;
-        } else if (it >= ctl->max_iter) {
-          ctl->done = 1;
-          ctl->status = 1;
-        }
+        ctl->st[par ^ 1] = transport_judge(ctl, ctl->st[par], tot[0], tot[1], gg.ntot);
         ctl->counter = 0u;
       }
     }
@@ -228,7 +217,7 @@ __global__ __launch_bounds__((RowCfgN<T, M, D + 1>::NT)) void k_transport_local(
   extern __shared__ __align__(16) char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   T* ldsr = reinterpret_cast<T*>(smem_raw);
-  if (ctl->done) return;
+  if (transport_done(ctl)) return;
   const int row0 = blockIdx.x * C::RB;
   const int nr = min(C::RB, nrows - row0);
   for (int c = 0; c < D; ++c) {
@@ -279,16 +268,39 @@ template <typename T, int N>
 __global__ __launch_bounds__((SlabCfg<T, N, N>::NT))
 __attribute__((amdgpu_waves_per_eu(SlabCfg<T, N, N>::WPE_ONE))) void k_transport_slab(
     cplx<T>* __restrict__ spec, const T* __restrict__ u, const uint8_t* __restrict__ H,
-    const TransportCtl* __restrict__ ctl, int64_t ntot, int64_t nspec,
-    const cplx<T>* __restrict__ twx, const cplx<T>* __restrict__ twy,
+    TransportCtl* ctl, const double* __restrict__ partials, int ngreen, int par, int64_t ntot,
+    int64_t nspec, const cplx<T>* __restrict__ twx, const cplx<T>* __restrict__ twy,
     const cplx<T>* __restrict__ rtw) {
   using S = SlabCfg<T, N, N>;
   using V = typename Vec4<T>::type;
   constexpr int D = 3;
   extern __shared__ __align__(32) char smem_raw[];
+  __shared__ double red[2 * 16];
+  __shared__ int s_stop;
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   T* ldsr = reinterpret_cast<T*>(smem_raw);
-  if (ctl->done) return;
+  if (transport_done(ctl)) return;
+  // Stop test of the previous green pass, formed by every workgroup from all
+  // its partial sums in the same order (same bits); workgroup 0 stores it.
+  {
+    const TransportState cur = ctl->st[par];
+    double tot[2] = {0.0, 0.0};
+    if (cur.pend) {
+      for (int j = threadIdx.x; j < ngreen; j += S::NT) {
+        tot[0] += partials[j * 2 + 0];
+        tot[1] += partials[j * 2 + 1];
+      }
+      block_sum<2>(tot, red);
+    }
+    if (threadIdx.x == 0) {
+      TransportState nx = cur.pend ? transport_judge(ctl, cur, tot[0], tot[1], ntot) : cur;
+      nx.pend = nx.done ? 0 : 1;  // the green pass of this iteration will run
+      if (blockIdx.x == 0 && blockIdx.y == 0) ctl->st[par ^ 1] = nx;
+      s_stop = nx.done;
+    }
+    __syncthreads();
+    if (s_stop) return;
+  }
   const int z = blockIdx.x, c = blockIdx.y;
   const int64_t soff = (int64_t)z * N * S::XH;
   slab_load_inverse<T, N, N>(lds, spec + c * nspec + soff, twx, twy, rtw);
@@ -369,7 +381,8 @@ int transport_green_blocks(const Geom& g, int prec_bytes) {
 template <typename T>
 hipError_t launch_transport_green(const Geom& g, const DevTables<T>& tb, int mode, void* spec,
                                   void* chat, const void* chat_m, double* partials,
-                                  TransportCtl* ctl, int nfpart, hipStream_t s) {
+                                  TransportCtl* ctl, int nfpart, int par, int judge,
+                                  hipStream_t s) {
   const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
   const T* rt = tb.rtab;
   TGreenGeom gg{g.dim, g.nx, g.xh, (int)g.plane, g.nspec, g.ntot};
@@ -382,7 +395,8 @@ hipError_t launch_transport_green(const Geom& g, const DevTables<T>& tb, int mod
     using C = TGCfg<T, LL, DD + 1>;                                                          \
     const int nb = (int)((g.plane + C::TX - 1) / C::TX);                                     \
     ACM_LAUNCH((k_transport_green<T, LL, DD, MM>), dim3(nb), dim3(C::NT),            \
-                       C::LDS_BYTES, s, sp, cp, cm, partials, ctl, gg, nfpart, tw,             \
+                       C::LDS_BYTES, s, sp, cp, cm, partials, ctl, gg, nfpart, par, judge,     \
+                       tw,                                                                   \
                        rt + tb.off.sx,                                                       \
                        rt + tb.off.lx, rt + tb.off.sy, rt + tb.off.ly, rt + tb.off.sz,       \
                        rt + tb.off.lz);                                                      \
@@ -437,7 +451,8 @@ hipError_t launch_transport_local(const Geom& g, const DevTables<T>& tb, void* s
 
 template <typename T>
 hipError_t launch_transport_slab(const Geom& g, const DevTables<T>& tb, void* spec, const T* u,
-                                 const uint8_t* H, const TransportCtl* ctl, hipStream_t s) {
+                                 const uint8_t* H, TransportCtl* ctl, const double* partials,
+                                 int ngreen, int par, hipStream_t s) {
   const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
   auto* sp = reinterpret_cast<cplx<T>*>(spec);
   if (g.dim != 3 || g.nx != g.ny) return hipErrorInvalidValue;
@@ -447,7 +462,8 @@ hipError_t launch_transport_slab(const Geom& g, const DevTables<T>& tb, void* sp
   case NN: {                                                                                    \
     using S = SlabCfg<T, NN, NN>;                                                               \
     ACM_LAUNCH((k_transport_slab<T, NN>), grid, dim3(S::NT), S::LDS_BYTES, s, sp, u, H, ctl,    \
-               g.ntot, g.nspec, ct + tb.off.tw_x, ct + tb.off.tw_y, ct + tb.off.rtw);           \
+               partials, ngreen, par, g.ntot, g.nspec, ct + tb.off.tw_x, ct + tb.off.tw_y,      \
+               ct + tb.off.rtw);                                                                \
     return hipGetLastError();                                                                   \
   }
     ACM_SLAB_LENGTHS(CASE)
@@ -460,10 +476,10 @@ hipError_t launch_transport_slab(const Geom& g, const DevTables<T>& tb, void* sp
 #define INST(T)                                                                              \
   template hipError_t launch_transport_green<T>(const Geom&, const DevTables<T>&, int, void*, \
                                                 void*, const void*, double*, TransportCtl*,  \
-                                                int, hipStream_t);                           \
+                                                int, int, int, hipStream_t);                 \
   template hipError_t launch_transport_slab<T>(const Geom&, const DevTables<T>&, void*,       \
-                                               const T*, const uint8_t*, const TransportCtl*, \
-                                               hipStream_t);                                 \
+                                               const T*, const uint8_t*, TransportCtl*,      \
+                                               const double*, int, int, hipStream_t);        \
   template hipError_t launch_transport_local<T>(const Geom&, const DevTables<T>&, void*,      \
                                                 const T*, const uint8_t*,                    \
                                                 const TransportCtl*, hipStream_t);

@@ -308,6 +308,11 @@ static std::vector<hipStream_t> branch_streams(int dev, int n) {
 static const StokesState& latest_state(const StokesCtl& c) {
   return c.st[1].iter > c.st[0].iter ? c.st[1] : c.st[0];
 }
+static const TransportState& latest_tstate(const TransportCtl& c) {
+  if (c.st[0].total_iter != c.st[1].total_iter)
+    return c.st[1].total_iter > c.st[0].total_iter ? c.st[1] : c.st[0];
+  return c.st[1].done ? c.st[1] : c.st[0];
+}
 
 // Cells sharing one plan (same grid and precision) are launched together.
 template <typename T>
@@ -906,7 +911,8 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
   c.calF = Pe * ubar_g;
   c.max_iter = o.max_iter;
   c.steady = steady ? 1 : 0;
-  c.status = 1;
+  c.st[0].status = 1;
+  c.st[1] = c.st[0];
   HIP_TRY(hipMemcpyAsync(dctl, &c, sizeof(c), hipMemcpyHostToDevice, s));
 
   // chi-hat^0 = FFT(chi^0); grad chi-hat^0 in the layout the local pass reads
@@ -915,30 +921,38 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
     if (e == hipSuccess) e = launch_cols<T>(g, tb, 1, -1, 1, chat, s);
     if (e == hipSuccess && d == 3) e = launch_cols<T>(g, tb, 2, -1, 1, chat, s);
     if (e == hipSuccess)
-      e = launch_transport_green<T>(g, tb, 1, spec, chat, chat_m, part, dctl, 1, s);
+      e = launch_transport_green<T>(g, tb, 1, spec, chat, chat_m, part, dctl, 1, 0, 1, s);
     if (e != hipSuccess) return fail(ACM_E_HIP, std::string("set-up: ") + hipGetErrorString(e));
   }
 
   Profiler prof;
   prof.on = o.profile != 0;
   prof.s = s;
+  // Iterations alternate between the two state slots (see TransportState);
+  // a captured graph holds an even number of them, so every replay starts on
+  // slot 0.  On the slab path the stop test of iteration n is formed by the
+  // slab pass of iteration n + 1 (no cross-workgroup traffic in the green pass).
+  int tpar = 0;
   auto one_iter = [&]() -> hipError_t {
     hipError_t e;
     hipEvent_t ev0 = nullptr;
+    const int par = tpar;
+    tpar ^= 1;
     if (tslab) {
       prof.begin(KK_T_LOCAL, &ev0);
-      e = launch_transport_slab<T>(g, tb, spec, u, H, dctl, s);
+      e = launch_transport_slab<T>(g, tb, spec, u, H, dctl, part, ngreen, par, s);
       if (e != hipSuccess) return e;
       prof.end(KK_T_LOCAL, ev0);
       prof.begin(KK_T_GREEN, &ev0);
-      e = launch_transport_green<T>(g, tb, 0, spec, chat, chat_m, part, dctl, nfpart, s);
+      e = launch_transport_green<T>(g, tb, 0, spec, chat, chat_m, part, dctl, nfpart, par ^ 1, 0,
+                                    s);
       if (e != hipSuccess) return e;
       prof.end(KK_T_GREEN, ev0);
       return hipSuccess;
     }
     if (d == 3) {
       prof.begin(KK_YINV, &ev0);
-      e = launch_cols<T>(g, tb, 1, +1, d, spec, s, &dctl->done);
+      e = launch_cols<T>(g, tb, 1, +1, d, spec, s, &dctl->st[0].done, &dctl->st[1].done);
       if (e != hipSuccess) return e;
       prof.end(KK_YINV, ev0);
     }
@@ -948,12 +962,12 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
     prof.end(KK_T_LOCAL, ev0);
     if (d == 3) {
       prof.begin(KK_YFWD, &ev0);
-      e = launch_cols<T>(g, tb, 1, -1, d + 1, spec, s, &dctl->done);
+      e = launch_cols<T>(g, tb, 1, -1, d + 1, spec, s, &dctl->st[0].done, &dctl->st[1].done);
       if (e != hipSuccess) return e;
       prof.end(KK_YFWD, ev0);
     }
     prof.begin(KK_T_GREEN, &ev0);
-    e = launch_transport_green<T>(g, tb, 0, spec, chat, chat_m, part, dctl, 1, s);
+    e = launch_transport_green<T>(g, tb, 0, spec, chat, chat_m, part, dctl, 1, par, 1, s);
     if (e != hipSuccess) return e;
     prof.end(KK_T_GREEN, ev0);
     return hipSuccess;
@@ -962,6 +976,7 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
   int K = o.check_every;
   if (K <= 0) K = 16;
   if (o.max_iter < K) K = (int)std::max<int64_t>(1, o.max_iter);
+  K += K & 1;  // even: see one_iter
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   const bool use_graph = o.use_graph && !prof.on;
@@ -999,12 +1014,17 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
   int status = 0;
   for (int step = 0; step < n_steps; ++step) {
     if (!steady) HIP_TRY(hipMemcpyAsync(chat_m, chat, one_b, hipMemcpyDeviceToDevice, s));
-    c.iter = 0;
-    c.total_iter = total;
-    c.r1_min = INFINITY;
-    c.done = 0;
-    c.status = 1;
+    TransportState s0{};
+    s0.iter = 0;
+    s0.total_iter = total;
+    s0.r1_min = INFINITY;
+    s0.done = 0;
+    s0.status = 1;
+    s0.pend = 0;
+    c.st[0] = s0;
+    c.st[1] = s0;
     c.counter = 0;
+    tpar = 0;
     HIP_TRY(hipMemcpyAsync(dctl, &c, sizeof(c), hipMemcpyHostToDevice, s));
     int64_t launched = 0;
     for (;;) {
@@ -1020,15 +1040,16 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
       HIP_TRY(hipMemcpyAsync(hctl, dctl, sizeof(TransportCtl), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
       prof.collect();
-      if (hctl->done) break;
+      if (transport_done(hctl)) break;
       if (launched > o.max_iter + 2LL * K) break;
     }
-    total = hctl->total_iter;
-    if (hctl->status == -5) {
+    const TransportState& ls = latest_tstate(*hctl);
+    total = ls.total_iter;
+    if (ls.status == -5) {
       status = -5;
       break;
     }
-    if (hctl->status != 0) status = 1;
+    if (ls.status != 0) status = 1;
   }
   auto t1 = std::chrono::steady_clock::now();
   if (status == -5) return fail(ACM_E_DIVERGED, "a transport residual became non-finite");
@@ -1045,8 +1066,8 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
   if (st) {
     memset(st, 0, sizeof(*st));
     st->iters = total;
-    st->r_p[0] = hctl->r1;
-    st->r_p[1] = hctl->r2;
+    st->r_p[0] = latest_tstate(*hctl).r1;
+    st->r_p[1] = latest_tstate(*hctl).r2;
     st->tol_p[0] = c.sqrt_n1 * o.eps;
     st->tol_p[1] = c.sqrt_n2 * o.eps;
     st->seconds = std::chrono::duration<double>(t1 - t0).count();
