@@ -19,15 +19,23 @@ from .api import acm_stokes_solve, acm_stokes_solve_batched
 from .fno import FNO
 
 
-def make_cells(n: int, count: int, seed0: int, radius_vox: float, por_lo: float, por_hi: float):
+def _one_cell(args):
+    n, seed, radius_vox, por_lo, por_hi = args
+    por = por_lo + (por_hi - por_lo) * I.SplitMix64(seed ^ 0x5DEECE66D).uniform()
+    return I.overlapping_spheres(n, radius_vox, por, seed=seed)
+
+
+def make_cells(n: int, count: int, seed0: int, radius_vox: float, por_lo: float, por_hi: float,
+               workers: int = 1):
     """Overlapping-sphere cells with porosity drawn uniformly in [por_lo, por_hi]
-    (the draw uses the cell's own SplitMix64 stream)."""
-    cells = []
-    for i in range(count):
-        seed = seed0 + i
-        por = por_lo + (por_hi - por_lo) * I.SplitMix64(seed ^ 0x5DEECE66D).uniform()
-        cells.append(I.overlapping_spheres(n, radius_vox, por, seed=seed))
-    return cells
+    (the draw uses the cell's own SplitMix64 stream).  workers > 1 builds them
+    in a process pool: call it only before the process has touched the GPU."""
+    jobs = [(n, seed0 + i, radius_vox, por_lo, por_hi) for i in range(count)]
+    if workers <= 1 or count < 2 * workers:
+        return [_one_cell(j) for j in jobs]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_one_cell, jobs, chunksize=max(1, count // (8 * workers)))
 
 
 def generate_dataset(cells, eps=1e-6, batch=64, max_iter=200000, log=print):
