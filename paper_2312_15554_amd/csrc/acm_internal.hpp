@@ -245,11 +245,11 @@ hipError_t launch_stokes_rhs(const Geom& g, const DevTables<T>& tb, const Stokes
 template <typename T>
 hipError_t launch_transport_green(const Geom& g, const DevTables<T>& tb, int mode, void* spec,
                                   void* chat, const void* chat_m, double* partials,
-                                  TransportCtl* ctl, int nfpart, int par, int judge,
+                                  TransportCtl* ctl, int slab, int par, int judge,
                                   hipStream_t s);
 // Slab form of the local pass (3D, nx == ny <= 128, u 16-byte aligned): reads
-// grad chi-hat from fields 0..2 and writes tau-hat to fields 0..2 and the
-// three partial spectra of f to fields 3..5 (green then runs with nfpart = 3).
+// grad chi-hat from fields 0..2 and writes G_x, G_y, f_z (fields 0..2) and
+// tau_z (field 3) for the green pass's slab input form (slab = 1).
 // Every workgroup first judges the pending green pass from its partial sums
 // (slot par; workgroup 0 stores the result in slot par ^ 1), then runs the
 // local pass unless the solve has stopped.
@@ -260,7 +260,9 @@ hipError_t launch_transport_slab(const Geom& g, const DevTables<T>& tb, void* sp
 template <typename T>
 hipError_t launch_transport_local(const Geom& g, const DevTables<T>& tb, void* spec, const T* u,
                                   const uint8_t* H, const TransportCtl* ctl, hipStream_t s);
-int transport_green_blocks(const Geom& g, int precision_bytes);
+// Green workgroups per cell (= partial-sum records) for the row (slab = false)
+// or slab input form.
+int transport_green_blocks(const Geom& g, int precision_bytes, bool slab);
 
 // FP64 reductions (per-block partials; the host adds them in order).
 template <typename T>

@@ -35,17 +35,25 @@ constexpr int kTGSpl = 1;
 template <typename T, int L, int NC>
 using TGCfg = ColCfg<T, L, NC, kTGVar, kTGSpl>;
 
+// Fields the green pass transforms forward: the row form brings tau-hat (D
+// fields) and f-hat; the slab form (SL) brings S = G_x + G_y + f_z as three
+// partial spectra, summed on load, and tau_z (see k_transport_slab).
+template <int D, bool SL>
+constexpr int tg_inputs() { return SL ? 2 : D + 1; }
+template <int D, bool SL>
+constexpr int tg_fields() { return SL ? D : D + 1; }
+
 // MODE 0: LS update.  MODE 1: only form grad chi-hat from chi-hat (set-up).
-template <typename T, int L, int D, int MODE>
-__global__ __launch_bounds__((TGCfg<T, L, D + 1>::NT)) void k_transport_green(
+template <typename T, int L, int D, int MODE, bool SL>
+__global__ __launch_bounds__((TGCfg<T, L, tg_fields<D, SL>()>::NT)) void k_transport_green(
     cplx<T>* __restrict__ spec, cplx<T>* __restrict__ chat, const cplx<T>* __restrict__ chat_m,
-    double* __restrict__ partials, TransportCtl* ctl, TGreenGeom gg, int nfpart, int par, int judge,
+    double* __restrict__ partials, TransportCtl* ctl, TGreenGeom gg, int par, int judge,
     const cplx<T>* __restrict__ tw, const T* __restrict__ sx, const T* __restrict__ lx,
     const T* __restrict__ sy, const T* __restrict__ ly, const T* __restrict__ sz,
     const T* __restrict__ lz) {
-  using C = TGCfg<T, L, D + 1>;
+  using C = TGCfg<T, L, tg_fields<D, SL>()>;
   constexpr int PS = L * C::TX;
-  constexpr int NIN = D + 1;
+  constexpr int NIN = tg_inputs<D, SL>();
   extern __shared__ __align__(16) char smem_raw[];
   __shared__ double red[2 * 16];
   __shared__ int s_last;
@@ -66,13 +74,16 @@ __global__ __launch_bounds__((TGCfg<T, L, D + 1>::NT)) void k_transport_green(
       const int f = f0 + col;
       cplx<T> v = cmake<T>(T(0), T(0));
       if (f < P) {
-        v = spec[c * gg.nspec + (int64_t)i * P + f];
-        // f-hat may arrive as nfpart partial spectra (one per field of the
-        // slab pass) in consecutive fields: their sum is f-hat
-        for (int j = 1; c == D && j < nfpart; ++j) {
-          const cplx<T> w = spec[(c + j) * gg.nspec + (int64_t)i * P + f];
-          v.x += w.x;
-          v.y += w.y;
+        const int64_t mi = (int64_t)i * P + f;
+        if constexpr (SL) {
+          if (c == 0) {  // S = G_x + G_y + f_z
+            const cplx<T> a = spec[mi], b = spec[gg.nspec + mi], d = spec[2 * gg.nspec + mi];
+            v = cmake<T>(a.x + b.x + d.x, a.y + b.y + d.y);
+          } else {  // tau_z
+            v = spec[3 * gg.nspec + mi];
+          }
+        } else {
+          v = spec[c * gg.nspec + mi];
         }
       }
       lds[e] = v;
@@ -118,15 +129,25 @@ __global__ __launch_bounds__((TGCfg<T, L, D + 1>::NT)) void k_transport_green(
     cplx<T> cn;
     if constexpr (MODE == 0) {
       const bool k0 = (kx == 0 && ky == 0 && kz == 0);
-      // F-hat = f-hat + i s . tau-hat
-      cplx<T> F = lds[D * PS + e];
+      // F-hat = f-hat + i s . tau-hat (slab form: S-hat + i s_z tau_z-hat, the
+      // x and y terms being already in S as central differences)
+      cplx<T> F;
       T bs = T(0);
 #pragma unroll
-      for (int c = 0; c < D; ++c) {
-        const cplx<T> tc = lds[c * PS + e];
-        F.x -= s[c] * tc.y;
-        F.y += s[c] * tc.x;
-        bs += B0[c] * s[c];
+      for (int c = 0; c < D; ++c) bs += B0[c] * s[c];
+      if constexpr (SL) {
+        F = lds[e];
+        const cplx<T> tz = lds[PS + e];
+        F.x -= s[D - 1] * tz.y;
+        F.y += s[D - 1] * tz.x;
+      } else {
+        F = lds[D * PS + e];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          const cplx<T> tc = lds[c * PS + e];
+          F.x -= s[c] * tc.y;
+          F.y += s[c] * tc.x;
+        }
       }
       if (k0) {
         double b0g = 0.0;
@@ -259,11 +280,13 @@ __global__ __launch_bounds__((RowCfgN<T, M, D + 1>::NT)) void k_transport_local(
 // Local pass on xy-slabs (3D cubes whose slab fits in LDS): workgroup (z, c)
 // takes the z-slab of d_c chi back to real space (column then row inverse
 // transforms), forms e_c = d_c chi + g_c, tau_c = (A - A0) e_c and this field's
-// share of f, f_c = calF (1-H) [c = 0 only] - (B_c - B0_c) e_c, and transforms
-// tau_c and f_c forward (rows then columns) into fields c and D + c.  The
-// green pass adds the D partial spectra of f.  Compared with the row pass it
-// saves the separate y passes (2 x 7 half-spectrum round trips per iteration)
-// at the price of D - 1 extra spectra of f written and read.
+// share of f, f_c = calF (1-H) [c = 0 only] - (B_c - B0_c) e_c.  Since F =
+// f + div tau, the x and y workgroups fold their divergence term in real
+// space, G_c = f_c + D_c tau_c, and transform only G_c (into field c); the z
+// workgroup transforms f_z (field 2) and tau_z (field 3), whose derivative
+// needs the z transform.  The green pass then transforms S = G_x + G_y + f_z
+// and tau_z.  Compared with the row pass this saves the separate y passes and
+// three of the seven forward transforms of the iteration.
 template <typename T, int N>
 __global__ __launch_bounds__((SlabCfg<T, N, N>::NT))
 __attribute__((amdgpu_waves_per_eu(SlabCfg<T, N, N>::WPE_ONE))) void k_transport_slab(
@@ -345,8 +368,44 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, N, N>::WPE_ONE))) void k_transport
     fr[j].w = f[3];
   }
   __syncthreads();
-  slab_forward_store<T, N, N>(lds, spec + c * nspec + soff, twx, twy, rtw);
-  __syncthreads();
+  if (c < 2) {
+    // G_c = f_c + D_c tau_c with D_c the central difference along x (c = 0)
+    // or y (c = 1) of the periodic slab: exactly the i s_c of the spectral
+    // derivative, so only G_c needs a forward transform
+    const T hs = T(0.5 * (double)N);  // 1 / (2 h) with h = 1 / N
+#pragma unroll
+    for (int j = 0; j < S::QPT; ++j) {
+      const int q = threadIdx.x + j * S::NT;
+      if (!S::FULL && q >= S::NQ) continue;
+      const int v = 4 * q;
+      const int y = v / N, x = v - y * N;
+      T d[4];
+      if (c == 0) {
+        const T* row = ldsr + y * 2 * S::P2;
+        const T left = row[x == 0 ? N - 1 : x - 1], right = row[x + 4 == N ? 0 : x + 4];
+        const V mid = lds_ld4<V>(row + x);
+        d[0] = mid.y - left;
+        d[1] = mid.z - mid.x;
+        d[2] = mid.w - mid.y;
+        d[3] = right - mid.z;
+      } else {
+        const V up = lds_ld4<V>(ldsr + (y + 1 == N ? 0 : y + 1) * 2 * S::P2 + x);
+        const V dn = lds_ld4<V>(ldsr + (y == 0 ? N - 1 : y - 1) * 2 * S::P2 + x);
+        d[0] = up.x - dn.x;
+        d[1] = up.y - dn.y;
+        d[2] = up.z - dn.z;
+        d[3] = up.w - dn.w;
+      }
+      fr[j].x += hs * d[0];
+      fr[j].y += hs * d[1];
+      fr[j].z += hs * d[2];
+      fr[j].w += hs * d[3];
+    }
+    __syncthreads();  // every tau neighbour has been read
+  } else {
+    slab_forward_store<T, N, N>(lds, spec + 3 * nspec + soff, twx, twy, rtw);  // tau_z
+    __syncthreads();
+  }
 #pragma unroll
   for (int j = 0; j < S::QPT; ++j) {
     const int q = threadIdx.x + j * S::NT;
@@ -356,21 +415,26 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, N, N>::WPE_ONE))) void k_transport
     lds_st4(ldsr + y * 2 * S::P2 + x, fr[j]);
   }
   __syncthreads();
-  slab_forward_store<T, N, N>(lds, spec + (D + c) * nspec + soff, twx, twy, rtw);
+  // G_x, G_y or f_z into the field this workgroup read
+  slab_forward_store<T, N, N>(lds, spec + c * nspec + soff, twx, twy, rtw);
 }
 
 // ------------------------------------------------------------------ launchers
-int transport_green_blocks(const Geom& g, int prec_bytes) {
+template <typename T, int LL>
+static int tg_blocks(const Geom& g, bool slab) {
+  int tx;
+  if (g.dim == 3)
+    tx = slab ? TGCfg<T, LL, tg_fields<3, true>()>::TX : TGCfg<T, LL, tg_fields<3, false>()>::TX;
+  else
+    tx = TGCfg<T, LL, tg_fields<2, false>()>::TX;
+  return (int)((g.plane + tx - 1) / tx);
+}
+
+int transport_green_blocks(const Geom& g, int prec_bytes, bool slab) {
   switch (g.last_n) {
-#define CASE(LL)                                                                              \
-  case LL:                                                                                    \
-    if (g.dim == 3)                                                                           \
-      return (int)((g.plane + (prec_bytes == 8 ? TGCfg<double, LL, 4>::TX                     \
-                                               : TGCfg<float, LL, 4>::TX) - 1) /              \
-                   (prec_bytes == 8 ? TGCfg<double, LL, 4>::TX : TGCfg<float, LL, 4>::TX));   \
-    return (int)((g.plane + (prec_bytes == 8 ? TGCfg<double, LL, 3>::TX                       \
-                                             : TGCfg<float, LL, 3>::TX) - 1) /                \
-                 (prec_bytes == 8 ? TGCfg<double, LL, 3>::TX : TGCfg<float, LL, 3>::TX));
+#define CASE(LL) \
+  case LL:       \
+    return prec_bytes == 8 ? tg_blocks<double, LL>(g, slab) : tg_blocks<float, LL>(g, slab);
     ACM_COL_LENGTHS(CASE)
 #undef CASE
     default:
@@ -381,7 +445,7 @@ int transport_green_blocks(const Geom& g, int prec_bytes) {
 template <typename T>
 hipError_t launch_transport_green(const Geom& g, const DevTables<T>& tb, int mode, void* spec,
                                   void* chat, const void* chat_m, double* partials,
-                                  TransportCtl* ctl, int nfpart, int par, int judge,
+                                  TransportCtl* ctl, int slab, int par, int judge,
                                   hipStream_t s) {
   const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
   const T* rt = tb.rtab;
@@ -390,12 +454,12 @@ hipError_t launch_transport_green(const Geom& g, const DevTables<T>& tb, int mod
   auto* sp = reinterpret_cast<cplx<T>*>(spec);
   auto* cp = reinterpret_cast<cplx<T>*>(chat);
   auto* cm = reinterpret_cast<const cplx<T>*>(chat_m);
-#define LAUNCH_TG(LL, DD, MM)                                                                \
+#define LAUNCH_TG(LL, DD, MM, SLB)                                                           \
   {                                                                                          \
-    using C = TGCfg<T, LL, DD + 1>;                                                          \
+    using C = TGCfg<T, LL, tg_fields<DD, SLB>()>;                                            \
     const int nb = (int)((g.plane + C::TX - 1) / C::TX);                                     \
-    ACM_LAUNCH((k_transport_green<T, LL, DD, MM>), dim3(nb), dim3(C::NT),            \
-                       C::LDS_BYTES, s, sp, cp, cm, partials, ctl, gg, nfpart, par, judge,     \
+    ACM_LAUNCH((k_transport_green<T, LL, DD, MM, SLB>), dim3(nb), dim3(C::NT),               \
+                       C::LDS_BYTES, s, sp, cp, cm, partials, ctl, gg, par, judge,             \
                        tw,                                                                   \
                        rt + tb.off.sx,                                                       \
                        rt + tb.off.lx, rt + tb.off.sy, rt + tb.off.ly, rt + tb.off.sz,       \
@@ -405,12 +469,13 @@ hipError_t launch_transport_green(const Geom& g, const DevTables<T>& tb, int mod
 #define CASE(LL)                            \
   case LL:                                  \
     if (g.dim == 3) {                       \
-      if (mode == 0) LAUNCH_TG(LL, 3, 0)    \
-      else LAUNCH_TG(LL, 3, 1)              \
-    } else {                                \
-      if (mode == 0) LAUNCH_TG(LL, 2, 0)    \
-      else LAUNCH_TG(LL, 2, 1)              \
-    }                                       \
+      if (mode == 0 && slab) LAUNCH_TG(LL, 3, 0, true)      \
+      else if (mode == 0) LAUNCH_TG(LL, 3, 0, false)        \
+      else LAUNCH_TG(LL, 3, 1, false)                       \
+    } else {                                                \
+      if (mode == 0) LAUNCH_TG(LL, 2, 0, false)             \
+      else LAUNCH_TG(LL, 2, 1, false)                       \
+    }                                                       \
     return hipGetLastError();
     ACM_COL_LENGTHS(CASE)
 #undef CASE

@@ -873,11 +873,11 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
   // passes; f arrives as d partial spectra)
   const bool tslab = d == 3 && slab_supported<T>(g) && ((uintptr_t)u % 16 == 0) &&
                      ((uintptr_t)H % 4 == 0);
-  const int nfpart = tslab ? d : 1;
   const size_t cb = sizeof(T) * 2;
-  const size_t spec_b = cb * (size_t)g.nspec * (d + nfpart);
+  const size_t spec_b = cb * (size_t)g.nspec * (d + 1);
   const size_t one_b = cb * (size_t)g.nspec;
-  const int ngreen = transport_green_blocks(g, pl->prec);
+  const int ngreen = std::max(transport_green_blocks(g, pl->prec, false),
+                              transport_green_blocks(g, pl->prec, tslab));
   const size_t part_b = sizeof(double) * 2 * (size_t)ngreen;
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   DevBuf ws;
@@ -921,7 +921,7 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
     if (e == hipSuccess) e = launch_cols<T>(g, tb, 1, -1, 1, chat, s);
     if (e == hipSuccess && d == 3) e = launch_cols<T>(g, tb, 2, -1, 1, chat, s);
     if (e == hipSuccess)
-      e = launch_transport_green<T>(g, tb, 1, spec, chat, chat_m, part, dctl, 1, 0, 1, s);
+      e = launch_transport_green<T>(g, tb, 1, spec, chat, chat_m, part, dctl, 0, 0, 1, s);
     if (e != hipSuccess) return fail(ACM_E_HIP, std::string("set-up: ") + hipGetErrorString(e));
   }
 
@@ -940,12 +940,12 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
     tpar ^= 1;
     if (tslab) {
       prof.begin(KK_T_LOCAL, &ev0);
-      e = launch_transport_slab<T>(g, tb, spec, u, H, dctl, part, ngreen, par, s);
+      e = launch_transport_slab<T>(g, tb, spec, u, H, dctl, part,
+                                   transport_green_blocks(g, pl->prec, true), par, s);
       if (e != hipSuccess) return e;
       prof.end(KK_T_LOCAL, ev0);
       prof.begin(KK_T_GREEN, &ev0);
-      e = launch_transport_green<T>(g, tb, 0, spec, chat, chat_m, part, dctl, nfpart, par ^ 1, 0,
-                                    s);
+      e = launch_transport_green<T>(g, tb, 0, spec, chat, chat_m, part, dctl, 1, par ^ 1, 0, s);
       if (e != hipSuccess) return e;
       prof.end(KK_T_GREEN, ev0);
       return hipSuccess;
@@ -967,7 +967,7 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
       prof.end(KK_YFWD, ev0);
     }
     prof.begin(KK_T_GREEN, &ev0);
-    e = launch_transport_green<T>(g, tb, 0, spec, chat, chat_m, part, dctl, 1, par, 1, s);
+    e = launch_transport_green<T>(g, tb, 0, spec, chat, chat_m, part, dctl, 0, par, 1, s);
     if (e != hipSuccess) return e;
     prof.end(KK_T_GREEN, ev0);
     return hipSuccess;
