@@ -192,6 +192,11 @@ def batched_section(ncell, log):
                 iterations_equal=it_plain == it_b, speedup=(t1 - t0) / (t2 - t1))
 
 
+def gbps(nbytes: float, ms: float):
+    """GB/s of a kernel moving nbytes in ms, or None without a byte model."""
+    return round(nbytes / (ms * 1e-3) / 1e9, 1) if math.isfinite(nbytes) else None
+
+
 def kernel_bytes(kind: str, n: int, d: int, nsolid: int, real_bytes: int = 4) -> float:
     """Algorithmic HBM bytes one launch of `kind` must move (FP32 fields).
     Half spectra hold nspec = n*n*(n/2+1) complex values per field."""
@@ -202,12 +207,14 @@ def kernel_bytes(kind: str, n: int, d: int, nsolid: int, real_bytes: int = 4) ->
         return nspec * cb * (2 * d + 4)
     if kind in ("y_inv", "y_fwd"):
         return nspec * cb * 2 * d
-    if kind == "local":   # spectra in; u in+out; a in+out on solid voxels; H
-        return d * nspec * cb + 2 * d * ntot * real_bytes + 2 * d * nsolid * real_bytes + ntot
-    if kind == "rhs":     # u in; a in on solid voxels; H; spectra out
+    if kind in ("local", "local+rhs"):
+        # spectra in; u in+out; a in+out on solid voxels; H; spectra of r out
+        return (2 * d * nspec * cb + 2 * d * ntot * real_bytes + 2 * d * nsolid * real_bytes
+                + ntot)
+    if kind == "rhs_full":  # the rhs pass when Step 4 changed b: u, a (solid), H in, spectra out
         return d * ntot * real_bytes + d * nsolid * real_bytes + ntot + d * nspec * cb
-    if kind == "local+rhs":  # one launch: the local pass plus the rhs pass's spectra out
-        return kernel_bytes("local", n, d, nsolid, real_bytes) + d * nspec * cb
+    # "rhs": Step 4 from the FP64 partial sums (a few KB), the full pass only
+    # when b changed, so no byte model
     return float("nan")
 
 
@@ -362,7 +369,7 @@ def main():
     achieved = algo / avg_s / 1e9
     per_kernel = {k: dict(avg_us=round(avg_ms[k] * 1e3, 2), avg_us_events=round(raw[k] * 1e3, 2),
                           calls=kc[k],
-                          GBps=round(kernel_bytes(k, n, d, nsolid) / (avg_ms[k] * 1e-3) / 1e9, 1))
+                          GBps=gbps(kernel_bytes(k, n, d, nsolid), avg_ms[k]))
                   for k in avg_ms}
     iter_us_profiled = 1e3 * sum(km.values()) / max(1, rp["stats"]["iters"])
 

@@ -221,6 +221,8 @@ hipError_t launch_cols_batched(const Geom& g, const DevTables<T>& tb, int axis, 
 // of 0 and 1 (kGreenVariants in all); *nblocks receives
 // the number of workgroups per cell (= partial-sum records written).
 constexpr int kGreenVariants = 7;
+// rounds in which the autotuner times every green variant (best round kept)
+constexpr int kTuneRounds = 3;
 
 // `par`: parity of the iteration (the state slot its passes read).  The row
 // local pass runs Step 4 in its last workgroup and writes slot par ^ 1; the row

@@ -3,10 +3,16 @@
 // workgroup owns one (field, z) slab:
 //   slab_local: load the half-spectrum slab, inverse y transform (columns),
 //               inverse x transform (rows) -> u^{n+1}, Steps 2-3 pointwise
-//               (Section 3.1), FP64 partial sums; the last workgroup runs
-//               Step 4 and the penalty update (shared with the row path).
-//   slab_rhs:   r = b^{n+1} ut^{n+1} - a^{n+1}, forward x transform (rows),
-//               forward y transform (columns), store the slab.
+//               (Section 3.1), FP64 partial sums; then r = b ut^{n+1} -
+//               a^{n+1} with the b of this iteration, forward x and y
+//               transforms, store the slab in place of the one it loaded.
+//   slab_rhs:   every workgroup forms Step 4 and the penalty update from the
+//               partial sums.  Only when that changes b (a few per cent of
+//               the iterations) is r formed again with the new b from the
+//               stored u, a and H and transformed; otherwise the pass ends.
+// r depends on the penalties only through b and the c of the iteration just
+// done (its solid coefficient is b c_prev), so the speculative r is exactly
+// the one the rhs pass would form whenever b is kept.
 // This replaces the separate x-row and y-column passes of the general path
 // and saves one HBM round trip of the spectra per direction of transform.
 #include "slab_common.hpp"
@@ -49,9 +55,15 @@ __attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
   const uint32_t gate0 = FUSED ? ctl->gate : 0u;  // read before this workgroup arrives
   const StokesState& cur = ctl->st[par];
   const double al = cur.psi[0], bb = cur.psi[2];
-  const T cc = (T)(bb / (bb + al));
+  const double ccd = bb / (bb + al);
+  const T cc = (T)ccd;
   const T cp = (T)cur.c_prev;
   const T ka = (T)(bb * al / (bb + al));
+  // r of the next Step 1 if Step 4 keeps b (it changes b in a few per cent of
+  // the iterations): the coefficients the rhs pass would use then, in the
+  // same arithmetic (c_prev of the next state is ccd)
+  const T rb = (T)bb;
+  const T rbc = (T)(bb * ccd);
   const int z = blockIdx.x, field = blockIdx.y;
 
   const int64_t off = field * ntot + (int64_t)z * S::NV;
@@ -150,6 +162,13 @@ __attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
     if constexpr (FUSED) {
       ao[j] = aoj;
       hw[j] = hwj;
+    } else {
+      V r;
+      r.x = ((hwj & 0xffu) ? rbc : rb) * un.x - aoj.x;
+      r.y = ((hwj & 0xff00u) ? rbc : rb) * un.y - aoj.y;
+      r.z = ((hwj & 0xff0000u) ? rbc : rb) * un.z - aoj.z;
+      r.w = ((hwj & 0xff000000u) ? rbc : rb) * un.w - aoj.w;
+      lds_st4(ldsr + y * 2 * S::P2 + x, r);
     }
   }
   block_sum<4>(acc, red);
@@ -164,6 +183,10 @@ __attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
       lpart[bid * 4 + 2] = acc[2];
       lpart[bid * 4 + 3] = acc[3];
     }
+    // the speculative r of this slab, forward transformed in place of the
+    // spectrum it was loaded from (only this workgroup touches that slab)
+    __syncthreads();
+    slab_forward_store<T, NX, NY>(lds, slab, twx, twy, rtw);
     return;
   }
   if (threadIdx.x == 0) {
@@ -252,7 +275,7 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_rhs(
   extern __shared__ __align__(32) char smem_raw[];
   __shared__ double red7[7 * 16];
   __shared__ double s_b, s_cp;
-  __shared__ int s_stop;
+  __shared__ int s_stop, s_kept;
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   T* ldsr = reinterpret_cast<T*>(smem_raw);
   if (stokes_done(ctl)) return;
@@ -278,14 +301,18 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_rhs(
       s_b = nx.psi[2];
       s_cp = nx.c_prev;
       s_stop = nx.done;
+      s_kept = nx.psi[2] == cur.psi[2];
     }
   } else if (threadIdx.x == 0) {
     s_b = ctl->st[par].psi[2];
     s_cp = ctl->st[par].c_prev;
     s_stop = 0;
+    s_kept = 0;
   }
   __syncthreads();
-  if (s_stop) return;
+  // after a slab local pass (step4) the spectra already hold r unless Step 4
+  // changed b
+  if (s_stop || s_kept) return;
   const T bb = (T)s_b;
   const T bcp = (T)(s_b * s_cp);
   // a vanishes in the pore, so r = (H ? b c : b) u - a needs no branch on H

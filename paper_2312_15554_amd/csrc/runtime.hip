@@ -599,7 +599,10 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
   // of a plan run eagerly, one kernel variant at a time (tile widths of the
   // LDS-staged kernel, then of the register-resident one), with HIP events
   // around whole iterations; the fastest variant is kept for this plan.  The
-  // variants apply the same arithmetic in the same order (up to the
+  // variants are timed in interleaved rounds and each keeps its best round:
+  // an iteration whose Step 4 changes b runs the full rhs pass, and a single
+  // round would charge such an iteration to whichever variant it fell on.
+  // The variants apply the same arithmetic in the same order (up to the
   // compiler's contraction choices), so the choice changes iterates only at
   // the rounding level.
   {
@@ -608,14 +611,16 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
       const Geom& g = G.pl->g;
       if (o.green_variant > 0) {
         G.green_var = o.green_variant - 1;
-      } else if (G.pl->green_var < 0 && g.ntot >= (int64_t)64 * 64 * 64 && o.max_iter >= 64) {
-        float best = 1e30f;
-        int bestv = 0;
+      } else if (G.pl->green_var < 0 && g.ntot >= (int64_t)64 * 64 * 64 &&
+                 o.max_iter >= 2 * kTuneRounds * kGreenVariants * 5) {
+        float vbest[kGreenVariants];
+        for (int v = 0; v < kGreenVariants; ++v) vbest[v] = 1e30f;
         hipEvent_t e0, e1;
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
         Profiler off;
-        for (int v = 0; v < kGreenVariants; ++v) {
+        for (int tv = 0; tv < kTuneRounds * kGreenVariants; ++tv) {
+          const int v = tv % kGreenVariants;
           G.green_var = v;
           G.ngreen = stokes_green_blocks(g, G.pl->prec, v);
           // one warm-up iteration, then 4 timed iterations back to back
@@ -631,13 +636,13 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
             (void)hipEventDestroy(e1);
             return fail(ACM_E_HIP, std::string("autotune: ") + hipGetErrorString(e));
           }
-          if (ms < best) {
-            best = ms;
-            bestv = v;
-          }
+          vbest[v] = std::min(vbest[v], ms);
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
+        int bestv = 0;
+        for (int v = 1; v < kGreenVariants; ++v)
+          if (vbest[v] < vbest[bestv]) bestv = v;
         G.pl->green_var = bestv;
         G.green_var = bestv;
       } else if (G.pl->green_var >= 0) {

@@ -68,7 +68,7 @@ struct SlabCfg {
   static constexpr int UNR = QPT;
   // loads in flight per thread when the rhs pass sums the partials (its state
   // loads are already in registers then)
-  static constexpr int SUM_U = 4;
+  static constexpr int SUM_U = 2;
   // Waves per SIMD that let as many workgroups reside per CU as LDS allows
   // (CDNA: 4 SIMDs and 160 KB of LDS per CU; at most 4 workgroups counted):
   // the minimum occupancy requested from the register allocator.

@@ -11,39 +11,32 @@ namespace acm {
 // |H (ut - ut_prev)|^2, |a|^2, |u - u_prev|^2) in a fixed order, so every
 // workgroup that forms them gets the same bits.  The whole workgroup calls
 // it; the totals are valid in thread 0.  `red` holds 7 * 16 doubles.
-// U: loads per thread issued together before any is added.
-template <int U = 4>
+// U: tuples of each kind per thread whose loads are issued together, green
+// and local ones in the same round, before any is added.
+template <int U = 2>
 __device__ __forceinline__ void stokes_sum_partials(const double* __restrict__ gpart, int ngreen,
                                                     const double* __restrict__ lpart, int nlocal,
                                                     double (&acc)[7], double* red) {
   for (int k = 0; k < 7; ++k) acc[k] = 0.0;
-  for (int j0 = threadIdx.x; j0 < ngreen; j0 += U * blockDim.x) {
-    double v[U][3];
+  const int nmax = ngreen > nlocal ? ngreen : nlocal;
+  for (int j0 = threadIdx.x; j0 < nmax; j0 += U * blockDim.x) {
+    double vg[U][3], vl[U][4];
 #pragma unroll
     for (int k = 0; k < U; ++k) {
       const int j = j0 + k * blockDim.x;
-      const bool in = j < ngreen;
+      const bool ig = j < ngreen, il = j < nlocal;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) v[k][c] = in ? gpart[j * 3 + c] : 0.0;
+      for (int c = 0; c < 3; ++c) vg[k][c] = ig ? gpart[j * 3 + c] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) vl[k][c] = il ? lpart[j * 4 + c] : 0.0;
     }
-#pragma unroll
-    for (int k = 0; k < U; ++k)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) acc[c] += v[k][c];
-  }
-  for (int j0 = threadIdx.x; j0 < nlocal; j0 += U * blockDim.x) {
-    double v[U][4];
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-      const int j = j0 + k * blockDim.x;
-      const bool in = j < nlocal;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) v[k][c] = in ? lpart[j * 4 + c] : 0.0;
+      for (int c = 0; c < 3; ++c) acc[c] += vg[k][c];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[3 + c] += vl[k][c];
     }
-#pragma unroll
-    for (int k = 0; k < U; ++k)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[3 + c] += v[k][c];
   }
   block_sum<7>(acc, red);
 }
