@@ -102,11 +102,11 @@ __attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
     }
   }
   {
-    const int grp = threadIdx.x / S::TPPX, t = threadIdx.x % S::TPPX;
+    const int grp = threadIdx.x % S::GX, t = threadIdx.x / S::GX;  // row index fastest
 #pragma unroll 1
     for (int r0 = 0; r0 < NY; r0 += S::GX) {
       const int row = r0 + grp;
-      const bool act = grp < S::GX && row < NY;
+      const bool act = t < S::TPPX && row < NY;
       rows_c2r_lds<T, S::M, 1, S::P2>(lds, 0, act ? row : 0, t, act, twx, rtw);
     }
   }

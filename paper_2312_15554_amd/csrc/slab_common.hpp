@@ -82,11 +82,15 @@ struct SlabCfg {
 template <typename T, int NX, int NY, int SIGN>
 __device__ __forceinline__ void slab_cols(cplx<T>* lds, const cplx<T>* __restrict__ tw) {
   using S = SlabCfg<T, NX, NY>;
-  const int grp = threadIdx.x / S::TPPY, t = threadIdx.x % S::TPPY;
+  // column index fastest across the lanes: every lane of a wave is at the
+  // same point of its pencil, so each LDS access of every stage touches
+  // consecutive complex values (no bank conflicts) and the twiddles are
+  // uniform across the wave
+  const int grp = threadIdx.x % S::GY, t = threadIdx.x / S::GY;
 #pragma unroll 1
   for (int c0 = 0; c0 < S::XH; c0 += S::GY) {
     const int col = c0 + grp;
-    const bool act = grp < S::GY && col < S::XH;
+    const bool act = t < S::TPPY && col < S::XH;
     PencilFFT<T, NY, 1, SIGN>::run_lds(t, act, lds + (act ? col : 0), 0, S::P2, tw);
     __syncthreads();
   }
@@ -101,11 +105,13 @@ __device__ __forceinline__ void slab_forward_store(cplx<T>* lds, cplx<T>* __rest
                                                    const cplx<T>* __restrict__ rtw) {
   using S = SlabCfg<T, NX, NY>;
   {
-    const int grp = threadIdx.x / S::TPPX, t = threadIdx.x % S::TPPX;
+    // row index fastest across the lanes (rows are an odd number of banks
+    // apart): conflict-free at every stage
+    const int grp = threadIdx.x % S::GX, t = threadIdx.x / S::GX;
 #pragma unroll 1
     for (int r0 = 0; r0 < NY; r0 += S::GX) {
       const int row = r0 + grp;
-      const bool act = grp < S::GX && row < NY;
+      const bool act = t < S::TPPX && row < NY;
       rows_r2c_lds<T, S::M, 1, S::P2>(lds, 0, act ? row : 0, t, act, twx, rtw);
     }
   }
@@ -132,11 +138,11 @@ __device__ __forceinline__ void slab_load_inverse(cplx<T>* lds, const cplx<T>* _
   }
   __syncthreads();
   slab_cols<T, NX, NY, +1>(lds, twy);
-  const int grp = threadIdx.x / S::TPPX, t = threadIdx.x % S::TPPX;
+  const int grp = threadIdx.x % S::GX, t = threadIdx.x / S::GX;  // row index fastest
 #pragma unroll 1
   for (int r0 = 0; r0 < NY; r0 += S::GX) {
     const int row = r0 + grp;
-    const bool act = grp < S::GX && row < NY;
+    const bool act = t < S::TPPX && row < NY;
     rows_c2r_lds<T, S::M, 1, S::P2>(lds, 0, act ? row : 0, t, act, twx, rtw);
   }
 }
