@@ -356,18 +356,21 @@ def main():
     km, kc = dict(rp["stats"]["kernel_ms"]), dict(rp["stats"]["kernel_calls"])
     if kc["local"] > 0 and kc["rhs"] == 0:  # local and rhs passes in one launch
         km["local+rhs"], kc["local+rhs"] = km.pop("local"), kc.pop("local")
-    # Each kernel's events are attached to its own dispatch but still include a
-    # per-launch overhead; the library times an empty kernel the same way
-    # ("other") and that mean is subtracted from every kernel's mean.
+    # Each kernel's events are attached to its own dispatch.  They include a
+    # fixed cost of a few microseconds per dispatch, which an empty kernel timed
+    # the same way ("other") shows; the graph replays of the solve pay it too
+    # (their kernel trace durations equal these event times), so the roofline
+    # uses the event times as they are and reports the empty kernel beside.
     ovh_ms = km.pop("other") / kc.pop("other") if kc.get("other") else 0.0
     raw = {k: km[k] / kc[k] for k in km if kc[k] > 0}
-    avg_ms = {k: max(raw[k] - ovh_ms, 1e-6) for k in raw}
+    avg_ms = dict(raw)
     share = {k: avg_ms[k] * kc[k] for k in avg_ms}
     dom = max(share, key=share.get)
     avg_s = avg_ms[dom] * 1e-3
     algo = kernel_bytes(dom, n, d, nsolid)
     achieved = algo / avg_s / 1e9
-    per_kernel = {k: dict(avg_us=round(avg_ms[k] * 1e3, 2), avg_us_events=round(raw[k] * 1e3, 2),
+    per_kernel = {k: dict(avg_us=round(avg_ms[k] * 1e3, 2),
+                          avg_us_less_empty_kernel=round(max(raw[k] - ovh_ms, 0.0) * 1e3, 2),
                           calls=kc[k],
                           GBps=gbps(kernel_bytes(k, n, d, nsolid), avg_ms[k]))
                   for k in avg_ms}
@@ -441,7 +444,7 @@ def main():
         "K": [[float(v) for v in row] for row in K],
         "iter_us_profiled": round(iter_us_profiled, 2),
         "kernels": per_kernel,
-        "event_launch_overhead_us": round(ovh_ms * 1e3, 2),
+        "empty_kernel_event_us": round(ovh_ms * 1e3, 2),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": counter_traffic(dom)},

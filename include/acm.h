@@ -80,8 +80,18 @@ typedef struct {
                            3 fused xy-slab passes with the local and rhs passes
                            in one launch joined by a device-wide gate (needs, in
                            addition, a single cell whose nz * 3 workgroups are
-                           all resident at once; otherwise ACM_E_INVALID).
-                           Automatic picks 2 where it applies, else 1. */
+                           all resident at once; otherwise ACM_E_INVALID),
+                           4 fused xy-slab passes where, after the first 64
+                           iterations, a one-workgroup kernel forms Step 4 in
+                           place of the rhs pass (the local pass has formed r
+                           with the b of its iteration); a Step 4 that changes
+                           b (rare after the first iterations) holds the
+                           iterations until the host has formed r again.  Same
+                           iterates as 2, bit for bit (needs a single cell;
+                           otherwise ACM_E_INVALID).
+                           Automatic picks 4 for a single cell where the
+                           slab passes apply, 2 for a batch of such cells,
+                           else 1. */
   int32_t green_variant; /* Stokes: kernel of the last-axis (green) pass. 0 automatic:
                            the first solve of a grid times every variant over a few
                            iterations and keeps the fastest for that grid; 1-3 force
@@ -104,7 +114,8 @@ enum {
   ACM_K_LOCAL = 1,   /* Stokes: x inverse transform + Steps 2-3 (+ Step 4 on the row
                         path; local and rhs together with pass_mode 3) */
   ACM_K_RHS = 2,     /* Stokes: (Step 4 on the slab path +) right-hand side of Step 1
-                        + x forward transform */
+                        + x forward transform; with pass_mode 4 also the Step 4
+                        kernel */
   ACM_K_YINV = 3,    /* y inverse transform (3D) */
   ACM_K_YFWD = 4,    /* y forward transform (3D) */
   ACM_K_T_GREEN = 5, /* transport: last-axis FFT pair + LS update */

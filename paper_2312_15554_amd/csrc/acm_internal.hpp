@@ -58,7 +58,9 @@ struct StokesCtl {
   int32_t adaptive;
   int32_t hist_cap;   // capacity of the residual history ring (entries)
   int32_t fault;      // non-zero: a single-launch slab pass gave up at its gate
-  int32_t pad_;
+  // non-zero (1 + state slot): the Step 4 kernel of pass mode 4 found b
+  // changed; every pass after it skips until the host has formed r again
+  int32_t hold;
   StokesState st[2];
   // Words that many workgroups hit at once sit on cache lines of their own,
   // away from the parameters every workgroup reads when it starts.
@@ -68,6 +70,10 @@ struct StokesCtl {
 
 __host__ __device__ inline bool stokes_done(const StokesCtl* c) {
   return (c->st[0].done | c->st[1].done) != 0;
+}
+// a pass of the solve has nothing to do: it stopped, or it is held
+__host__ __device__ inline bool stokes_skip(const StokesCtl* c) {
+  return (c->st[0].done | c->st[1].done | c->hold) != 0;
 }
 
 // One history record per iteration: rp[3], rd[3], tp[3], td[3], psi[3].
@@ -157,7 +163,7 @@ struct StokesCellArgs {
   void* a;             // real [d][ntot]
   const uint8_t* H;    // uint8 [ntot]
   double* part;        // green partials [3*ngreen]
-  double* lpart;       // local partials [4*nlocal]
+  double* lpart;       // local partials: [4*nlocal] (rows, single launch) or [7*nlocal] (slabs)
   StokesCtl* ctl;
   double* hist;        // may be null
 };
@@ -223,6 +229,10 @@ hipError_t launch_cols_batched(const Geom& g, const DevTables<T>& tb, int axis, 
 constexpr int kGreenVariants = 7;
 // rounds in which the autotuner times every green variant (best round kept)
 constexpr int kTuneRounds = 3;
+// iterations of a pass-mode-4 solve that form Step 4 in the rhs pass before
+// the Step 4 kernel takes it over (Step 4 changes b in most of the first few
+// dozen)
+constexpr int64_t kRhsStep4Iters = 64;
 
 // `par`: parity of the iteration (the state slot its passes read).  The row
 // local pass runs Step 4 in its last workgroup and writes slot par ^ 1; the row
@@ -295,11 +305,19 @@ int slab_local_blocks(const Geom& g);
 // With step4 = 0 the rhs pass uses slot par as it is (warm-start set-up).
 template <typename T>
 hipError_t launch_slab_local(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
-                             const StokesCellArgs* many, int ncells, int par, hipStream_t s);
+                             const StokesCellArgs* many, int ncells, int par, int green_blocks,
+                             hipStream_t s);
 template <typename T>
 hipError_t launch_slab_rhs(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
                            const StokesCellArgs* many, int ncells, int par, int step4,
                            int green_blocks, hipStream_t s);
+// Step 4 of one cell from the records of the slab local pass, in one
+// workgroup: slot par ^ 1 and the history record are written, and the hold
+// word is set (1 + (par ^ 1)) when Step 4 changed b.  Pass mode 4 runs it in
+// place of the rhs pass, whose r the slab local pass has formed with the old b.
+template <typename T>
+hipError_t launch_slab_step4(const Geom& g, const StokesCellArgs& one, int par, int nrec,
+                             hipStream_t s);
 // Local and rhs slab passes of one cell in a single launch: every workgroup
 // runs the local pass, waits at a device-wide gate that the last one opens
 // after Step 4, then runs the rhs pass on the slab still held in LDS.  Valid

@@ -51,8 +51,14 @@ __attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
   __shared__ int s_last, s_go;
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   T* ldsr = reinterpret_cast<T*>(smem_raw);
-  if (stokes_done(ctl)) return;
+  if (stokes_skip(ctl)) return;
   const uint32_t gate0 = FUSED ? ctl->gate : 0u;  // read before this workgroup arrives
+  // Two-launch form: this workgroup's share of the green partials of the
+  // iteration (records [g0, g1)) goes into its own record, so that Step 4
+  // sums one record per local workgroup.  kShare threads sum it (fixed order)
+  // into LDS while the slab loads are in flight.
+  constexpr int kShare = 8;
+  __shared__ double gsh[3 * kShare];
   const StokesState& cur = ctl->st[par];
   const double al = cur.psi[0], bb = cur.psi[2];
   const double ccd = bb / (bb + al);
@@ -89,6 +95,21 @@ __attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
   for (int v = threadIdx.x; v < NY * S::XH; v += S::NT) {
     const int y = v / S::XH, k = v - y * S::XH;
     lds[y * S::P2 + k] = slab[v];
+  }
+  if constexpr (!FUSED) {
+    if (threadIdx.x < kShare) {
+      const int nb = gridDim.x * gridDim.y, b = blockIdx.y * gridDim.x + blockIdx.x;
+      const int g0 = (int)((int64_t)ngreen * b / nb), g1 = (int)((int64_t)ngreen * (b + 1) / nb);
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+      for (int j = g0 + (int)threadIdx.x; j < g1; j += kShare) {
+        s0 += gpart[j * 3 + 0];
+        s1 += gpart[j * 3 + 1];
+        s2 += gpart[j * 3 + 2];
+      }
+      gsh[threadIdx.x * 3 + 0] = s0;
+      gsh[threadIdx.x * 3 + 1] = s1;
+      gsh[threadIdx.x * 3 + 2] = s2;
+    }
   }
   __syncthreads();
   slab_cols<T, NX, NY, +1>(lds, twy);
@@ -171,17 +192,19 @@ __attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
       lds_st4(ldsr + y * 2 * S::P2 + x, r);
     }
   }
-  block_sum<4>(acc, red);
   const int nblk = gridDim.x * gridDim.y;
   const int bid = blockIdx.y * gridDim.x + blockIdx.x;
   if constexpr (!FUSED) {
-    // Step 4 is formed by the rhs pass from these partials after the launch
-    // boundary: no cross-workgroup traffic here
+    // Step 4 is formed after the launch boundary (by the rhs pass or the next
+    // green pass) from one record per workgroup: the green share, then these
+    // partials.  No cross-workgroup traffic here.
+    block_sum<4>(acc, red);
     if (threadIdx.x == 0) {
-      lpart[bid * 4 + 0] = acc[0];
-      lpart[bid * 4 + 1] = acc[1];
-      lpart[bid * 4 + 2] = acc[2];
-      lpart[bid * 4 + 3] = acc[3];
+      double gs[3] = {0.0, 0.0, 0.0};
+      for (int t = 0; t < kShare; ++t)
+        for (int c = 0; c < 3; ++c) gs[c] += gsh[t * 3 + c];
+      for (int c = 0; c < 3; ++c) lpart[bid * 7 + c] = gs[c];
+      for (int c = 0; c < 4; ++c) lpart[bid * 7 + 3 + c] = acc[c];
     }
     // the speculative r of this slab, forward transformed in place of the
     // spectrum it was loaded from (only this workgroup touches that slab)
@@ -189,6 +212,7 @@ __attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
     slab_forward_store<T, NX, NY>(lds, slab, twx, twy, rtw);
     return;
   }
+  block_sum<4>(acc, red);
   if (threadIdx.x == 0) {
     lpart[bid * 4 + 0] = acc[0];
     lpart[bid * 4 + 1] = acc[1];
@@ -278,7 +302,7 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_rhs(
   __shared__ int s_stop, s_kept;
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   T* ldsr = reinterpret_cast<T*>(smem_raw);
-  if (stokes_done(ctl)) return;
+  if (stokes_skip(ctl)) return;
   const int z = blockIdx.x, field = blockIdx.y;
   const int64_t off = field * ntot + (int64_t)z * S::NV;
   const V* uq = reinterpret_cast<const V*>(u + off);
@@ -289,7 +313,7 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_rhs(
   // state in the other slot.  Without step4 the current slot is used as is.
   if (step4) {
     double tot[7];
-    stokes_sum_partials<S::SUM_U>(ca.part, ngreen, ca.lpart, gridDim.x * gridDim.y, tot, red7);
+    stokes_sum_records<S::SUM_U>(ca.lpart, gridDim.x * gridDim.y, tot, red7);
     if (threadIdx.x == 0) {
       const StokesState cur = ctl->st[par];
       StokesState nx;
@@ -336,7 +360,66 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_rhs(
   slab_forward_store<T, NX, NY>(lds, spec + field * nspec + (int64_t)z * NY * S::XH, twx, twy, rtw);
 }
 
+// Step 4 in one workgroup (pass mode 4) of the slab passes' block size: the
+// same sums as the rhs pass forms (same records, same order), so the same bits.
+__global__ __launch_bounds__(1024) void k_slab_step4(StokesCellArgs one, int par, int nrec,
+                                                     int64_t ntot) {
+  __shared__ double red7[7 * 16];
+  StokesCtl* ctl = one.ctl;
+  // The kernel is a chain of latencies: everything it reads (the stop words,
+  // this thread's records, the current state) is loaded before any of it is
+  // used.  The sum is the one stokes_sum_records<2> forms.
+  const int32_t skip = ctl->st[0].done | ctl->st[1].done | ctl->hold;
+  double v[2][7];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int j = threadIdx.x + k * blockDim.x;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) v[k][c] = j < nrec ? one.lpart[j * 7 + c] : 0.0;
+  }
+  StokesState cur;
+  if (threadIdx.x == 0) cur = ctl->st[par];
+  if (skip) return;
+  double tot[7];
+  if (nrec <= 2 * (int)blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) tot[c] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int c = 0; c < 7; ++c) tot[c] += v[k][c];
+    block_sum<7>(tot, red7);
+  } else {
+    stokes_sum_records<2>(one.lpart, nrec, tot, red7);
+  }
+  if (threadIdx.x == 0) {
+    StokesState nx;
+    stokes_step4(ctl, cur, tot, ntot, nx);
+    stokes_history(ctl, cur, nx, one.hist);
+    ctl->st[par ^ 1] = nx;
+    if (!nx.done && nx.psi[2] != cur.psi[2]) ctl->hold = 1 + (par ^ 1);
+  }
+}
+
 // ------------------------------------------------------------------ launchers
+
+template <typename T>
+hipError_t launch_slab_step4(const Geom& g, const StokesCellArgs& one, int par, int nrec,
+                             hipStream_t s) {
+  int nt = 0;
+  switch (g.nx) {
+#define CASE(N)                  \
+  case N:                        \
+    nt = SlabCfg<T, N, N>::NT;   \
+    break;
+    ACM_SLAB_LENGTHS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  ACM_LAUNCH(k_slab_step4, dim3(1), dim3(nt), 0, s, one, par, nrec, g.ntot);
+  return hipGetLastError();
+}
 
 template <typename T>
 bool slab_supported(const Geom& g) {
@@ -359,7 +442,8 @@ int slab_local_blocks(const Geom& g) {
 
 template <typename T>
 hipError_t launch_slab_local(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
-                             const StokesCellArgs* many, int ncells, int par, hipStream_t s) {
+                             const StokesCellArgs* many, int ncells, int par, int green_blocks,
+                             hipStream_t s) {
   const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
   dim3 grid((unsigned)g.nz, (unsigned)g.dim, (unsigned)ncells);
   switch (g.nx) {
@@ -367,7 +451,8 @@ hipError_t launch_slab_local(const Geom& g, const DevTables<T>& tb, const Stokes
   case N: {                                                                                    \
     using S = SlabCfg<T, N, N>;                                                                \
     ACM_LAUNCH((k_slab_local<T, N, N, false>), grid, dim3(S::NT), S::LDS_BYTES, s, one, many,  \
-               par, 0, g.ntot, g.nspec, ct + tb.off.tw_x, ct + tb.off.tw_y, ct + tb.off.rtw);  \
+               par, green_blocks, g.ntot, g.nspec, ct + tb.off.tw_x, ct + tb.off.tw_y,         \
+               ct + tb.off.rtw);                                                               \
     return hipGetLastError();                                                                  \
   }
     ACM_SLAB_LENGTHS(CASE)
@@ -451,9 +536,11 @@ hipError_t launch_slab_fused(const Geom& g, const DevTables<T>& tb, const Stokes
   template hipError_t launch_slab_fused<T>(const Geom&, const DevTables<T>&,                   \
                                            const StokesCellArgs&, int, int, hipStream_t);      \
   template int slab_local_blocks<T>(const Geom&);                                              \
+  template hipError_t launch_slab_step4<T>(const Geom&, const StokesCellArgs&, int, int,       \
+                                           hipStream_t);                                       \
   template hipError_t launch_slab_local<T>(const Geom&, const DevTables<T>&,                   \
                                            const StokesCellArgs&, const StokesCellArgs*, int,   \
-                                           int, hipStream_t);                                  \
+                                           int, int, hipStream_t);                             \
   template hipError_t launch_slab_rhs<T>(const Geom&, const DevTables<T>&,                     \
                                          const StokesCellArgs&, const StokesCellArgs*, int,     \
                                          int, int, int, hipStream_t);

@@ -47,7 +47,7 @@ __global__ __launch_bounds__((ColCfg<T, L, NC, VAR, SPL>::NT)) void k_stokes_gre
   extern __shared__ __align__(16) char smem_raw[];
   __shared__ double red[3 * 16];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-  if (stokes_done(ctl)) return;
+  if (stokes_skip(ctl)) return;
   const T beta = (T)ctl->st[par].psi[1];
   const T bpen = (T)ctl->st[par].psi[2];
   const T nu = (T)ctl->nu;
@@ -200,7 +200,7 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_stokes_local(
   __shared__ int s_last;
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   T* ldsr = reinterpret_cast<T*>(smem_raw);
-  if (stokes_done(ctl)) return;
+  if (stokes_skip(ctl)) return;
   const StokesState& S = ctl->st[par];
   const double al = S.psi[0], bb = S.psi[2];
   const T cc = (T)(bb / (bb + al));
@@ -270,7 +270,7 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_stokes_rhs(
   extern __shared__ __align__(16) char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   T* ldsr = reinterpret_cast<T*>(smem_raw);
-  if (stokes_done(ctl)) return;
+  if (stokes_skip(ctl)) return;
   const StokesState& S = ctl->st[slot];
   const T bb = (T)S.psi[2];
   const T bcp = (T)(S.psi[2] * S.c_prev);
@@ -318,7 +318,7 @@ __global__ __launch_bounds__((ColCfg<T, L, NC, VAR>::NT)) void k_stokes_green_re
   extern __shared__ __align__(16) char smem_raw[];
   __shared__ double red[3 * 16];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-  if (stokes_done(ctl)) return;
+  if (stokes_skip(ctl)) return;
   const T beta = (T)ctl->st[par].psi[1];
   const T bpen = (T)ctl->st[par].psi[2];
   const T nu = (T)ctl->nu;

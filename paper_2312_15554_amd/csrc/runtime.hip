@@ -321,6 +321,7 @@ struct StokesGroup {
   std::vector<int> cells;  // indices into the call's cell list
   bool slab = false;
   bool fused = false;    // slab local + rhs in one launch (single resident cell)
+  bool s4 = false;       // Step 4 in the green pass after the first iterations (single slab cell)
   int green_var = 0;     // tile variant of the green pass
   int ngreen = 0;        // green workgroups per cell for that variant
   int ngreen_max = 0;    // partial-buffer capacity (largest variant)
@@ -337,8 +338,15 @@ struct StokesGroup {
 
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// IT_RHS: Step 4 in the rhs pass (slab) or the local pass (rows).
+// IT_STEP4: slab passes whose iteration ends with the one-workgroup Step 4
+// kernel instead of the rhs pass (the local pass has formed r with the b of
+// the iteration; a Step 4 that changes b sets the hold word).
+enum { IT_RHS = 0, IT_STEP4 = 1 };
+
 template <typename T>
-static hipError_t enqueue_iteration(StokesGroup<T>& G, hipStream_t s, Profiler* prof) {
+static hipError_t enqueue_iteration(StokesGroup<T>& G, hipStream_t s, Profiler* prof,
+                                    int mode = IT_RHS) {
   const Geom& g = G.pl->g;
   DevTables<T> tb = tables_of<T>(G.pl);
   const int n = (int)G.cells.size();
@@ -369,6 +377,17 @@ static hipError_t enqueue_iteration(StokesGroup<T>& G, hipStream_t s, Profiler* 
   e = launch_stokes_green<T>(g, tb, one, many, n, par, G.green_var, nullptr, s);
   if (e != hipSuccess) return e;
   prof->end(KK_GREEN, ev0);
+  if (mode == IT_STEP4) {
+    prof->begin(KK_LOCAL, &ev0);
+    e = launch_slab_local<T>(g, tb, one, many, n, par, G.ngreen, s);
+    if (e != hipSuccess) return e;
+    prof->end(KK_LOCAL, ev0);
+    prof->begin(KK_RHS, &ev0);
+    e = launch_slab_step4<T>(g, one, par, slab_local_blocks<T>(g), s);
+    if (e != hipSuccess) return e;
+    prof->end(KK_RHS, ev0);
+    return hipSuccess;
+  }
   if (G.fused) {
     prof->begin(KK_LOCAL, &ev0);
     e = launch_slab_fused<T>(g, tb, one, par, G.ngreen, s);
@@ -378,7 +397,7 @@ static hipError_t enqueue_iteration(StokesGroup<T>& G, hipStream_t s, Profiler* 
   }
   if (G.slab) {
     prof->begin(KK_LOCAL, &ev0);
-    e = launch_slab_local<T>(g, tb, one, many, n, par, s);
+    e = launch_slab_local<T>(g, tb, one, many, n, par, G.ngreen, s);
     if (e != hipSuccess) return e;
     prof->end(KK_LOCAL, ev0);
     prof->begin(KK_RHS, &ev0);
@@ -444,11 +463,14 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
     bool aligned = true;
     for (int i : G.cells)
       aligned = aligned && ((uintptr_t)cells[i].u % 32 == 0) && ((uintptr_t)cells[i].H % 16 == 0);
-    if (o.pass_mode == 2 || o.pass_mode == 3) {
+    const bool one_cell = groups.size() == 1 && G.cells.size() == 1;
+    if (o.pass_mode == 2 || o.pass_mode == 3 || o.pass_mode == 4) {
       if (!(slab_supported<T>(g) && aligned))
         return fail(ACM_E_INVALID,
                     "fused xy passes need a 3D cell with nx == ny <= 128 and aligned u, H");
-      const bool one_cell = groups.size() == 1 && G.cells.size() == 1;
+      if (o.pass_mode == 4 && !one_cell)
+        return fail(ACM_E_INVALID, "the Step 4 kernel form needs a single cell");
+      G.s4 = o.pass_mode == 4;
       if (o.pass_mode == 3 && !(one_cell && slab_fused_capacity<T>(g) >= g.nz * g.dim))
         return fail(ACM_E_INVALID,
                     "the single-launch slab pass needs one cell whose nz * 3 workgroups are all "
@@ -457,11 +479,13 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
       G.fused = o.pass_mode == 3;
     } else if (o.pass_mode == 0) {
       // the single-launch structure is not chosen automatically: its
-      // device-wide gate has measured slower than the launch boundary
+      // device-wide gate has measured slower than the launch boundary; the
+      // Step 4 kernel form is (one cell)
       G.slab = slab_supported<T>(g) && aligned;
+      G.s4 = G.slab && one_cell;
     }
     G.nlocal = std::max(G.pl->local_blocks, slab_local_blocks<T>(g));
-    G.part_b = sizeof(double) * (size_t)(3 * G.ngreen_max + 4 * G.nlocal);
+    G.part_b = sizeof(double) * (size_t)(3 * G.ngreen_max + 7 * G.nlocal);
     G.cell_b = al256(G.spec_b) + 2 * al256(G.one_b) + al256(G.a_b) + al256(G.part_b);
     HIP_TRY(hipMalloc(&G.ws.p, G.cell_b * G.cells.size()));
     for (size_t k = 0; k < G.cells.size(); ++k) {
@@ -662,6 +686,23 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
     }
   } evf{&evs};
   const bool use_graph = o.use_graph && !prof.on;
+  // Step 4 in its own kernel: a single slab cell after its first iterations
+  // (in which Step 4 changes b often); graph_b holds those iterations
+  StokesGroup<T>* s4g = (groups.size() == 1 && groups[0]->s4) ? groups[0].get() : nullptr;
+  // profiled solves check every other iteration, so that the launches that
+  // skip behind a hold (counted by the profiler) stay at most one iteration
+  if (s4g && prof.on) K = std::min(K, 2);
+  hipGraph_t graph_b = nullptr;
+  hipGraphExec_t exec_b = nullptr;
+  struct GraphFreeB {
+    hipGraph_t* g;
+    hipGraphExec_t* x;
+    ~GraphFreeB() {
+      if (*x) (void)hipGraphExecDestroy(*x);
+      if (*g) (void)hipGraphDestroy(*g);
+    }
+  } gfb{&graph_b, &exec_b};
+  const int start_par = groups[0]->par;  // state slot every replay starts from
   if (use_graph) {
     std::vector<hipStream_t> br;
     if (groups.size() > 1) {
@@ -672,6 +713,22 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
         HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         evs.push_back(e);
       }
+    }
+    if (s4g) {
+      // the iterations ending with the Step 4 kernel, captured from the same
+      // state slot as the others
+      HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      hipError_t e = hipSuccess;
+      for (int k = 0; k < K && e == hipSuccess; ++k)
+        e = enqueue_iteration<T>(*s4g, s, &prof, IT_STEP4);
+      hipError_t e2 = hipStreamEndCapture(s, &graph_b);
+      if (e != hipSuccess) {
+        if (graph_b) (void)hipGraphDestroy(graph_b);
+        graph_b = nullptr;
+        return fail(ACM_E_HIP, std::string("kernel launch during capture: ") + hipGetErrorString(e));
+      }
+      HIP_TRY(e2);
+      HIP_TRY(hipGraphInstantiate(&exec_b, graph_b, nullptr, nullptr, 0));
     }
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
@@ -707,13 +764,15 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
   auto t0 = std::chrono::steady_clock::now();
   std::vector<double> t_done(ncell, -1.0);
   int64_t launched = 0;
+  bool step4_kernel = false;  // the iterations now end with the Step 4 kernel
+  int64_t it_prev = -1;
   for (;;) {
     if (use_graph) {
-      HIP_TRY(hipGraphLaunch(exec, s));
+      HIP_TRY(hipGraphLaunch(step4_kernel ? exec_b : exec, s));
     } else {
       for (int k = 0; k < K; ++k)
         for (auto& Gp : groups) {
-          hipError_t e = enqueue_iteration<T>(*Gp, s, &prof);
+          hipError_t e = enqueue_iteration<T>(*Gp, s, &prof, step4_kernel ? IT_STEP4 : IT_RHS);
           if (e != hipSuccess) return fail(ACM_E_HIP, std::string("launch: ") + hipGetErrorString(e));
         }
     }
@@ -729,7 +788,38 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
       all = all && done;
     }
     if (all) break;
-    if (launched > o.max_iter + 2LL * K) break;  // safety net: the device caps iterations itself
+    // safety net (the device caps the iterations itself): launches that no
+    // longer advance any cell; iterations skipped behind a hold do not count
+    int64_t it_now = 0;
+    for (int i = 0; i < ncell; ++i) it_now = std::max(it_now, latest_state(hctl[i]).iter);
+    const bool held = s4g && step4_kernel && hctl[0].hold;
+    if (!held && launched > o.max_iter + 2LL * K && it_now == it_prev) break;
+    it_prev = it_now;
+    if (s4g && !step4_kernel && launched >= kRhsStep4Iters) {
+      // from here Step 4 runs in its own kernel (Step 4 of the last iteration
+      // was formed by its rhs pass: nothing else to do)
+      step4_kernel = true;
+    } else if (s4g && step4_kernel && hctl[0].hold) {
+      // A Step 4 kernel found that b changed, stored the new state in slot
+      // hold - 1 and stopped the iterations after it.  r is formed again from
+      // u, a and H with the new b; then, if needed, one iteration brings the
+      // next state slot back to the one the captured iterations start from.
+      StokesGroup<T>& G = *s4g;
+      const Geom& g = G.pl->g;
+      DevTables<T> tb = tables_of<T>(G.pl);
+      const int slot = hctl[0].hold - 1;
+      HIP_TRY(hipMemsetAsync(&dctl[0].hold, 0, sizeof(int32_t), s));
+      hipEvent_t ev0 = nullptr;
+      prof.begin(KK_RHS, &ev0);
+      hipError_t e = launch_slab_rhs<T>(g, tb, G.hargs[0], nullptr, 1, slot, 0, 0, s);
+      prof.end(KK_RHS, ev0);
+      G.par = slot;
+      if (e == hipSuccess && G.par != start_par) {
+        e = enqueue_iteration<T>(G, s, &prof, IT_STEP4);
+        launched += 1;
+      }
+      if (e != hipSuccess) return fail(ACM_E_HIP, std::string("launch: ") + hipGetErrorString(e));
+    }
   }
   auto t1 = std::chrono::steady_clock::now();
 
@@ -823,7 +913,7 @@ static acm_status check_stokes_cell(const acm_grid* grid, const uint8_t* H, cons
 static acm_status check_penalty_opts(const acm_penalty& P, const acm_opts& O, double nu) {
   if (!(nu > 0.0) || !isfinite(nu)) return fail(ACM_E_INVALID, "nu must be positive");
   if (!(O.eps >= 0.0) || O.max_iter < 1) return fail(ACM_E_INVALID, "eps >= 0 and max_iter >= 1 required");
-  if (O.pass_mode < 0 || O.pass_mode > 3) return fail(ACM_E_INVALID, "pass_mode must be 0, 1, 2 or 3");
+  if (O.pass_mode < 0 || O.pass_mode > 4) return fail(ACM_E_INVALID, "pass_mode must be 0 to 4");
   if (O.green_variant < 0 || O.green_variant > kGreenVariants)
     return fail(ACM_E_INVALID, "green_variant must be in [0, " + std::to_string(kGreenVariants) + "]");
   for (int k = 0; k < 3; ++k)

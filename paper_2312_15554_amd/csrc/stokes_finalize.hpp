@@ -41,6 +41,29 @@ __device__ __forceinline__ void stokes_sum_partials(const double* __restrict__ g
   block_sum<7>(acc, red);
 }
 
+// Totals of the records of the two-launch slab local pass (7 per workgroup:
+// its share of the green partials, then its 4 local partials), in a fixed
+// order; valid in thread 0.  `red` holds 7 * 16 doubles.
+template <int U>
+__device__ __forceinline__ void stokes_sum_records(const double* __restrict__ rec, int nrec,
+                                                   double (&acc)[7], double* red) {
+  for (int k = 0; k < 7; ++k) acc[k] = 0.0;
+  for (int j0 = threadIdx.x; j0 < nrec; j0 += U * blockDim.x) {
+    double v[U][7];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int j = j0 + k * blockDim.x;
+#pragma unroll
+      for (int c = 0; c < 7; ++c) v[k][c] = j < nrec ? rec[j * 7 + c] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+#pragma unroll
+      for (int c = 0; c < 7; ++c) acc[c] += v[k][c];
+  }
+  block_sum<7>(acc, red);
+}
+
 // Step 4 and the penalty update: the state `nx` that follows `cur` given the
 // totals.  Pure function of its inputs (one thread calls it).
 __device__ __forceinline__ void stokes_step4(const StokesCtl* __restrict__ ctl,

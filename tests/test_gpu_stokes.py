@@ -48,7 +48,7 @@ def test_fixed_penalty_iterates_match_oracle(shape, dtype):
 @pytest.mark.gpu
 @pytest.mark.parametrize("shape", SLAB_SHAPES)
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("pass_mode", [1, 2, 3])
+@pytest.mark.parametrize("pass_mode", [1, 2, 3, 4])
 def test_fused_and_separate_passes_match_oracle(shape, dtype, pass_mode):
     """All 3D pass structures (separate x/y passes, fused xy slabs, and fused
     slabs with local and rhs in one launch) reproduce the oracle's iterates
@@ -317,3 +317,91 @@ def test_profile_mode_times_every_pass_and_changes_nothing(shape, pass_mode):
     for k in kinds:
         assert st["kernel_calls"][k] == 30, (k, st["kernel_calls"])
         assert st["kernel_ms"][k] > 0.0, k
+
+
+def _b_changes_after(history, first):
+    """Iterations past `first` whose Step 4 changed b (history column 14 holds
+    the b each iteration used)."""
+    b = history[:, 14]
+    return [i for i in range(max(first, 1), len(b)) if b[i] != b[i - 1]]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,iters,check", [(32, 400, 16), (64, 300, 16), (128, 420, 0)])
+@pytest.mark.parametrize("graph", [True, False])
+def test_step4_kernel_gives_the_bits_of_the_rhs_form(n, iters, check, graph):
+    """Pass mode 4 (once the first iterations are done, a one-workgroup kernel
+    forms Step 4 in place of the rhs pass; a Step 4 that changes b holds the
+    iterations until r is formed again) computes what pass mode 2 computes
+    over a run long enough for several such holds (overlapping spheres,
+    adaptive penalties of the random-geometry schedule, FP32): the same
+    penalties at every iteration, the same residual history and the same u
+    and q, bit for bit.  graph = False runs the same modes eagerly
+    (profiled)."""
+    require_gpu()
+    print(f"step4 kernel vs rhs form n={n} iters={iters} graph={graph}", flush=True)
+    H = dev(I.overlapping_spheres(n, n / 16.0, 0.40, seed=1))
+    # one green kernel for both (the autotuner's trial iterations would
+    # otherwise run other variants, equal only to rounding, in the first solve)
+    kw = dict(penalty=dict(tau=(5.0, 10.0, 5.0)), eps=0.0, max_iter=iters, want_q=True,
+              history_cap=iters, check_every=check, use_graph=graph, profile=not graph,
+              green_variant=1)
+    r2 = _solve_dev(H, (1.0, 0.0, 0.0), pass_mode=2, **kw)
+    r4 = _solve_dev(H, (1.0, 0.0, 0.0), pass_mode=4, **kw)
+    assert r2["stats"]["iters"] == r4["stats"]["iters"] == iters
+    holds = _b_changes_after(r4["history"], 65)
+    print(f"  b changed after the switch at iterations {holds}", flush=True)
+    assert len(holds) >= 2
+    bad = np.argwhere(r2["history"] != r4["history"])
+    if len(bad):
+        i, j = bad[0]
+        print(f"  first difference: iteration {i} column {j}: {r2['history'][i, j]!r} vs "
+              f"{r4['history'][i, j]!r} ({len(bad)} entries)", flush=True)
+    assert np.array_equal(r2["history"], r4["history"])
+    for key in ("psi", "r_p", "r_d", "tol_p", "tol_d"):
+        assert r2["stats"][key] == r4["stats"][key], key
+    assert torch.equal(r2["u"], r4["u"])
+    assert torch.equal(r2["q"], r4["q"])
+    if not graph:
+        # every iteration ends with a rhs pass or the Step 4 kernel (both
+        # counted as "rhs"); each hold adds one rhs pass
+        calls = r4["stats"]["kernel_calls"]
+        assert calls["green"] == calls["local"] >= iters
+        assert calls["green"] < calls["rhs"] <= calls["green"] + len(holds)
+
+
+@pytest.mark.gpu
+def test_step4_kernel_matches_oracle_with_adaptive_penalties():
+    """Pass mode 4 against the FP64 oracle with adaptive penalties over 240
+    iterations (the last 176 with Step 4 in its own kernel)."""
+    require_gpu()
+    shape = (16, 32, 32)
+    print(f"step4 kernel oracle parity {shape}", flush=True)
+    H = I.overlapping_spheres(shape, 2.0, 0.45, seed=7)
+    g = (1.0, 0.3, -0.5)
+    M = 240
+    r = _solve(H, g, dtype=torch.float64, penalty=dict(tau=(5.0, 10.0, 5.0)), eps=0.0,
+               max_iter=M, check_every=8, pass_mode=4, history_cap=M)
+    o = O.stokes_admm(H, g, tau=(5.0, 10.0, 5.0), eps=0.0, max_iter=M, history=True)
+    assert r["stats"]["iters"] == M
+    tol = 1e-10
+    assert np.abs(host(r["u"]) - o["u"]).max() < tol * np.abs(o["u"]).max()
+    assert np.abs(host(r["q"]) - o["q"]).max() < tol * 10 * np.abs(o["q"]).max()
+    # the penalties every iteration used, and its residuals
+    hp = np.array([h["psi"] for h in o["history"]])
+    hr = np.array([h["rp"] + h["rd"] for h in o["history"]])
+    assert np.array_equal(r["history"][:, 12:15], hp)
+    assert len(_b_changes_after(r["history"], 65)) >= 1
+    assert np.allclose(r["history"][:, 0:6], hr, rtol=1e-8, atol=1e-14)
+
+
+@pytest.mark.gpu
+def test_step4_kernel_rejects_batches():
+    """Pass mode 4 is for a single cell: a batch of two is refused."""
+    require_gpu()
+    from paper_2312_15554_amd import abi
+    from paper_2312_15554_amd.api import acm_stokes_solve_batched
+    Hs = [dev(I.overlapping_spheres(32, 2.0, 0.5, seed=s)) for s in (3, 4)]
+    with pytest.raises(abi.AcmError) as e:
+        acm_stokes_solve_batched(Hs, [(1.0, 0.0, 0.0)] * 2, eps=1e-5, max_iter=100, pass_mode=4)
+    assert e.value.status == abi.ACM_E_INVALID
