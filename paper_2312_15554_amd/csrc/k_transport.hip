@@ -37,7 +37,8 @@ using TGCfg = ColCfg<T, L, NC, kTGVar, kTGSpl>;
 
 // Fields the green pass transforms forward: the row form brings tau-hat (D
 // fields) and f-hat; the slab form (SL) brings S = G_x + G_y + f_z as three
-// partial spectra, summed on load, and tau_z (see k_transport_slab).
+// partial spectra (fields 0, 1, 4), summed on load, and tau_z (field 3; see
+// k_transport_slab).
 template <int D, bool SL>
 constexpr int tg_inputs() { return SL ? 2 : D + 1; }
 template <int D, bool SL>
@@ -77,7 +78,7 @@ __global__ __launch_bounds__((TGCfg<T, L, tg_fields<D, SL>()>::NT)) void k_trans
         const int64_t mi = (int64_t)i * P + f;
         if constexpr (SL) {
           if (c == 0) {  // S = G_x + G_y + f_z
-            const cplx<T> a = spec[mi], b = spec[gg.nspec + mi], d = spec[2 * gg.nspec + mi];
+            const cplx<T> a = spec[mi], b = spec[gg.nspec + mi], d = spec[4 * gg.nspec + mi];
             v = cmake<T>(a.x + b.x + d.x, a.y + b.y + d.y);
           } else {  // tau_z
             v = spec[3 * gg.nspec + mi];
@@ -283,10 +284,11 @@ __global__ __launch_bounds__((RowCfgN<T, M, D + 1>::NT)) void k_transport_local(
 // share of f, f_c = calF (1-H) [c = 0 only] - (B_c - B0_c) e_c.  Since F =
 // f + div tau, the x and y workgroups fold their divergence term in real
 // space, G_c = f_c + D_c tau_c, and transform only G_c (into field c); the z
-// workgroup transforms f_z (field 2) and tau_z (field 3), whose derivative
-// needs the z transform.  The green pass then transforms S = G_x + G_y + f_z
-// and tau_z.  Compared with the row pass this saves the separate y passes and
-// three of the seven forward transforms of the iteration.
+// workgroups transform f_z (field 4) and tau_z (field 3, whose derivative
+// needs the z transform), one each, so that every workgroup does one inverse
+// and one forward transform.  The green pass then transforms S = G_x + G_y +
+// f_z and tau_z.  Compared with the row pass this saves the separate y passes
+// and three of the seven forward transforms of the iteration.
 template <typename T, int N>
 __global__ __launch_bounds__((SlabCfg<T, N, N>::NT))
 __attribute__((amdgpu_waves_per_eu(SlabCfg<T, N, N>::WPE_ONE))) void k_transport_slab(
@@ -324,15 +326,18 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, N, N>::WPE_ONE))) void k_transport
     __syncthreads();
     if (s_stop) return;
   }
-  const int z = blockIdx.x, c = blockIdx.y;
+  // workgroup kinds: c = 0, 1 (axis c, output G_c), 2 (axis z, output f_z),
+  // 3 (axis z, output tau_z): four kinds of equal work (one inverse and one
+  // forward slab transform each)
+  const int z = blockIdx.x, c = blockIdx.y, ax = c < 2 ? c : 2;
   const int64_t soff = (int64_t)z * N * S::XH;
-  slab_load_inverse<T, N, N>(lds, spec + c * nspec + soff, twx, twy, rtw);
+  slab_load_inverse<T, N, N>(lds, spec + ax * nspec + soff, twx, twy, rtw);
 
-  const T gc = (T)ctl->g[c], B0c = (T)ctl->B0[c];
+  const T gc = (T)ctl->g[ax], B0c = (T)ctl->B0[ax];
   const T A0 = (T)ctl->A0, Pe = (T)ctl->Pe, eta = (T)ctl->eta, dif = (T)ctl->diff;
   const T calF = c == 0 ? (T)ctl->calF : T(0);
   const int64_t off = (int64_t)z * S::NV;
-  const V* uq = reinterpret_cast<const V*>(u + c * ntot + off);
+  const V* uq = reinterpret_cast<const V*>(u + ax * ntot + off);
   const uint32_t* hq = reinterpret_cast<const uint32_t*>(H + off);
   V fr[S::QPT];
 #pragma unroll
@@ -402,9 +407,9 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, N, N>::WPE_ONE))) void k_transport
       fr[j].w += hs * d[3];
     }
     __syncthreads();  // every tau neighbour has been read
-  } else {
+  } else if (c == 3) {
     slab_forward_store<T, N, N>(lds, spec + 3 * nspec + soff, twx, twy, rtw);  // tau_z
-    __syncthreads();
+    return;
   }
 #pragma unroll
   for (int j = 0; j < S::QPT; ++j) {
@@ -415,8 +420,9 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, N, N>::WPE_ONE))) void k_transport
     lds_st4(ldsr + y * 2 * S::P2 + x, fr[j]);
   }
   __syncthreads();
-  // G_x, G_y or f_z into the field this workgroup read
-  slab_forward_store<T, N, N>(lds, spec + c * nspec + soff, twx, twy, rtw);
+  // G_x, G_y into the field this workgroup read; f_z into field 4 (field 2 is
+  // still read by the tau_z workgroup of this slab)
+  slab_forward_store<T, N, N>(lds, spec + (c < 2 ? c : 4) * nspec + soff, twx, twy, rtw);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -521,7 +527,7 @@ hipError_t launch_transport_slab(const Geom& g, const DevTables<T>& tb, void* sp
   const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
   auto* sp = reinterpret_cast<cplx<T>*>(spec);
   if (g.dim != 3 || g.nx != g.ny) return hipErrorInvalidValue;
-  dim3 grid((unsigned)g.nz, 3u, 1u);
+  dim3 grid((unsigned)g.nz, 4u, 1u);
   switch (g.nx) {
 #define CASE(NN)                                                                                \
   case NN: {                                                                                    \

@@ -969,7 +969,8 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
   const bool tslab = d == 3 && slab_supported<T>(g) && ((uintptr_t)u % 16 == 0) &&
                      ((uintptr_t)H % 4 == 0);
   const size_t cb = sizeof(T) * 2;
-  const size_t spec_b = cb * (size_t)g.nspec * (d + 1);
+  // slab form: a fifth field holds f_z (see k_transport_slab)
+  const size_t spec_b = cb * (size_t)g.nspec * (d + (tslab ? 2 : 1));
   const size_t one_b = cb * (size_t)g.nspec;
   const int ngreen = std::max(transport_green_blocks(g, pl->prec, false),
                               transport_green_blocks(g, pl->prec, tslab));
