@@ -100,6 +100,19 @@ def transport_section(H, u_flow, log):
         chis.append(chi)
         log(f"transport g_chi=e{j}: {r['stats']['iters']} LS iterations, {secs[-1]:.2f} s, "
             f"converged {r['stats']['converged']}")
+    # per-kernel event times of one profiled time step (g_chi = e_x) against
+    # the byte model of the transport passes
+    rp = acm_transport_step(H, un, [1.0, 0.0, 0.0], Pe, eta=0.01, A0=A0, B0=B0, dt=2e-3,
+                            n_steps=1, eps=1e-6, max_iter=2000, profile=True)
+    st = rp["stats"]
+    nn3 = H.shape[0]
+    kern = {}
+    for k, kind in (("t_green", "t_green"), ("t_local", "t_slab")):
+        if st["kernel_calls"][k]:
+            ms = st["kernel_ms"][k] / st["kernel_calls"][k]
+            kern[k] = dict(avg_us=round(ms * 1e3, 2), calls=st["kernel_calls"][k],
+                           GBps=gbps(kernel_bytes(kind, nn3, 3, 0), ms))
+    out["kernels"] = kern
     p = acm_effective_props(H, [], chis, u_transport=un, Pe=Pe)
     n = H.numel()
     # What drives the solute-mass drift: with B = Pe (1-H) u the mean of chi
@@ -213,6 +226,11 @@ def kernel_bytes(kind: str, n: int, d: int, nsolid: int, real_bytes: int = 4) ->
                 + ntot)
     if kind == "rhs_full":  # the rhs pass when Step 4 changed b: u, a (solid), H in, spectra out
         return d * ntot * real_bytes + d * nsolid * real_bytes + ntot + d * nspec * cb
+    if kind == "t_slab":  # transport slab pass (3D): grad chi-hat in, u and H in, 4 spectra out
+        return (d + d + 1) * nspec * cb + d * ntot * real_bytes + ntot
+    if kind == "t_green":  # transport green pass (3D slab form, time step): 4 spectra,
+        # chi-hat and chi-hat of the last step in; chi-hat and grad chi-hat out
+        return (4 + 1 + 1 + 1 + d) * nspec * cb
     # "rhs": Step 4 from the FP64 partial sums (a few KB), the full pass only
     # when b changed, so no byte model
     return float("nan")
