@@ -100,10 +100,12 @@ def transport_section(H, u_flow, log):
         chis.append(chi)
         log(f"transport g_chi=e{j}: {r['stats']['iters']} LS iterations, {secs[-1]:.2f} s, "
             f"converged {r['stats']['converged']}")
-    # per-kernel event times of one profiled time step (g_chi = e_x) against
-    # the byte model of the transport passes
+    # per-kernel event times of one profiled time step (g_chi = e_x, 192 LS
+    # iterations with no stop test: a multiple of the 16 between host checks,
+    # so that no launch skips after the last iteration) against the byte
+    # model of the transport passes
     rp = acm_transport_step(H, un, [1.0, 0.0, 0.0], Pe, eta=0.01, A0=A0, B0=B0, dt=2e-3,
-                            n_steps=1, eps=1e-6, max_iter=2000, profile=True)
+                            n_steps=1, eps=0.0, max_iter=192, check_every=16, profile=True)
     st = rp["stats"]
     nn3 = H.shape[0]
     kern = {}
