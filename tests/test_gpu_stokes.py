@@ -50,9 +50,10 @@ def test_fixed_penalty_iterates_match_oracle(shape, dtype):
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("pass_mode", [1, 2, 3, 4])
 def test_fused_and_separate_passes_match_oracle(shape, dtype, pass_mode):
-    """All 3D pass structures (separate x/y passes, fused xy slabs, and fused
-    slabs with local and rhs in one launch) reproduce the oracle's iterates
-    with fixed penalties."""
+    """All 3D pass structures (separate x/y passes, fused xy slabs, fused
+    slabs with local and rhs in one launch, and the Step 4 kernel form, whose
+    first 64 iterations are those of the fused slabs) reproduce the oracle's
+    iterates with fixed penalties."""
     require_gpu()
     print(f"pass parity shape={shape} dtype={dtype} mode={pass_mode}", flush=True)
     H = I.overlapping_spheres(shape, shape[-1] / 16.0, 0.5, seed=5)
