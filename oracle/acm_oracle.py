@@ -70,13 +70,20 @@ def _ifft(F):
 # Symbols (Section 3.2, eq. fft_app)
 # ---------------------------------------------------------------------------
 
-def symbols(shape):
-    """Central first-derivative symbols s_c and compact Laplacian symbol L.
+def symbols(shape, kind="central"):
+    """First-derivative symbols s_c and Laplacian symbol L on the unit cell.
 
+    kind "central" (the paper's scheme, Section 3.3): s_c = sin(theta_c)/h_c,
+    the symbol of the central difference, and the compact Laplacian
+    L = sum_c 4 sin^2(theta_c/2)/h_c^2.  kind "spectral" (the exact-FFT
+    alternative the paper compares against in Section 4): s_c = theta_c/h_c =
+    2 pi m_c and L = sum_c (2 pi m_c)^2, with m_c the signed wavenumber.
     Returns (s, L): s is a list with one broadcastable array per vector
-    component c (0=x on the last numpy axis); L = sum_c 4 sin^2(theta_c/2)/h_c^2.
-    s_c vanishes exactly at the Nyquist index (sin(pi) = 0).
+    component c (0=x on the last numpy axis).  s_c vanishes at the Nyquist
+    index in both (sin(pi) = 0; a real field has no odd Nyquist derivative).
     """
+    if kind not in ("central", "spectral"):
+        raise ValueError("kind must be 'central' or 'spectral'")
     nd = len(shape)
     s = []
     L = np.zeros([1] * nd)
@@ -85,10 +92,14 @@ def symbols(shape):
         n = shape[ax]
         m = np.fft.fftfreq(n, d=1.0 / n)
         theta = 2.0 * np.pi * m / n
-        sc = np.sin(theta) * n
+        if kind == "central":
+            sc = np.sin(theta) * n
+            lc = 4.0 * np.sin(theta / 2.0) ** 2 * n * n
+        else:
+            sc = theta * n
+            lc = (theta * n) ** 2
         if n % 2 == 0:
             sc[np.abs(m) == n // 2] = 0.0
-        lc = 4.0 * np.sin(theta / 2.0) ** 2 * n * n
         bshape = [1] * nd
         bshape[ax] = n
         s.append(sc.reshape(bshape))
@@ -155,7 +166,7 @@ def default_penalty(shape, nu=1.0):
 def stokes_admm(H, g, nu=1.0, alpha=None, beta=None, b=None,
                 phi=(1.1, 1.1, 1.1), tau=(5.0, 10.0, 5.0), psi_min=None,
                 adaptive=True, eps=1e-6, max_iter=100000,
-                u_init=None, q_init=None, history=False):
+                u_init=None, q_init=None, history=False, derivative="central"):
     """Solve the unit-cell Stokes problem (eq. unit cell, first two lines) by
     the paper's ADMM on the extended domain.
 
@@ -174,7 +185,7 @@ def stokes_admm(H, g, nu=1.0, alpha=None, beta=None, b=None,
     d = len(shape)
     Ntot = H.size
     Hf = H.astype(np.float64)
-    s, L = symbols(shape)
+    s, L = symbols(shape, derivative)
     pen = default_penalty(shape, nu)
     alpha = pen["alpha"] if alpha is None else float(alpha)
     beta = pen["beta"] if beta is None else float(beta)
@@ -274,10 +285,10 @@ def pore_mean_velocity(H, u):
 
 def transport_ls(H, u, g, Pe, A0=0.55, B0=None, eta=0.01, diffusivity=1.0,
                  eps=1e-6, max_iter=100000, dt=math.inf, n_steps=1,
-                 chi_init=None, history=False):
+                 chi_init=None, history=False, derivative="central"):
     """Penalised advection-diffusion (eq. penalization) by the LS iteration
     (eq. iter, solved in Fourier by eq. fft_solute with the symbols of
-    eq. fft_app).
+    eq. fft_app; derivative="spectral" takes the exact symbols instead).
 
     A = diffusivity (1-H) + eta H, B = Pe (1-H) u, calF = Pe (1-H) ubar . g.
     dt = inf: the paper's steady cell problem (one solve, chi-hat(0) = 0).
@@ -291,7 +302,7 @@ def transport_ls(H, u, g, Pe, A0=0.55, B0=None, eta=0.01, diffusivity=1.0,
     d = len(shape)
     Ntot = H.size
     Hf = H.astype(np.float64)
-    s, L = symbols(shape)
+    s, L = symbols(shape, derivative)
     u = np.asarray(u, dtype=np.float64)
     gvec = np.array([float(g[c]) for c in range(d)])
     B0 = np.zeros(d) if B0 is None else np.array([float(B0[c]) for c in range(d)])

@@ -245,3 +245,73 @@ def test_paper_parameters_fixture():
     assert p["comparison_medium_A0"]["value"] == 0.55
     assert p["adaptive_tau_model_geometry"]["value"] == [20, 10, 30]
     assert p["adaptive_tau_random_geometry"]["value"] == [5, 10, 5]
+
+
+@pytest.mark.parametrize("shape", [(12, 8), (8, 12, 16)])
+def test_spectral_symbols_differentiate_fourier_modes_exactly(shape):
+    """The exact-FFT symbols (kind "spectral", the alternative to eq. fft_app
+    the paper compares in Section 4) give the calculus derivatives of a
+    resolved Fourier mode: each d/dx_c and the Laplacian of sin(2 pi m.x).
+    The central symbols of eq. fft_app miss them at second order in h."""
+    nd = len(shape)
+    grids = np.meshgrid(*[np.arange(n) / n for n in shape], indexing="ij")
+    m = [1, 2, 3][:nd]  # per numpy axis, below n/2
+    phase = 2 * np.pi * sum(m[a] * grids[a] for a in range(nd))
+    f = np.sin(phase)
+    fh = np.fft.fftn(f)
+    s, L = O.symbols(shape, "spectral")
+    for c in range(nd):
+        ax = nd - 1 - c
+        d = np.real(np.fft.ifftn(1j * s[c] * fh))
+        assert np.abs(d - 2 * np.pi * m[ax] * np.cos(phase)).max() < 1e-10
+    lap = np.real(np.fft.ifftn(-L * fh))
+    k2 = (2 * np.pi) ** 2 * sum(mm * mm for mm in m)
+    assert np.abs(lap + k2 * f).max() < 1e-9 * k2
+    _, Lc = O.symbols(shape, "central")
+    assert np.abs(np.real(np.fft.ifftn(-Lc * fh)) - lap).max() > 1e-3 * k2
+
+
+def test_spectral_diffusion_mode_decay_closed_form():
+    """Pure diffusion of one Fourier mode with the exact symbols: each
+    backward-Euler step divides it by 1 + dt |k|^2, |k| = 2 pi |m|."""
+    shape = (16, 16)
+    H = np.zeros(shape, np.uint8)
+    u = np.zeros((2,) + shape)
+    y, x = np.meshgrid((np.arange(16) + 0.5) / 16, (np.arange(16) + 0.5) / 16, indexing="ij")
+    mode = (2, 1)
+    chi0 = np.cos(2 * np.pi * (mode[0] * x + mode[1] * y))
+    dt, n = 2e-3, 5
+    r = O.transport_ls(H, u, (0.0, 0.0), 0.0, A0=0.55, B0=(0.0, 0.0), eps=1e-12,
+                       dt=dt, n_steps=n, chi_init=chi0, derivative="spectral")
+    amp = (1.0 + dt * (2 * np.pi) ** 2 * (mode[0] ** 2 + mode[1] ** 2)) ** (-n)
+    assert r["status"] == "converged"
+    assert np.abs(r["chi"] - amp * chi0).max() < 1e-9
+
+
+def test_spectral_admm_satisfies_the_spectral_stokes_equations():
+    """ADMM with the exact symbols converges to a field that satisfies the
+    Stokes equations with exact spectral derivatives (written here with
+    numpy's own wavenumbers): divergence-free, momentum balance in the pore,
+    no velocity in the solid."""
+    shape = (16, 16)
+    H = I.random_mask(shape, 3, 0.3)
+    g = (1.0, 0.3)
+    r = O.stokes_admm(H, g, eps=1e-10, tau=(20, 10, 30), derivative="spectral")
+    assert r["status"] == "converged"
+    u, q = r["u"], r["q"]
+    ky, kx = np.meshgrid(2 * np.pi * np.fft.fftfreq(16, 1 / 16), 2 * np.pi * np.fft.fftfreq(16, 1 / 16),
+                         indexing="ij")
+    k1 = [kx.copy(), ky.copy()]
+    for kk in k1:  # first derivatives drop the Nyquist mode of a real field
+        kk[np.isclose(np.abs(kk), np.pi * 16)] = 0.0
+    k2 = kx ** 2 + ky ** 2
+    uh = [np.fft.fft2(u[c]) for c in range(2)]
+    div = np.real(np.fft.ifft2(1j * k1[0] * uh[0] + 1j * k1[1] * uh[1]))
+    scale = np.abs(u).max() * 2 * np.pi * 16
+    assert np.abs(div).max() < 1e-6 * scale
+    qh = np.fft.fft2(q)
+    pore = H == 0
+    for c in range(2):
+        mom = g[c] - np.real(np.fft.ifft2(1j * k1[c] * qh)) - np.real(np.fft.ifft2(k2 * uh[c]))
+        assert np.abs(mom[pore]).max() < 1e-5 * max(1.0, np.abs(g).max())
+        assert np.abs(u[c][~pore]).max() < 1e-5 * np.abs(u).max()  # ADMM constraint at eps
