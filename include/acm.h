@@ -103,6 +103,13 @@ typedef struct {
                            field during the transforms (default and half pencil
                            count).  All variants compute the same iterates up to
                            rounding. */
+  int32_t derivative;   /* derivative symbols: 0 the central-difference symbol and
+                           compact Laplacian (Section 3.2, eq. fft_app; the
+                           paper's scheme), 1 the exact spectral symbols i k and
+                           |k|^2 (the exact-FFT alternative of Section 4).  The
+                           Stokes warm start needs 0; the transport slab form
+                           folds central differences and is replaced by the row
+                           form with 1. */
 } acm_opts;
 
 /* Kernel kinds reported in acm_stats.kernel_ms (with opts.profile = 1).  Each

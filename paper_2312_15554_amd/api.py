@@ -84,6 +84,14 @@ def default_penalty(**kw) -> abi.acm_penalty:
     return p
 
 
+def _deriv(kind) -> int:
+    """acm_opts.derivative of "central" (the paper's symbols) or "spectral"."""
+    table = {"central": 0, "spectral": 1}
+    if kind not in table:
+        raise ValueError(f"derivative must be 'central' or 'spectral', not {kind!r}")
+    return table[kind]
+
+
 def default_opts(**kw) -> abi.acm_opts:
     o = abi.acm_opts()
     abi.load().acm_default_opts(C.byref(o))
@@ -105,7 +113,8 @@ def acm_stokes_solve(H: torch.Tensor, g, nu: float = 1.0, *, dtype=torch.float32
                      check_every: int = 0, use_graph: bool = True, profile: bool = False,
                      history_cap: int = 0, u: torch.Tensor | None = None,
                      q: torch.Tensor | None = None, want_q: bool = True, warm_start: bool = False,
-                     pass_mode: int = 0, green_variant: int = 0, stream=None) -> dict:
+                     pass_mode: int = 0, green_variant: int = 0, derivative: str = "central",
+                     stream=None) -> dict:
     """Stokes cell problem by ADMM (acm_stokes_solve).  H: uint8 device tensor
     in numpy order.  Returns dict(u, q, status, stats, history)."""
     lib = abi.load()
@@ -124,7 +133,7 @@ def acm_stokes_solve(H: torch.Tensor, g, nu: float = 1.0, *, dtype=torch.float32
     opts = default_opts(eps=eps, max_iter=max_iter, precision=_prec(dtype), check_every=check_every,
                         use_graph=int(use_graph), profile=int(profile), history_cap=history_cap,
                         warm_start=int(warm_start), pass_mode=int(pass_mode),
-                        green_variant=int(green_variant))
+                        green_variant=int(green_variant), derivative=_deriv(derivative))
     st = abi.acm_stats()
     hist = (C.c_double * (max(history_cap, 1) * abi.HIST_DOUBLES))() if history_cap > 0 else None
     gr = _grid(shape)
@@ -145,7 +154,8 @@ def acm_stokes_solve_batched(Hs, gs, nu: float = 1.0, *, dtype=torch.float32,
                              penalty: dict | None = None, eps: float = 1e-6,
                              max_iter: int = 1_000_000, check_every: int = 0,
                              use_graph: bool = True, us=None, qs=None, warm_start: bool = False,
-                             pass_mode: int = 0, green_variant: int = 0, stream=None) -> dict:
+                             pass_mode: int = 0, green_variant: int = 0,
+                             derivative: str = "central", stream=None) -> dict:
     """Many cells in one call (acm_stokes_solve_batched).  Hs: list of uint8
     device tensors (any supported sizes), gs: list of body forces.  Returns
     dict(us, qs, status, stats=[per-cell dicts])."""
@@ -176,7 +186,7 @@ def acm_stokes_solve_batched(Hs, gs, nu: float = 1.0, *, dtype=torch.float32,
     pen = default_penalty(**(penalty or {}))
     opts = default_opts(eps=eps, max_iter=max_iter, precision=_prec(dtype), check_every=check_every,
                         use_graph=int(use_graph), warm_start=int(warm_start), pass_mode=int(pass_mode),
-                        green_variant=int(green_variant))
+                        green_variant=int(green_variant), derivative=_deriv(derivative))
     st = (abi.acm_stats * n)()
     status = lib.acm_stokes_solve_batched(n, grids, hp, gp, float(nu), C.byref(pen), C.byref(opts),
                                           up, qp, st, _stream(stream))
@@ -218,7 +228,7 @@ def acm_transport_step(H: torch.Tensor, u: torch.Tensor, g_chi, Pe: float, *,
                        B0=(0.0, 0.0, 0.0), dt: float = math.inf, n_steps: int = 1,
                        eps: float = 1e-6, max_iter: int = 1_000_000, chi: torch.Tensor | None = None,
                        check_every: int = 0, use_graph: bool = True, profile: bool = False,
-                       stream=None) -> dict:
+                       derivative: str = "central", stream=None) -> dict:
     """Penalised advection-diffusion by the LS iteration (acm_transport_step).
     u: flow field (d, *shape) in the working precision.  chi (optional) holds
     the initial value and receives the result.  Returns dict(chi, status, stats)."""
@@ -231,7 +241,8 @@ def acm_transport_step(H: torch.Tensor, u: torch.Tensor, g_chi, Pe: float, *,
         chi = torch.zeros(shape, dtype=u.dtype, device=u.device)
     _expect(chi, shape, u.dtype, "chi")
     opts = default_opts(eps=eps, max_iter=max_iter, precision=_prec(u.dtype),
-                        check_every=check_every, use_graph=int(use_graph), profile=int(profile))
+                        check_every=check_every, use_graph=int(use_graph), profile=int(profile),
+                        derivative=_deriv(derivative))
     st = abi.acm_stats()
     gr = _grid(shape)
     d = len(shape)

@@ -48,6 +48,7 @@ struct CellPlan {
   int green_blocks = 0;  // largest green-pass grid over the tile variants
   int local_blocks = 0;
   int green_var = -1;    // tile variant picked by the autotuner (-1: not yet)
+  int deriv = 0;         // derivative symbols (acm_opts.derivative)
   ~CellPlan() {
     if (ctab) (void)hipFree(ctab);
     if (rtab) (void)hipFree(rtab);
@@ -55,7 +56,7 @@ struct CellPlan {
 };
 
 static std::mutex g_mu;
-static std::map<std::tuple<int, int, int, int, int, int>, std::unique_ptr<CellPlan>> g_plans;
+static std::map<std::tuple<int, int, int, int, int, int, int>, std::unique_ptr<CellPlan>> g_plans;
 
 static bool make_geom(const acm_grid* grid, Geom* g, std::string* why) {
   if (!grid) {
@@ -103,16 +104,27 @@ static void push_twiddles(std::vector<double>& c, int L) {
   }
 }
 
-static void push_symbols(std::vector<double>& rv, int n, int count, int* s_off, int* l_off) {
+// Per-axis symbols on the unit cell (h = 1/n) for bins k < count: kind 0 the
+// central difference sin(2 pi k/n)/h and the compact Laplacian
+// 4 sin^2(pi k/n)/h^2 (eq. fft_app); kind 1 the exact 2 pi m and (2 pi m)^2
+// with m the signed wavenumber.  The first derivative vanishes at Nyquist.
+static void push_symbols(std::vector<double>& rv, int n, int count, int kind, int* s_off,
+                         int* l_off) {
   *s_off = (int)rv.size();
   for (int k = 0; k < count; ++k) {
-    double v = (2 * k == n || n == 1) ? 0.0 : sin(2.0 * M_PI * k / n) * n;
+    const int m = 2 * k <= n ? k : k - n;
+    double v;
+    if (2 * k == n || n == 1) v = 0.0;
+    else v = kind == 1 ? 2.0 * M_PI * m : sin(2.0 * M_PI * k / n) * n;
     rv.push_back(v);
   }
   *l_off = (int)rv.size();
   for (int k = 0; k < count; ++k) {
+    const int m = 2 * k <= n ? k : k - n;
     const double sn = sin(M_PI * k / n);
-    rv.push_back(n == 1 ? 0.0 : 4.0 * sn * sn * n * n);
+    double l = 0.0;
+    if (n != 1) l = kind == 1 ? (2.0 * M_PI * m) * (2.0 * M_PI * m) : 4.0 * sn * sn * n * n;
+    rv.push_back(l);
   }
 }
 
@@ -127,7 +139,7 @@ static hipError_t upload(const std::vector<double>& v, void** dst) {
   return e;
 }
 
-static acm_status get_plan(const acm_grid* grid, int precision, CellPlan** out) {
+static acm_status get_plan(const acm_grid* grid, int precision, CellPlan** out, int deriv = 0) {
   Geom g;
   std::string why;
   if (!make_geom(grid, &g, &why)) return fail(ACM_E_INVALID, why);
@@ -139,7 +151,8 @@ static acm_status get_plan(const acm_grid* grid, int precision, CellPlan** out) 
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_mu);
-  auto key = std::make_tuple(dev, precision, g.dim, g.nx, g.ny, g.nz);
+  if (deriv != 0 && deriv != 1) return fail(ACM_E_INVALID, "derivative must be 0 or 1");
+  auto key = std::make_tuple(dev, precision, g.dim, g.nx, g.ny, g.nz, deriv);
   auto it = g_plans.find(key);
   if (it != g_plans.end()) {
     *out = it->second.get();
@@ -149,6 +162,7 @@ static acm_status get_plan(const acm_grid* grid, int precision, CellPlan** out) 
   p->g = g;
   p->prec = precision == ACM_FP64 ? 8 : 4;
   p->device = dev;
+  p->deriv = deriv;
   std::vector<double> c, r;
   p->off.tw_x = 0;
   push_twiddles(c, g.nx / 2);
@@ -163,9 +177,9 @@ static acm_status get_plan(const acm_grid* grid, int precision, CellPlan** out) 
     c.push_back(sin(ang));
   }
   p->off.ncomplex = (int)(c.size() / 2);
-  push_symbols(r, g.nx, g.xh, &p->off.sx, &p->off.lx);
-  push_symbols(r, g.ny, g.ny, &p->off.sy, &p->off.ly);
-  push_symbols(r, g.nz, g.nz, &p->off.sz, &p->off.lz);
+  push_symbols(r, g.nx, g.xh, deriv, &p->off.sx, &p->off.lx);
+  push_symbols(r, g.ny, g.ny, deriv, &p->off.sy, &p->off.ly);
+  push_symbols(r, g.nz, g.nz, deriv, &p->off.sz, &p->off.lz);
   p->off.nreal = (int)r.size();
   hipError_t e;
   if (precision == ACM_FP64) {
@@ -889,9 +903,10 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
 
 // Argument checks shared by the single and batched Stokes entry points.
 static acm_status check_stokes_cell(const acm_grid* grid, const uint8_t* H, const double* g_p,
-                                    void* u, int precision, hipStream_t cs, CellPlan** pl) {
+                                    void* u, int precision, int deriv, hipStream_t cs,
+                                    CellPlan** pl) {
   if (!H || !g_p || !u) return fail(ACM_E_INVALID, "H, g_p and u must be non-NULL");
-  acm_status r = get_plan(grid, precision, pl);
+  acm_status r = get_plan(grid, precision, pl, deriv);
   if (r != ACM_OK) return r;
   for (int k = 0; k < grid->dim; ++k)
     if (!isfinite(g_p[k])) return fail(ACM_E_INVALID, "g_p must be finite");
@@ -914,6 +929,9 @@ static acm_status check_penalty_opts(const acm_penalty& P, const acm_opts& O, do
   if (!(nu > 0.0) || !isfinite(nu)) return fail(ACM_E_INVALID, "nu must be positive");
   if (!(O.eps >= 0.0) || O.max_iter < 1) return fail(ACM_E_INVALID, "eps >= 0 and max_iter >= 1 required");
   if (O.pass_mode < 0 || O.pass_mode > 4) return fail(ACM_E_INVALID, "pass_mode must be 0 to 4");
+  if (O.derivative != 0 && O.derivative != 1) return fail(ACM_E_INVALID, "derivative must be 0 or 1");
+  if (O.derivative == 1 && O.warm_start)
+    return fail(ACM_E_INVALID, "the warm start forms its state with central differences: derivative 0");
   if (O.green_variant < 0 || O.green_variant > kGreenVariants)
     return fail(ACM_E_INVALID, "green_variant must be in [0, " + std::to_string(kGreenVariants) + "]");
   for (int k = 0; k < 3; ++k)
@@ -966,8 +984,10 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
 
   // 3D cubes that fit take the slab form of the local pass (no separate y
   // passes; f arrives as d partial spectra)
-  const bool tslab = d == 3 && slab_supported<T>(g) && ((uintptr_t)u % 16 == 0) &&
-                     ((uintptr_t)H % 4 == 0);
+  // (the slab form folds the x and y divergence in as central differences, so
+  // the exact symbols take the row form)
+  const bool tslab = d == 3 && pl->deriv == 0 && slab_supported<T>(g) &&
+                     ((uintptr_t)u % 16 == 0) && ((uintptr_t)H % 4 == 0);
   const size_t cb = sizeof(T) * 2;
   // slab form: a fifth field holds f_z (see k_transport_slab)
   const size_t spec_b = cb * (size_t)g.nspec * (d + (tslab ? 2 : 1));
@@ -1495,7 +1515,7 @@ void acm_default_opts(acm_opts* o) {
 
 const char* acm_last_error(void) { return g_err.c_str(); }
 
-int32_t acm_version(void) { return 3; }
+int32_t acm_version(void) { return 4; }
 
 acm_status acm_stokes_solve(const acm_grid* grid, const uint8_t* H, const double* g_p, double nu,
                             const acm_penalty* pen, const acm_opts* opts, void* u, void* q,
@@ -1510,7 +1530,7 @@ acm_status acm_stokes_solve(const acm_grid* grid, const uint8_t* H, const double
   acm_status r = check_penalty_opts(P, O, nu);
   if (r != ACM_OK) return r;
   CellPlan* pl = nullptr;
-  r = check_stokes_cell(grid, H, g_p, u, O.precision, (hipStream_t)stream, &pl);
+  r = check_stokes_cell(grid, H, g_p, u, O.precision, O.derivative, (hipStream_t)stream, &pl);
   if (r != ACM_OK) return r;
   StokesCellIn c{H, {0, 0, 0}, u, q};
   for (int k = 0; k < grid->dim; ++k) c.g[k] = g_p[k];
@@ -1538,7 +1558,8 @@ acm_status acm_stokes_solve_batched(int32_t ncell, const acm_grid* grids, const 
   std::vector<CellPlan*> plans(ncell);
   std::vector<StokesCellIn> cells(ncell);
   for (int i = 0; i < ncell; ++i) {
-    r = check_stokes_cell(grids + i, H[i], g_p + 3 * i, u[i], O.precision, (hipStream_t)stream,
+    r = check_stokes_cell(grids + i, H[i], g_p + 3 * i, u[i], O.precision, O.derivative,
+                          (hipStream_t)stream,
                           &plans[i]);
     if (r != ACM_OK) return fail(r, "cell " + std::to_string(i) + ": " + g_err);
     cells[i] = StokesCellIn{H[i], {g_p[3 * i], g_p[3 * i + 1], g_p[3 * i + 2]}, u[i], q ? q[i] : nullptr};
@@ -1587,7 +1608,7 @@ acm_status acm_transport_step(const acm_grid* grid, const uint8_t* H, const void
   if (!isfinite(dt) && n_steps != 1) return fail(ACM_E_INVALID, "the steady problem takes n_steps = 1");
   if (!(O.eps >= 0.0) || O.max_iter < 1) return fail(ACM_E_INVALID, "eps >= 0 and max_iter >= 1 required");
   CellPlan* pl = nullptr;
-  acm_status r = get_plan(grid, O.precision, &pl);
+  acm_status r = get_plan(grid, O.precision, &pl, O.derivative);
   if (r != ACM_OK) return r;
   for (int k = 0; k < grid->dim; ++k)
     if (!isfinite(g_chi[k]) || !isfinite(B0[k])) return fail(ACM_E_INVALID, "g_chi, B0 must be finite");

@@ -406,3 +406,66 @@ def test_step4_kernel_rejects_batches():
     with pytest.raises(abi.AcmError) as e:
         acm_stokes_solve_batched(Hs, [(1.0, 0.0, 0.0)] * 2, eps=1e-5, max_iter=100, pass_mode=4)
     assert e.value.status == abi.ACM_E_INVALID
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("shape,pass_mode", [((16, 24), 0), ((16, 32, 32), 1), ((16, 32, 32), 2),
+                                             ((8, 24, 16), 0)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_spectral_symbols_match_oracle(shape, pass_mode, dtype):
+    """derivative = "spectral" (exact i k and |k|^2 symbols): the iterates of
+    every pass structure equal the oracle's with the same symbols."""
+    require_gpu()
+    print(f"spectral symbols shape={shape} mode={pass_mode} dtype={dtype}", flush=True)
+    H = I.random_mask(shape, 23, 0.35)
+    d = len(shape)
+    g = (1.0, -0.4, 0.3)[:d]
+    M = 40
+    r = _solve(H, g, dtype=dtype, penalty=dict(alpha=30.0, beta=50.0, b=20.0, adaptive=0),
+               eps=0.0, max_iter=M, pass_mode=pass_mode, derivative="spectral")
+    o = O.stokes_admm(H, g, alpha=30.0, beta=50.0, b=20.0, adaptive=False, eps=0.0, max_iter=M,
+                      derivative="spectral")
+    oc = O.stokes_admm(H, g, alpha=30.0, beta=50.0, b=20.0, adaptive=False, eps=0.0, max_iter=M)
+    tol = 1e-11 if dtype == torch.float64 else 2e-5
+    u = host(r["u"])
+    scale = np.abs(o["u"]).max()
+    assert np.abs(u - o["u"]).max() < tol * scale
+    assert np.abs(host(r["q"]) - o["q"]).max() < tol * 10 * np.abs(o["q"]).max()
+    # and the symbols matter: the central-difference iterates are elsewhere
+    assert np.abs(o["u"] - oc["u"]).max() > 100 * tol * scale
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("shape", [(16, 16), (16, 32, 32)])
+def test_spectral_symbols_transport_matches_oracle(shape):
+    """Transport with the exact symbols (3D cubes take the row form) equals
+    the oracle's LS iterates: steady cell problem in FP64, flow from the
+    spectral Stokes solve."""
+    require_gpu()
+    from paper_2312_15554_amd.api import acm_transport_step
+    print(f"spectral transport {shape}", flush=True)
+    H = I.random_mask(shape, 29, 0.3)
+    d = len(shape)
+    g = (1.0, 0.0, 0.0)[:d]
+    o = O.stokes_admm(H, g, eps=1e-8, derivative="spectral")
+    u = o["u"] / np.abs(o["u"]).max()
+    kw = dict(A0=1.2, B0=[0.5, 0.1, 0.0][:d], eta=0.01, eps=0.0, max_iter=30)
+    ot = O.transport_ls(H, u, (0.0, 1.0, 0.0)[:d], 2.0, derivative="spectral", **kw)
+    r = acm_transport_step(dev(H), dev(u, torch.float64), (0.0, 1.0, 0.0)[:d], 2.0,
+                           derivative="spectral", **kw)
+    chi = host(r["chi"])
+    assert np.abs(chi - ot["chi"]).max() < 1e-10 * np.abs(ot["chi"]).max()
+
+
+@pytest.mark.gpu
+def test_spectral_symbols_reject_warm_start():
+    """The warm start forms its state with central differences: refused with
+    the exact symbols."""
+    require_gpu()
+    from paper_2312_15554_amd import abi
+    H = dev(I.random_mask((16, 16), 3, 0.3))
+    u0 = torch.zeros((2, 16, 16), dtype=torch.float32, device=H.device)
+    with pytest.raises(abi.AcmError) as e:
+        _solve_dev(H, (1.0, 0.0), u=u0, warm_start=True, want_q=False, derivative="spectral",
+                   max_iter=10)
+    assert e.value.status == abi.ACM_E_INVALID
