@@ -151,7 +151,7 @@ void acm_default_opts(acm_opts* o);
  * the next call on the same thread. */
 const char* acm_last_error(void);
 
-/* ABI version (incremented on any signature or struct change): 3. */
+/* ABI version (incremented on any signature or struct change): 4. */
 int32_t acm_version(void);
 
 /*

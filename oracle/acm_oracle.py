@@ -225,6 +225,7 @@ def stokes_admm(H, g, nu=1.0, alpha=None, beta=None, b=None,
     hist = []
     it = 0
     rp = rd = tp = td = [np.nan] * 3
+    rsum_min = math.inf
     for it in range(1, max_iter + 1):
         al, be, bb = psi
         # Step 1: stationarity in u (eq. step1por solved in Fourier, eq. FFT step1)
@@ -256,7 +257,11 @@ def stokes_admm(H, g, nu=1.0, alpha=None, beta=None, b=None,
         u, ut, q, a, lam, divu = u_new, ut_new, q_new, a_new, lam_new, divu_new
         if history:
             hist.append(dict(rp=list(rp), rd=list(rd), tp=list(tp), td=list(td), psi=list(psi)))
-        if not all(np.isfinite(rp + rd)):
+        # divergence: a non-finite residual, or the sum of the six grown a
+        # millionfold over its smallest value so far
+        rsum = sum(rp) + sum(rd)
+        rsum_min = min(rsum_min, rsum)
+        if not all(np.isfinite(rp + rd)) or (it > 5 and rsum > 1e6 * rsum_min):
             status = "diverged"
             break
         if all(rp[k] <= tp[k] and rd[k] <= td[k] for k in range(3)):
@@ -330,6 +335,7 @@ def transport_ls(H, u, g, Pe, A0=0.55, B0=None, eta=0.01, diffusivity=1.0,
         chi_m_hat = chi_hat.copy()
         st = "not_converged"
         it = 0
+        r1_min = math.inf
         for it in range(1, max_iter + 1):
             # Step 1: residual F^n in real space
             e = grad + gvec.reshape((d,) + (1,) * d)
@@ -349,7 +355,11 @@ def transport_ls(H, u, g, Pe, A0=0.55, B0=None, eta=0.01, diffusivity=1.0,
             chi, chi_hat, grad = chi_new, chi_hat_new, grad_new
             if history:
                 hist.append((r1, r2))
-            if not (np.isfinite(r1) and np.isfinite(r2)):
+            # divergence (the LS iteration contracts only for a large enough
+            # comparison medium): non-finite, or r_1 grown a millionfold over
+            # its smallest value within this time step
+            r1_min = min(r1_min, r1)
+            if not (np.isfinite(r1) and np.isfinite(r2)) or (it > 5 and r1 > 1e6 * r1_min):
                 st = "diverged"
                 break
             if r1 <= sqn1 * eps and r2 <= sqn2 * eps:

@@ -41,6 +41,7 @@ struct StokesState {
   double psi[3];      // alpha, beta, b of the iteration that reads this slot
   double c_prev;      // b/(b+alpha) of the iteration before it
   double rp[3], rd[3], tp[3], td[3], mu[3];  // residuals of the iteration that wrote it
+  double s_min;       // smallest sum of the six residuals so far (divergence test)
   int64_t iter;       // iterations completed
   int32_t done;       // sticky: once set in either slot every pass exits at once
   int32_t status;     // 0 ok, 1 not converged, -5 diverged

@@ -555,6 +555,7 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
       c.g[k] = k < d ? cells[i].g[k] : 0.0;
     }
     s0.c_prev = 0.0;
+    s0.s_min = INFINITY;
     s0.iter = 0;
     s0.done = 0;
     s0.status = 1;
@@ -897,14 +898,15 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
         st->kernel_calls[k] = prof.calls[k];
       }
   }
-  if (worst == -5) return fail(ACM_E_DIVERGED, "a residual became non-finite");
+  if (worst == -5)
+    return fail(ACM_E_DIVERGED, "a residual became non-finite or grew a millionfold over its minimum");
   return worst == 0 ? ACM_OK : ACM_NOT_CONVERGED;
 }
 
 // Argument checks shared by the single and batched Stokes entry points.
 static acm_status check_stokes_cell(const acm_grid* grid, const uint8_t* H, const double* g_p,
                                     void* u, int precision, int deriv, hipStream_t cs,
-                                    CellPlan** pl) {
+                                    CellPlan** pl, bool* all_solid) {
   if (!H || !g_p || !u) return fail(ACM_E_INVALID, "H, g_p and u must be non-NULL");
   acm_status r = get_plan(grid, precision, pl, deriv);
   if (r != ACM_OK) return r;
@@ -916,12 +918,30 @@ static acm_status check_stokes_cell(const acm_grid* grid, const uint8_t* H, cons
   hipError_t e = hipMemcpyAsync(hh.data(), H, hh.size(), hipMemcpyDeviceToHost, cs);
   if (e == hipSuccess) e = hipStreamSynchronize(cs);
   if (e != hipSuccess) return fail(ACM_E_HIP, std::string("reading H: ") + hipGetErrorString(e));
-  bool any = false;
+  bool any = false, all = true;
   for (uint8_t v : hh) {
     if (v > 1) return fail(ACM_E_INVALID, "H must hold 0 or 1");
     any |= v == 1;
+    all &= v == 1;
   }
   if (!any) return fail(ACM_E_INVALID, "H has no solid voxel: no steady flow under a body force");
+  *all_solid = all;
+  return ACM_OK;
+}
+
+// An all-solid cell: the flow is zero (u = 0 in the solid) and so is the
+// multiplier q; no iteration runs.
+static acm_status stokes_all_solid(const CellPlan* pl, void* u, void* q, acm_stats* st,
+                                   hipStream_t cs) {
+  const Geom& g = pl->g;
+  HIP_TRY(hipMemsetAsync(u, 0, (size_t)pl->prec * g.dim * (size_t)g.ntot, cs));
+  if (q) HIP_TRY(hipMemsetAsync(q, 0, (size_t)pl->prec * (size_t)g.ntot, cs));
+  HIP_TRY(hipStreamSynchronize(cs));
+  if (st) {
+    memset(st, 0, sizeof(*st));
+    st->converged = 1;
+    st->status = 0;
+  }
   return ACM_OK;
 }
 
@@ -1530,8 +1550,11 @@ acm_status acm_stokes_solve(const acm_grid* grid, const uint8_t* H, const double
   acm_status r = check_penalty_opts(P, O, nu);
   if (r != ACM_OK) return r;
   CellPlan* pl = nullptr;
-  r = check_stokes_cell(grid, H, g_p, u, O.precision, O.derivative, (hipStream_t)stream, &pl);
+  bool solid = false;
+  r = check_stokes_cell(grid, H, g_p, u, O.precision, O.derivative, (hipStream_t)stream, &pl,
+                        &solid);
   if (r != ACM_OK) return r;
+  if (solid) return stokes_all_solid(pl, u, q, stats, (hipStream_t)stream);
   StokesCellIn c{H, {0, 0, 0}, u, q};
   for (int k = 0; k < grid->dim; ++k) c.g[k] = g_p[k];
   std::vector<CellPlan*> plans{pl};
@@ -1555,18 +1578,42 @@ acm_status acm_stokes_solve_batched(int32_t ncell, const acm_grid* grids, const 
   if (opts) O = *opts;
   acm_status r = check_penalty_opts(P, O, nu);
   if (r != ACM_OK) return r;
-  std::vector<CellPlan*> plans(ncell);
-  std::vector<StokesCellIn> cells(ncell);
+  // all-solid cells are answered at once (u = 0, q = 0); the others run
+  std::vector<CellPlan*> plans;
+  std::vector<StokesCellIn> cells;
+  std::vector<int> active;
+  std::vector<CellPlan*> solid_plan(ncell, nullptr);
   for (int i = 0; i < ncell; ++i) {
+    CellPlan* pl = nullptr;
+    bool solid = false;
     r = check_stokes_cell(grids + i, H[i], g_p + 3 * i, u[i], O.precision, O.derivative,
-                          (hipStream_t)stream,
-                          &plans[i]);
+                          (hipStream_t)stream, &pl, &solid);
     if (r != ACM_OK) return fail(r, "cell " + std::to_string(i) + ": " + g_err);
-    cells[i] = StokesCellIn{H[i], {g_p[3 * i], g_p[3 * i + 1], g_p[3 * i + 2]}, u[i], q ? q[i] : nullptr};
+    if (solid) {
+      solid_plan[i] = pl;
+      continue;
+    }
+    active.push_back(i);
+    plans.push_back(pl);
+    cells.push_back(StokesCellIn{H[i], {g_p[3 * i], g_p[3 * i + 1], g_p[3 * i + 2]}, u[i],
+                                 q ? q[i] : nullptr});
   }
-  if (O.precision == ACM_FP64)
-    return stokes_run<double>(plans, cells, nu, P, O, stats, nullptr, (hipStream_t)stream);
-  return stokes_run<float>(plans, cells, nu, P, O, stats, nullptr, (hipStream_t)stream);
+  for (int i = 0; i < ncell; ++i)
+    if (solid_plan[i]) {
+      r = stokes_all_solid(solid_plan[i], u[i], q ? q[i] : nullptr, stats ? stats + i : nullptr,
+                           (hipStream_t)stream);
+      if (r != ACM_OK) return r;
+    }
+  if (active.empty()) return ACM_OK;
+  std::vector<acm_stats> st(active.size());
+  r = O.precision == ACM_FP64
+          ? stokes_run<double>(plans, cells, nu, P, O, stats ? st.data() : nullptr, nullptr,
+                               (hipStream_t)stream)
+          : stokes_run<float>(plans, cells, nu, P, O, stats ? st.data() : nullptr, nullptr,
+                              (hipStream_t)stream);
+  if (stats && r >= 0)
+    for (size_t k = 0; k < active.size(); ++k) stats[active[k]] = st[k];
+  return r;
 }
 
 acm_status acm_fft_r2c(const acm_grid* grid, int32_t precision, int32_t nfields, const void* in,
@@ -1645,7 +1692,6 @@ acm_status acm_effective_props(const acm_grid* grid, int32_t precision, const ui
   return props_impl<float>(pl, H, n_flow, u, n_chi, chi, u_transport, nu, Pe, K, D, mass,
                            (hipStream_t)stream);
 }
-
 
 int64_t acm_fno_param_count(const acm_fno_shape* shape) {
   FnoLayout f;

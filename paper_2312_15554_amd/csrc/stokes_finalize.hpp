@@ -97,6 +97,11 @@ __device__ __forceinline__ void stokes_step4(const StokesCtl* __restrict__ ctl,
   nx.c_prev = cc;
   nx.done = 0;
   nx.status = 1;
+  // divergence: a non-finite residual, or the sum of the six grown a
+  // millionfold over its smallest value so far
+  const double rsum = rp[0] + rp[1] + rp[2] + rd[0] + rd[1] + rd[2];
+  nx.s_min = fmin(cur.s_min, rsum);
+  if (nx.iter > 5 && rsum > 1e6 * nx.s_min) finite = false;
   if (!finite) {
     nx.done = 1;
     nx.status = -5;

@@ -7,7 +7,10 @@ from paper_2312_15554_amd import inputs as I
 from tests.gpu_common import dev, host, require_gpu
 
 SHAPES = [(8, 8), (16, 24), (64, 64), (48, 96), (8, 16, 24), (16, 16, 16), (32, 48, 64),
-          (24, 32, 16), (128, 128, 128)]
+          (24, 32, 16), (128, 128, 128),
+          # 256- and 512-long axes along x (rows), y and z (columns)
+          (8, 16, 256), (256, 8, 16), (16, 256, 8), (256, 256), (8, 8, 512), (512, 8, 8),
+          (192, 16, 16)]
 
 
 @pytest.mark.gpu

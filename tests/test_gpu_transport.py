@@ -24,14 +24,16 @@ def _flow(H, g):
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("shape", [(16, 16), (16, 24, 32), (16, 16, 16), (16, 32, 32), (8, 48, 48),
-                                   (8, 96, 96)])
+                                   (16, 64, 64), (8, 96, 96), (16, 128, 128), (8, 16, 256),
+                                   (256, 8, 8)])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("dt", [math.inf, 5e-3])
 def test_ls_iterates_match_oracle(shape, dtype, dt):
     """Fixed iteration count (eps = 0): chi of the HIP path equals the
     oracle's after the same LS iterations (eq. iter / eq. fft_solute).  Cubes
-    in x-y with nx = ny in {32, 48, 96} take the slab form of the local pass,
-    the others the row form with separate y passes."""
+    in x-y with nx = ny in {32, 48, 64, 96, 128} take the slab form of the
+    local pass (128 is the width of the timed cell), the others the row form
+    with separate y passes."""
     require_gpu()
     from paper_2312_15554_amd.api import acm_transport_step
     print(f"LS parity shape={shape} dtype={dtype} dt={dt}", flush=True)
@@ -158,3 +160,41 @@ def test_exact_symbols_ring_where_central_symbols_do_not():
         ring[kind] = float(np.abs(gf - nb)[inner].mean())
     print(f"  mean ringing: {ring}", flush=True)
     assert ring["spectral"] > 5.0 * ring["central"]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("shape", [(32, 32, 32), (16, 24, 32)])
+def test_ls_divergence_is_reported(shape):
+    """A comparison medium far below the largest diffusivity (A0 = 0.2 against
+    A = 1 in the pore): the LS iteration grows, and the solve stops with
+    ACM_E_DIVERGED once r_1 has grown a millionfold (Section 3.2: the
+    iteration contracts only for a large enough A0).  The oracle diverges on
+    the same cell."""
+    require_gpu()
+    from paper_2312_15554_amd import abi
+    from paper_2312_15554_amd.api import acm_transport_step
+    H = I.random_mask(shape, 13, 0.3)
+    u = np.zeros((3,) + shape)
+    o = O.transport_ls(H, u, (1.0, 0.0, 0.0), 0.0, A0=0.2, eta=0.01, eps=1e-6, max_iter=3000)
+    assert o["status"] == "diverged"
+    with pytest.raises(abi.AcmError) as e:
+        acm_transport_step(dev(H), dev(u, torch.float32), (1.0, 0.0, 0.0), 0.0, A0=0.2,
+                           B0=(0.0, 0.0, 0.0), eta=0.01, eps=1e-6, max_iter=3000)
+    assert e.value.status == abi.ACM_E_DIVERGED
+
+
+@pytest.mark.gpu
+def test_nan_flow_reports_divergence():
+    """A NaN in the advecting flow makes r_1 NaN at once: ACM_E_DIVERGED."""
+    require_gpu()
+    from paper_2312_15554_amd import abi
+    from paper_2312_15554_amd.api import acm_transport_step
+    shape = (32, 32, 32)
+    H = I.random_mask(shape, 17, 0.3)
+    u = np.zeros((3,) + shape)
+    pz, py, px = np.argwhere(H == 0)[0]
+    u[0, pz, py, px] = np.nan
+    with pytest.raises(abi.AcmError) as e:
+        acm_transport_step(dev(H), dev(u, torch.float32), (1.0, 0.0, 0.0), 5.0, A0=0.55,
+                           B0=(1.0, 0.0, 0.0), eta=0.01, eps=1e-6, max_iter=3000)
+    assert e.value.status == abi.ACM_E_DIVERGED
