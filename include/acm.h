@@ -234,6 +234,26 @@ acm_status acm_effective_props(const acm_grid* grid, int32_t precision, const ui
                                const void* const* chi, const void* u_transport, double nu,
                                double Pe, double* K, double* D, double* mass, void* stream);
 
+/*
+ * acm_effective_props without any allocation, for callers that cannot
+ * allocate memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results and error statuses as
+ * acm_effective_props, bit for bit, with two differences:
+ *   - at most 16 flows and 16 chi fields per call (ACM_E_INVALID beyond);
+ *   - the kernels run on `stream` itself (the caller's stream, NULL = the
+ *     default stream); the call returns after synchronising it.
+ * The FP64 partial sums live in a fixed 36,864-byte device array that the
+ * library holds on every GPU it runs on until the process ends; nothing is
+ * allocated on the host or the device on the success path (the device address
+ * of the array is looked up once per device on the first call).  Calls that
+ * overlap on one GPU share that array and race: serialise them.
+ */
+acm_status acm_effective_props_noalloc(const acm_grid* grid, int32_t precision, const uint8_t* H,
+                                       int32_t n_flow, const void* const* u, int32_t n_chi,
+                                       const void* const* chi, const void* u_transport, double nu,
+                                       double Pe, double* K, double* D, double* mass,
+                                       void* stream);
+
 /* Multi-dimensional real FFT of nfields fields (forward unnormalised /
  * inverse normalised by 1/ntot), half spectra as described above.  These are
  * the transforms every solver pass is built from. */

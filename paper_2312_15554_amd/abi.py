@@ -67,6 +67,10 @@ SIGNATURES = {
                                       C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p), C.c_void_p,
                                       C.c_double, C.c_double, C.POINTER(C.c_double),
                                       C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]),
+    "acm_effective_props_noalloc": (C.c_int, [C.POINTER(acm_grid), C.c_int32, C.c_void_p, C.c_int32,
+                                              C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p),
+                                              C.c_void_p, C.c_double, C.c_double, C.POINTER(C.c_double),
+                                              C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]),
     "acm_fno_param_count": (C.c_int64, [C.POINTER(acm_fno_shape)]),
     "acm_fno_workspace_bytes": (C.c_int64, [C.POINTER(acm_fno_shape), C.POINTER(acm_grid), C.c_int32,
                                             C.c_int32]),

@@ -259,6 +259,18 @@ def acm_effective_props(H: torch.Tensor, us=(), chis=(), u_transport: torch.Tens
                         nu: float = 1.0, Pe: float = 0.0, stream=None) -> dict:
     """Effective permeability rows K[i] (flow i) and diffusivity columns D[:, j]
     (chi j) with solute masses (acm_effective_props)."""
+    return _props("acm_effective_props", H, us, chis, u_transport, nu, Pe, stream)
+
+
+def acm_effective_props_noalloc(H: torch.Tensor, us=(), chis=(), u_transport: torch.Tensor | None = None,
+                                nu: float = 1.0, Pe: float = 0.0, stream=None) -> dict:
+    """The same as acm_effective_props through the allocation-free entry point
+    (acm_effective_props_noalloc): partial sums in the library's fixed device
+    array, kernels on the caller's stream."""
+    return _props("acm_effective_props_noalloc", H, us, chis, u_transport, nu, Pe, stream)
+
+
+def _props(entry, H, us, chis, u_transport, nu, Pe, stream) -> dict:
     import numpy as np
     lib = abi.load()
     shape = tuple(H.shape)
@@ -281,10 +293,10 @@ def acm_effective_props(H: torch.Tensor, us=(), chis=(), u_transport: torch.Tens
     D = (C.c_double * max(d * nc, 1))()
     mass = (C.c_double * max(nc, 1))()
     gr = _grid(shape)
-    abi.check(lib.acm_effective_props(C.byref(gr), prec, _dev(H, "H"), nf, up, nc, cp,
-                                      _dev(u_transport, "u_transport") if u_transport is not None else None,
-                                      float(nu), float(Pe), K if nf else None, D if nc else None,
-                                      mass if nc else None, _stream(stream)))
+    abi.check(getattr(lib, entry)(C.byref(gr), prec, _dev(H, "H"), nf, up, nc, cp,
+                                  _dev(u_transport, "u_transport") if u_transport is not None else None,
+                                  float(nu), float(Pe), K if nf else None, D if nc else None,
+                                  mass if nc else None, _stream(stream)))
     return dict(K=np.array(K[: nf * d]).reshape(nf, d) if nf else None,
                 D=np.array(D[: d * nc]).reshape(d, nc) if nc else None,
                 mass=np.array(mass[:nc]) if nc else None)

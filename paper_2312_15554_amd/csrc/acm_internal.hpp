@@ -285,6 +285,13 @@ template <typename T>
 hipError_t launch_chi_sums(const Geom& g, const T* chi, const T* u, const uint8_t* H,
                            double* part, int* nsums, hipStream_t s);
 int reduction_blocks(const Geom& g);
+// Upper bound of reduction_blocks() over every grid.
+constexpr int kReductionBlocksMax = 512;
+// Largest number of partial sums per block record (k_chi_sums in 3D: 8).
+constexpr int kReductionSumsMax = 8;
+// out[k] = sum over b in [0, nb) of part[b * ns + k], added in block order from
+// 0.0 (one workgroup); ns <= 64.
+hipError_t launch_sum_partials(const double* part, int nb, int ns, double* out, hipStream_t s);
 
 // Warm start: a = H (g - grad q + nu Delta_h u0), div = div_c u0 (real, in
 // `div`), then u <- (1-H) u in place.  q may be null (q0 = 0).

@@ -6,7 +6,7 @@
 
 namespace acm {
 
-constexpr int kRedBlocks = 512;
+constexpr int kRedBlocks = kReductionBlocksMax;
 constexpr int kRedThreads = 256;
 
 // sums[0] = sum_pore 1, sums[1+c] = sum_pore u_c, sums[1+d+c] = sum_Y u_c
@@ -183,6 +183,25 @@ hipError_t launch_warm_init(const Geom& g, const T* u, const T* q, const uint8_t
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_mask_pore<T>), dim3(nb), dim3(256), 0, s, const_cast<T*>(u), H, g.dim, g.ntot);
+  return hipGetLastError();
+}
+
+// Totals of nb per-block records of ns partial sums: record b is added to the
+// running sum in block order, starting from 0.0 -- the additions the host makes
+// when it adds the copied partials, in the same order, so the totals are the
+// same bits either way.
+__global__ __launch_bounds__(64) void k_sum_partials(const double* __restrict__ part, int nb,
+                                                     int ns, double* __restrict__ out) {
+  const int k = threadIdx.x;
+  if (k >= ns) return;
+  double acc = 0.0;
+  for (int b = 0; b < nb; ++b) acc += part[(int64_t)b * ns + k];
+  out[k] = acc;
+}
+
+hipError_t launch_sum_partials(const double* part, int nb, int ns, double* out, hipStream_t s) {
+  if (ns < 1 || ns > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, part, nb, ns, out);
   return hipGetLastError();
 }
 

@@ -58,7 +58,7 @@ struct CellPlan {
 static std::mutex g_mu;
 static std::map<std::tuple<int, int, int, int, int, int, int>, std::unique_ptr<CellPlan>> g_plans;
 
-static bool make_geom(const acm_grid* grid, Geom* g, std::string* why) {
+static bool make_geom(const acm_grid* grid, Geom* g, const char** why) {
   if (!grid) {
     *why = "grid is NULL";
     return false;
@@ -83,6 +83,9 @@ static bool make_geom(const acm_grid* grid, Geom* g, std::string* why) {
   g->plane = g->dim == 3 ? (int64_t)g->ny * g->xh : g->xh;
   return true;
 }
+
+static const char* const kUnsupportedSizeMsg =
+    "grid lengths must be in {8,16,24,32,48,64,96,128,192,256,512} (nx <= 512)";
 
 static bool size_supported(const Geom& g) {
   auto ok = [](int n) { return fft_length_supported(n); };
@@ -141,11 +144,9 @@ static hipError_t upload(const std::vector<double>& v, void** dst) {
 
 static acm_status get_plan(const acm_grid* grid, int precision, CellPlan** out, int deriv = 0) {
   Geom g;
-  std::string why;
+  const char* why = nullptr;
   if (!make_geom(grid, &g, &why)) return fail(ACM_E_INVALID, why);
-  if (!size_supported(g))
-    return fail(ACM_E_UNSUPPORTED_SIZE,
-                "grid lengths must be in {8,16,24,32,48,64,96,128,192,256,512} (nx <= 512)");
+  if (!size_supported(g)) return fail(ACM_E_UNSUPPORTED_SIZE, kUnsupportedSizeMsg);
   if (precision != ACM_FP32 && precision != ACM_FP64)
     return fail(ACM_E_INVALID, "precision must be ACM_FP32 or ACM_FP64");
   int dev = 0;
@@ -1218,42 +1219,27 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
 }
 
 // --------------------------------------------------------------- properties
-template <typename T>
-static acm_status props_impl(CellPlan* pl, const uint8_t* H, int n_flow, const void* const* u,
-                             int n_chi, const void* const* chi, const void* u_tr, double nu,
-                             double Pe, double* K, double* D, double* mass, hipStream_t caller) {
-  const Geom& g = pl->g;
+// eq. K and eq. D from the FP64 totals of the reductions:
+//   flow[i] = k_flow_sums totals of flow i (for K),
+//   tr      = k_flow_sums totals of u_transport (pore volume and pore sums of u),
+//   chi[j]  = k_chi_sums totals of chi^j.
+// Host arithmetic only; both properties entry points call it.
+static acm_status props_from_totals(const Geom& g, int n_flow, const double* const* flow,
+                                    const double* tr, int n_chi, const double* const* chi,
+                                    double nu, double Pe, double* K, double* D, double* mass) {
   const int d = g.dim;
-  hipStream_t s = work_stream(pl->device);
-  if (!s) return fail(ACM_E_HIP, "cannot create work stream");
-  HIP_TRY(join_from(caller, s));
   const double N = (double)g.ntot;
-  std::vector<double> fs;
-  if (K) {
-    for (int i = 0; i < n_flow; ++i) {
-      acm_status r = reduce_on_host(g, s, &fs, [&](double* part, int* ns) {
-        return launch_flow_sums<T>(g, (const T*)u[i], H, part, ns, s);
-      });
-      if (r != ACM_OK) return r;
-      for (int j = 0; j < d; ++j) K[i * d + j] = fs[1 + d + j] / (N * nu);
-    }
-  }
+  if (K)
+    for (int i = 0; i < n_flow; ++i)
+      for (int j = 0; j < d; ++j) K[i * d + j] = flow[i][1 + d + j] / (N * nu);
   if (n_chi > 0 && (D || mass)) {
-    acm_status r = reduce_on_host(g, s, &fs, [&](double* part, int* ns) {
-      return launch_flow_sums<T>(g, (const T*)u_tr, H, part, ns, s);
-    });
-    if (r != ACM_OK) return r;
-    const double npore = fs[0];
+    const double npore = tr[0];
     if (!(npore > 0.0)) return fail(ACM_E_INVALID, "H has no pore voxel");
-    std::vector<double> ubar(d);
-    for (int c = 0; c < d; ++c) ubar[c] = fs[1 + c] / npore;
+    double ubar[3] = {0.0, 0.0, 0.0};
+    for (int c = 0; c < d; ++c) ubar[c] = tr[1 + c] / npore;
     const double por = npore / N;
     for (int j = 0; j < n_chi; ++j) {
-      std::vector<double> cs;
-      r = reduce_on_host(g, s, &cs, [&](double* part, int* ns) {
-        return launch_chi_sums<T>(g, (const T*)chi[j], (const T*)u_tr, H, part, ns, s);
-      });
-      if (r != ACM_OK) return r;
+      const double* cs = chi[j];
       if (mass) mass[j] = cs[0] / N;
       if (D)
         for (int i = 0; i < d; ++i)
@@ -1261,8 +1247,121 @@ static acm_status props_impl(CellPlan* pl, const uint8_t* H, int n_flow, const v
                              cs[2 + d + i] / N;
     }
   }
-  HIP_TRY(hipStreamSynchronize(s));
   return ACM_OK;
+}
+
+template <typename T>
+static acm_status props_impl(CellPlan* pl, const uint8_t* H, int n_flow, const void* const* u,
+                             int n_chi, const void* const* chi, const void* u_tr, double nu,
+                             double Pe, double* K, double* D, double* mass, hipStream_t caller) {
+  const Geom& g = pl->g;
+  hipStream_t s = work_stream(pl->device);
+  if (!s) return fail(ACM_E_HIP, "cannot create work stream");
+  HIP_TRY(join_from(caller, s));
+  std::vector<std::vector<double>> fl(K ? n_flow : 0), cs;
+  std::vector<double> tr;
+  for (size_t i = 0; i < fl.size(); ++i) {
+    acm_status r = reduce_on_host(g, s, &fl[i], [&](double* part, int* ns) {
+      return launch_flow_sums<T>(g, (const T*)u[i], H, part, ns, s);
+    });
+    if (r != ACM_OK) return r;
+  }
+  const bool want_chi = n_chi > 0 && (D || mass);
+  if (want_chi) {
+    acm_status r = reduce_on_host(g, s, &tr, [&](double* part, int* ns) {
+      return launch_flow_sums<T>(g, (const T*)u_tr, H, part, ns, s);
+    });
+    if (r != ACM_OK) return r;
+    cs.resize(n_chi);
+    for (int j = 0; j < n_chi; ++j) {
+      r = reduce_on_host(g, s, &cs[j], [&](double* part, int* ns) {
+        return launch_chi_sums<T>(g, (const T*)chi[j], (const T*)u_tr, H, part, ns, s);
+      });
+      if (r != ACM_OK) return r;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  std::vector<const double*> flp, csp;
+  for (auto& v : fl) flp.push_back(v.data());
+  for (auto& v : cs) csp.push_back(v.data());
+  return props_from_totals(g, (int)fl.size(), flp.data(), tr.data(), want_chi ? n_chi : 0,
+                           csp.data(), nu, Pe, K, D, mass);
+}
+
+// ------------------------------------------------- allocation-free properties
+// acm_effective_props_noalloc keeps its partial sums in this file-scope array,
+// which every GPU holds for the life of the process:
+//   [0, kNaPart)               per-block records of the reduction in flight
+//                              (every reduction of a call reuses them, in
+//                              stream order);
+//   [kNaPart, kNaPart + kNaTot) one record of totals per reduction.
+// Every kernel writes all of the records it owns before they are read, so
+// nothing needs clearing between calls.  Calls that overlap on one GPU share
+// the array and race.
+constexpr int kNaMaxReductions = 33;  // n_flow <= 16, plus u_transport and n_chi <= 16
+constexpr int kNaPart = kReductionBlocksMax * kReductionSumsMax;
+constexpr int kNaTot = kNaMaxReductions * kReductionSumsMax;
+constexpr int kNaMaxDevices = 64;
+static __device__ __align__(256) double scratch[kNaPart + kNaTot];
+
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kNaMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (the name itself is a host-side stand-in, not a device address).
+static acm_status scratch_address(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(ACM_E_HIP, hipGetErrorString(e));
+  if (dev < 0 || dev >= kNaMaxDevices)
+    return fail(ACM_E_INVALID, "device index above the allocation-free table (64 devices)");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(ACM_E_HIP, "hipGetSymbolAddress(scratch) failed");
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return ACM_OK;
+}
+
+template <typename T>
+static acm_status props_noalloc_impl(const Geom& g, double* sc, const uint8_t* H, int n_flow,
+                                     const void* const* u, int n_chi, const void* const* chi,
+                                     const void* u_tr, double nu, double Pe, double* K, double* D,
+                                     double* mass, hipStream_t s) {
+  double* part = sc;
+  double* tot = sc + kNaPart;
+  const int nb = reduction_blocks(g);
+  const int nf = K ? n_flow : 0;
+  const int nc = (n_chi > 0 && (D || mass)) ? n_chi : 0;
+  const int nred = nf + (nc > 0 ? 1 + nc : 0);
+  int ns = 0;
+  hipError_t e = hipSuccess;
+  for (int r = 0; r < nred && e == hipSuccess; ++r) {
+    if (r < nf)
+      e = launch_flow_sums<T>(g, (const T*)u[r], H, part, &ns, s);
+    else if (r == nf)
+      e = launch_flow_sums<T>(g, (const T*)u_tr, H, part, &ns, s);
+    else
+      e = launch_chi_sums<T>(g, (const T*)chi[r - nf - 1], (const T*)u_tr, H, part, &ns, s);
+    if (e == hipSuccess) e = launch_sum_partials(part, nb, ns, tot + r * kReductionSumsMax, s);
+  }
+  if (e != hipSuccess) return fail(ACM_E_HIP, hipGetErrorString(e));
+  double host[kNaTot];
+  if (nred > 0) {
+    e = hipMemcpyAsync(host, tot, sizeof(double) * kReductionSumsMax * nred,
+                       hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(ACM_E_HIP, hipGetErrorString(e));
+  }
+  const double* flp[16];
+  const double* csp[16];
+  for (int i = 0; i < nf; ++i) flp[i] = host + i * kReductionSumsMax;
+  for (int j = 0; j < nc; ++j) csp[j] = host + (nf + 1 + j) * kReductionSumsMax;
+  return props_from_totals(g, nf, flp, host + nf * kReductionSumsMax, nc, csp, nu, Pe, K, D,
+                           mass);
 }
 
 // --------------------------------------------------------------------- FFT
@@ -1691,6 +1790,41 @@ acm_status acm_effective_props(const acm_grid* grid, int32_t precision, const ui
                               (hipStream_t)stream);
   return props_impl<float>(pl, H, n_flow, u, n_chi, chi, u_transport, nu, Pe, K, D, mass,
                            (hipStream_t)stream);
+}
+
+acm_status acm_effective_props_noalloc(const acm_grid* grid, int32_t precision,
+                                       const uint8_t* H, int32_t n_flow, const void* const* u,
+                                       int32_t n_chi, const void* const* chi,
+                                       const void* u_transport, double nu, double Pe, double* K,
+                                       double* D, double* mass, void* stream) {
+  if (!H) return fail(ACM_E_INVALID, "H must be non-NULL");
+  if (n_flow < 0 || n_chi < 0) return fail(ACM_E_INVALID, "counts must be >= 0");
+  if (n_flow > 16 || n_chi > 16)
+    return fail(ACM_E_INVALID, "allocation-free properties take at most 16 flows and 16 chi fields");
+  if (K && n_flow > 0 && !u) return fail(ACM_E_INVALID, "u must be non-NULL when K is requested");
+  if (n_chi > 0 && (D || mass) && (!chi || !u_transport))
+    return fail(ACM_E_INVALID, "chi and u_transport must be non-NULL when D or mass is requested");
+  if (K && !(nu > 0.0)) return fail(ACM_E_INVALID, "nu must be positive");
+  if (precision != ACM_FP32 && precision != ACM_FP64)
+    return fail(ACM_E_INVALID, "precision must be ACM_FP32 or ACM_FP64");
+  Geom g;
+  const char* why = nullptr;
+  if (!make_geom(grid, &g, &why)) return fail(ACM_E_INVALID, why);
+  if (!size_supported(g)) return fail(ACM_E_UNSUPPORTED_SIZE, kUnsupportedSizeMsg);
+  if (K)
+    for (int i = 0; i < n_flow; ++i)
+      if (!u[i]) return fail(ACM_E_INVALID, "null flow field");
+  if (n_chi > 0 && (D || mass))
+    for (int j = 0; j < n_chi; ++j)
+      if (!chi[j]) return fail(ACM_E_INVALID, "null chi field");
+  double* sc = nullptr;
+  acm_status r = scratch_address(&sc);
+  if (r != ACM_OK) return r;
+  if (precision == ACM_FP64)
+    return props_noalloc_impl<double>(g, sc, H, n_flow, u, n_chi, chi, u_transport, nu, Pe, K, D,
+                                      mass, (hipStream_t)stream);
+  return props_noalloc_impl<float>(g, sc, H, n_flow, u, n_chi, chi, u_transport, nu, Pe, K, D,
+                                   mass, (hipStream_t)stream);
 }
 
 int64_t acm_fno_param_count(const acm_fno_shape* shape) {
