@@ -110,6 +110,18 @@ typedef struct {
                            Stokes warm start needs 0; the transport slab form
                            folds central differences and is replaced by the row
                            form with 1. */
+  int32_t step1_form;   /* Stokes: 0 automatic (2 for FP32 on the fused xy-slab
+                           passes of pass modes 2 and 4, else 1); 1 Step 1 solved
+                           for u from r = b ut - a (the paper's form); 2 increment
+                           form: while b is unchanged the spectra carry the change
+                           X of Step 1's right-hand side since the last solve and
+                           Step 1 is solved for the change of u, which the local
+                           pass adds to u (the same iterates in exact arithmetic;
+                           FP32 transforms then round quantities that vanish at
+                           convergence instead of the O(1) reaction in the solid,
+                           so the residuals keep falling below the FP32 floor of
+                           form 1); an iteration after a change of b is in form 1.
+                           Form 2 needs pass mode 2 or 4 (ACM_E_INVALID otherwise). */
 } acm_opts;
 
 /* Kernel kinds reported in acm_stats.kernel_ms (with opts.profile = 1).  Each
@@ -151,7 +163,7 @@ void acm_default_opts(acm_opts* o);
  * the next call on the same thread. */
 const char* acm_last_error(void);
 
-/* ABI version (incremented on any signature or struct change): 4. */
+/* ABI version (incremented on any signature or struct change): 5. */
 int32_t acm_version(void);
 
 /*

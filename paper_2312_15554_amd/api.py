@@ -114,7 +114,7 @@ def acm_stokes_solve(H: torch.Tensor, g, nu: float = 1.0, *, dtype=torch.float32
                      history_cap: int = 0, u: torch.Tensor | None = None,
                      q: torch.Tensor | None = None, want_q: bool = True, warm_start: bool = False,
                      pass_mode: int = 0, green_variant: int = 0, derivative: str = "central",
-                     stream=None) -> dict:
+                     step1_form: int = 0, stream=None) -> dict:
     """Stokes cell problem by ADMM (acm_stokes_solve).  H: uint8 device tensor
     in numpy order.  Returns dict(u, q, status, stats, history)."""
     lib = abi.load()
@@ -133,7 +133,8 @@ def acm_stokes_solve(H: torch.Tensor, g, nu: float = 1.0, *, dtype=torch.float32
     opts = default_opts(eps=eps, max_iter=max_iter, precision=_prec(dtype), check_every=check_every,
                         use_graph=int(use_graph), profile=int(profile), history_cap=history_cap,
                         warm_start=int(warm_start), pass_mode=int(pass_mode),
-                        green_variant=int(green_variant), derivative=_deriv(derivative))
+                        green_variant=int(green_variant), derivative=_deriv(derivative),
+                        step1_form=int(step1_form))
     st = abi.acm_stats()
     hist = (C.c_double * (max(history_cap, 1) * abi.HIST_DOUBLES))() if history_cap > 0 else None
     gr = _grid(shape)
@@ -155,7 +156,8 @@ def acm_stokes_solve_batched(Hs, gs, nu: float = 1.0, *, dtype=torch.float32,
                              max_iter: int = 1_000_000, check_every: int = 0,
                              use_graph: bool = True, us=None, qs=None, warm_start: bool = False,
                              pass_mode: int = 0, green_variant: int = 0,
-                             derivative: str = "central", stream=None) -> dict:
+                             derivative: str = "central", step1_form: int = 0,
+                             stream=None) -> dict:
     """Many cells in one call (acm_stokes_solve_batched).  Hs: list of uint8
     device tensors (any supported sizes), gs: list of body forces.  Returns
     dict(us, qs, status, stats=[per-cell dicts])."""
@@ -186,7 +188,8 @@ def acm_stokes_solve_batched(Hs, gs, nu: float = 1.0, *, dtype=torch.float32,
     pen = default_penalty(**(penalty or {}))
     opts = default_opts(eps=eps, max_iter=max_iter, precision=_prec(dtype), check_every=check_every,
                         use_graph=int(use_graph), warm_start=int(warm_start), pass_mode=int(pass_mode),
-                        green_variant=int(green_variant), derivative=_deriv(derivative))
+                        green_variant=int(green_variant), derivative=_deriv(derivative),
+                        step1_form=int(step1_form))
     st = (abi.acm_stats * n)()
     status = lib.acm_stokes_solve_batched(n, grids, hp, gp, float(nu), C.byref(pen), C.byref(opts),
                                           up, qp, st, _stream(stream))

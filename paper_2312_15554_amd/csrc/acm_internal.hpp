@@ -45,6 +45,12 @@ struct StokesState {
   int64_t iter;       // iterations completed
   int32_t done;       // sticky: once set in either slot every pass exits at once
   int32_t status;     // 0 ok, 1 not converged, -5 diverged
+  // Step 1 of the iteration that reads this slot is in increment form: the
+  // spectra hold X = rhs^n - M u^n (the change of the right-hand side since
+  // the last solve), the green pass solves M du = X and the local pass adds du
+  // to u.  Otherwise they hold r and Step 1 is solved for u itself.
+  int32_t incr;
+  int32_t pad_;
 };
 
 // Device control block for one ADMM solve: constant parameters written by the
@@ -62,6 +68,10 @@ struct StokesCtl {
   // non-zero (1 + state slot): the Step 4 kernel of pass mode 4 found b
   // changed; every pass after it skips until the host has formed r again
   int32_t hold;
+  // the local passes form X (increment form) for the next Step 1; Step 4 keeps
+  // that form while b is unchanged (a change of b makes the rhs pass form r)
+  int32_t incr_enabled;
+  int32_t pad_;
   StokesState st[2];
   // Words that many workgroups hit at once sit on cache lines of their own,
   // away from the parameters every workgroup reads when it starts.

@@ -70,6 +70,14 @@ __attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
   // same arithmetic (c_prev of the next state is ccd)
   const T rb = (T)bb;
   const T rbc = (T)(bb * ccd);
+  // increment form: this iteration's transforms give the change of u, and the
+  // next Step 1 gets the change of its right-hand side,
+  //   X = b (ut^{n+1} - ut^n) - (a^{n+1} - a^n),
+  // with ut = c u in the solid (c of the iteration that formed it) and the
+  // change of a as stored
+  const bool incr = cur.incr != 0;
+  const bool xform = !FUSED && ctl->incr_enabled != 0;
+  const T rbcp = (T)(bb * cur.c_prev);
   const int z = blockIdx.x, field = blockIdx.y;
 
   const int64_t off = field * ntot + (int64_t)z * S::NV;
@@ -152,9 +160,16 @@ __attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
       hwj = hw[j];
       aoj = ao[j];
     }
-    const V un = lds_ld4<V>(ldsr + y * 2 * S::P2 + x);
+    V un = lds_ld4<V>(ldsr + y * 2 * S::P2 + x);
+    if (incr) {
+      un.x += upj.x;
+      un.y += upj.y;
+      un.z += upj.z;
+      un.w += upj.w;
+    }
     const T unv[4] = {un.x, un.y, un.z, un.w};
     const T upv[4] = {upj.x, upj.y, upj.z, upj.w};
+    T dav[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const double du = (double)unv[e] - (double)upv[e];
@@ -167,6 +182,7 @@ __attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
       for (int e = 0; e < 4; ++e) {
         if ((hwj >> (8 * e)) & 0xffu) {
           const T an = aov[e] + ka * unv[e];
+          dav[e] = an - aov[e];
           aov[e] = an;
           const T dd = cc * unv[e] - cp * upv[e];
           acc[0] += (double)unv[e] * unv[e];
@@ -183,6 +199,13 @@ __attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
     if constexpr (FUSED) {
       ao[j] = aoj;
       hw[j] = hwj;
+    } else if (xform) {
+      V r;
+      r.x = ((hwj & 0xffu) ? rbc * un.x - rbcp * upj.x : rb * (un.x - upj.x)) - dav[0];
+      r.y = ((hwj & 0xff00u) ? rbc * un.y - rbcp * upj.y : rb * (un.y - upj.y)) - dav[1];
+      r.z = ((hwj & 0xff0000u) ? rbc * un.z - rbcp * upj.z : rb * (un.z - upj.z)) - dav[2];
+      r.w = ((hwj & 0xff000000u) ? rbc * un.w - rbcp * upj.w : rb * (un.w - upj.w)) - dav[3];
+      lds_st4(ldsr + y * 2 * S::P2 + x, r);
     } else {
       V r;
       r.x = ((hwj & 0xffu) ? rbc : rb) * un.x - aoj.x;

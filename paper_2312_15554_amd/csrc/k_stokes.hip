@@ -30,6 +30,28 @@ struct GreenGeom {
   int64_t ntot;
 };
 
+// Component c of the right-hand side of Step 1 at one mode (eq. FFT step1):
+//   form 1: r-hat - i s_c q-hat (+ N g_c at k = 0: `g0`);
+//   increment form: X-hat + i beta s_c div-hat, where X is the change of the
+//   real-space part since the last solve and i beta s div-hat = -i s (q-hat -
+//   q-hat_prev) + i (beta - beta_prev) s div-hat is the change of the
+//   pressure term plus the change of beta s s^T applied to the last u-hat.
+// Every green kernel calls this with the same operands, and the fused
+// multiply-adds are explicit, so the kernels round the same way.
+template <typename T>
+__device__ __forceinline__ cplx<T> step1_rhs(cplx<T> r, T s, const cplx<T>& q, const cplx<T>& dp,
+                                             T beta, bool incr, T g0) {
+  if (incr) {
+    const T bs = beta * s;
+    r.x = fma(-bs, dp.y, r.x);
+    r.y = fma(bs, dp.x, r.y);
+  } else {
+    r.x = fma(s, q.y, r.x) + g0;
+    r.y = fma(-s, q.x, r.y);
+  }
+  return r;
+}
+
 template <typename T, int L, int NC, int VAR, int SPL>
 __global__ __launch_bounds__((ColCfg<T, L, NC, VAR, SPL>::NT)) void k_stokes_green(
     StokesCellArgs one, const StokesCellArgs* __restrict__ many, GreenGeom gg, int par,
@@ -51,6 +73,7 @@ __global__ __launch_bounds__((ColCfg<T, L, NC, VAR, SPL>::NT)) void k_stokes_gre
   const T beta = (T)ctl->st[par].psi[1];
   const T bpen = (T)ctl->st[par].psi[2];
   const T nu = (T)ctl->nu;
+  const bool incr = ctl->st[par].incr != 0;
   const int P = gg.plane;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int f0 = tile * C::TX;
@@ -124,14 +147,9 @@ __global__ __launch_bounds__((ColCfg<T, L, NC, VAR, SPL>::NT)) void k_stokes_gre
     cplx<T> R[NC];
     const bool k0 = (kx == 0 && ky == 0 && kz == 0);
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      cplx<T> r = lds[c * PS + e];
-      // - i s_c q
-      r.x += s[c] * q.y;
-      r.y -= s[c] * q.x;
-      if (k0) r.x += (T)((double)gg.ntot * ctl->g[c]);
-      R[c] = r;
-    }
+    for (int c = 0; c < NC; ++c)
+      R[c] = step1_rhs<T>(lds[c * PS + e], s[c], q, dp, beta, incr,
+                          k0 ? (T)((double)gg.ntot * ctl->g[c]) : T(0));
     const T c0 = nu * Lk + bpen;
     cplx<T> sr = cmake<T>(T(0), T(0));
     T ss = T(0);
@@ -150,12 +168,14 @@ __global__ __launch_bounds__((ColCfg<T, L, NC, VAR, SPL>::NT)) void k_stokes_gre
       cplx<T> uc = cmake<T>((R[c].x - s[c] * coef.x) * inv_c0, (R[c].y - s[c] * coef.y) * inv_c0);
       lds[c * PS + e] = cscale(uc, inv_ntot);
     }
-    // div u-hat = i s . u-hat = i (s . R) / den
-    const cplx<T> dl = cmake<T>(-sr.y * inv_den, sr.x * inv_den);
+    // div u-hat = i s . u-hat = i (s . R) / den (its change in increment form)
+    const cplx<T> di = cmake<T>(-sr.y * inv_den, sr.x * inv_den);
+    const cplx<T> dl = incr ? cmake<T>(dp.x + di.x, dp.y + di.y) : di;
     const cplx<T> qn = cmake<T>(q.x - beta * dl.x, q.y - beta * dl.y);
     qhat[mi] = qn;
     dhat[mi] = dl;
-    const double ddx = (double)dl.x - (double)dp.x, ddy = (double)dl.y - (double)dp.y;
+    const double ddx = incr ? (double)di.x : (double)dl.x - (double)dp.x;
+    const double ddy = incr ? (double)di.y : (double)dl.y - (double)dp.y;
     acc[0] += w * ((double)dl.x * dl.x + (double)dl.y * dl.y);
     acc[1] += w * (ddx * ddx + ddy * ddy);
     acc[2] += w * ((double)qn.x * qn.x + (double)qn.y * qn.y);
@@ -322,6 +342,7 @@ __global__ __launch_bounds__((ColCfg<T, L, NC, VAR>::NT)) void k_stokes_green_re
   const T beta = (T)ctl->st[par].psi[1];
   const T bpen = (T)ctl->st[par].psi[2];
   const T nu = (T)ctl->nu;
+  const bool incr = ctl->st[par].incr != 0;
   const int P = gg.plane;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int f0 = tile * C::TX;
@@ -372,13 +393,9 @@ __global__ __launch_bounds__((ColCfg<T, L, NC, VAR>::NT)) void k_stokes_green_re
       const bool k0 = (kx == 0 && ky == 0 && kz == 0);
       cplx<T> R[NC];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        cplx<T> r = v[c][m];
-        r.x += s[c] * q.y;
-        r.y -= s[c] * q.x;
-        if (k0) r.x += (T)((double)gg.ntot * ctl->g[c]);
-        R[c] = r;
-      }
+      for (int c = 0; c < NC; ++c)
+        R[c] = step1_rhs<T>(v[c][m], s[c], q, dp, beta, incr,
+                            k0 ? (T)((double)gg.ntot * ctl->g[c]) : T(0));
       const T c0 = nu * Lk + bpen;
       cplx<T> sr = cmake<T>(T(0), T(0));
       T ss = T(0);
@@ -395,12 +412,14 @@ __global__ __launch_bounds__((ColCfg<T, L, NC, VAR>::NT)) void k_stokes_green_re
       for (int c = 0; c < NC; ++c)
         v[c][m] = cscale(cmake<T>((R[c].x - s[c] * coef.x) * inv_c0, (R[c].y - s[c] * coef.y) * inv_c0),
                          inv_ntot);
-      const cplx<T> dl = cmake<T>(-sr.y * inv_den, sr.x * inv_den);
+      const cplx<T> di = cmake<T>(-sr.y * inv_den, sr.x * inv_den);
+      const cplx<T> dl = incr ? cmake<T>(dp.x + di.x, dp.y + di.y) : di;
       const cplx<T> qn = cmake<T>(q.x - beta * dl.x, q.y - beta * dl.y);
       const int64_t mi = (int64_t)i * P + f;
       qhat[mi] = qn;
       dhat[mi] = dl;
-      const double ddx = (double)dl.x - (double)dp.x, ddy = (double)dl.y - (double)dp.y;
+      const double ddx = incr ? (double)di.x : (double)dl.x - (double)dp.x;
+      const double ddy = incr ? (double)di.y : (double)dl.y - (double)dp.y;
       acc[0] += w * ((double)dl.x * dl.x + (double)dl.y * dl.y);
       acc[1] += w * (ddx * ddx + ddy * ddy);
       acc[2] += w * ((double)qn.x * qn.x + (double)qn.y * qn.y);

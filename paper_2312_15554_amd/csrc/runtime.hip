@@ -570,6 +570,16 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
     c.adaptive = pen.adaptive;
     c.hist_cap = hist_cap;
   }
+  // Step 1 in increment form: the two-launch slab passes form X in their
+  // local pass (automatic for FP32 there; FP64 keeps the paper's form)
+  for (auto& Gp : groups) {
+    const bool can = Gp->slab && !Gp->fused;
+    const int form = o.step1_form != 0 ? o.step1_form : (can && sizeof(T) == 4 ? 2 : 1);
+    if (form == 2 && !can)
+      return fail(ACM_E_INVALID,
+                  "the increment form of Step 1 needs the two-launch xy-slab passes (pass mode 2 or 4)");
+    for (int i : Gp->cells) hc[i].incr_enabled = form == 2 ? 1 : 0;
+  }
   HIP_TRY(hipMemcpyAsync(dctl, hc.data(), sizeof(StokesCtl) * ncell, hipMemcpyHostToDevice, s));
 
   // ---- warm start: u0 = (1-H) u_in, q0 = q_in, a0 = lambda0 = H (g - grad q0 +
@@ -951,6 +961,7 @@ static acm_status check_penalty_opts(const acm_penalty& P, const acm_opts& O, do
   if (!(O.eps >= 0.0) || O.max_iter < 1) return fail(ACM_E_INVALID, "eps >= 0 and max_iter >= 1 required");
   if (O.pass_mode < 0 || O.pass_mode > 4) return fail(ACM_E_INVALID, "pass_mode must be 0 to 4");
   if (O.derivative != 0 && O.derivative != 1) return fail(ACM_E_INVALID, "derivative must be 0 or 1");
+  if (O.step1_form < 0 || O.step1_form > 2) return fail(ACM_E_INVALID, "step1_form must be 0, 1 or 2");
   if (O.derivative == 1 && O.warm_start)
     return fail(ACM_E_INVALID, "the warm start forms its state with central differences: derivative 0");
   if (O.green_variant < 0 || O.green_variant > kGreenVariants)
@@ -1634,7 +1645,7 @@ void acm_default_opts(acm_opts* o) {
 
 const char* acm_last_error(void) { return g_err.c_str(); }
 
-int32_t acm_version(void) { return 4; }
+int32_t acm_version(void) { return 5; }
 
 acm_status acm_stokes_solve(const acm_grid* grid, const uint8_t* H, const double* g_p, double nu,
                             const acm_penalty* pen, const acm_opts* opts, void* u, void* q,

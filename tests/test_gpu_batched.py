@@ -27,10 +27,14 @@ def test_batched_equals_single_cell_solves(pass_mode):
     from paper_2312_15554_amd.api import acm_stokes_solve, acm_stokes_solve_batched
     Hs = [dev(H) for H in _cells()]
     gs = [(1.0, 0.0, 0.0)] * len(Hs)
-    rb = acm_stokes_solve_batched(Hs, gs, eps=1e-5, max_iter=20000, pass_mode=pass_mode)
+    # one green kernel for both calls: the autotuner's trial iterations (in
+    # the first solve of a grid) run the other kernels, equal only to rounding
+    rb = acm_stokes_solve_batched(Hs, gs, eps=1e-5, max_iter=20000, pass_mode=pass_mode,
+                                  green_variant=1)
     for i, H in enumerate(Hs):
         print(f"batched cell {i} shape={tuple(H.shape)}", flush=True)
-        rs = acm_stokes_solve(H, gs[i], eps=1e-5, max_iter=20000, want_q=False, pass_mode=pass_mode)
+        rs = acm_stokes_solve(H, gs[i], eps=1e-5, max_iter=20000, want_q=False, pass_mode=pass_mode,
+                              green_variant=1)
         assert rb["stats"][i]["converged"] and rs["stats"]["converged"]
         assert rb["stats"][i]["iters"] == rs["stats"]["iters"]
         assert torch.equal(rb["us"][i], rs["u"])
