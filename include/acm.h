@@ -89,9 +89,18 @@ typedef struct {
                            iterations until the host has formed r again.  Same
                            iterates as 2, bit for bit (needs a single cell;
                            otherwise ACM_E_INVALID).
+                           5 row-step passes (any grid, a single cell with
+                           32-byte aligned u and 16-byte aligned H; otherwise
+                           ACM_E_INVALID): one pass over x rows takes the
+                           spectra back to real space, applies Steps 2-3 and
+                           forms the next right-hand side with the b of its
+                           iteration, transformed in place (y transforms in
+                           their own passes in 3D); a one-workgroup kernel
+                           forms Step 4, and only when that changes b is the
+                           right-hand side formed again.
                            Automatic picks 4 for a single cell where the
                            slab passes apply, 2 for a batch of such cells,
-                           else 1. */
+                           5 for any other single 3D cell, else 1. */
   int32_t green_variant; /* Stokes: kernel of the last-axis (green) pass. 0 automatic:
                            the first solve of a grid times every variant over a few
                            iterations and keeps the fastest for that grid; 1-3 force
@@ -110,8 +119,8 @@ typedef struct {
                            Stokes warm start needs 0; the transport slab form
                            folds central differences and is replaced by the row
                            form with 1. */
-  int32_t step1_form;   /* Stokes: 0 automatic (2 for FP32 on the fused xy-slab
-                           passes of pass modes 2 and 4, else 1); 1 Step 1 solved
+  int32_t step1_form;   /* Stokes: 0 automatic (2 for FP32 with pass modes 2, 4
+                           and 5, else 1); 1 Step 1 solved
                            for u from r = b ut - a (the paper's form); 2 increment
                            form: while b is unchanged the spectra carry the change
                            X of Step 1's right-hand side since the last solve and
@@ -121,7 +130,7 @@ typedef struct {
                            convergence instead of the O(1) reaction in the solid,
                            so the residuals keep falling below the FP32 floor of
                            form 1); an iteration after a change of b is in form 1.
-                           Form 2 needs pass mode 2 or 4 (ACM_E_INVALID otherwise). */
+                           Form 2 needs pass mode 2, 4 or 5 (ACM_E_INVALID otherwise). */
 } acm_opts;
 
 /* Kernel kinds reported in acm_stats.kernel_ms (with opts.profile = 1).  Each

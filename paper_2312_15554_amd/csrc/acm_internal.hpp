@@ -312,6 +312,20 @@ hipError_t launch_warm_init(const Geom& g, const T* u, const T* q, const uint8_t
 // An empty kernel (profiling: calibrates the per-launch event overhead).
 hipError_t launch_noop(hipStream_t s);
 
+// Row-step pass structure (single cell): rows_step (inverse x transform,
+// Steps 2-3, next right-hand side with the b of the iteration, forward x
+// transform, one record per workgroup), the Step 4 kernel without the hold
+// word, and rows_rhs_cond (r again from u, a and H only when Step 4 changed b).
+int rows_step_blocks(const Geom& g, int prec_bytes);
+template <typename T>
+hipError_t launch_rows_step(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
+                            int par, int green_blocks, hipStream_t s);
+template <typename T>
+hipError_t launch_rows_rhs_cond(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
+                                int par, hipStream_t s);
+hipError_t launch_step4_nohold(const Geom& g, const StokesCellArgs& one, int par, int nrec,
+                               hipStream_t s);
+
 // Fused xy-slab Stokes passes (3D, nx == ny, slab of one field in LDS).
 template <typename T>
 bool slab_supported(const Geom& g);

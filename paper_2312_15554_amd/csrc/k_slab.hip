@@ -386,7 +386,7 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_rhs(
 // Step 4 in one workgroup (pass mode 4) of the slab passes' block size: the
 // same sums as the rhs pass forms (same records, same order), so the same bits.
 __global__ __launch_bounds__(1024) void k_slab_step4(StokesCellArgs one, int par, int nrec,
-                                                     int64_t ntot) {
+                                                     int64_t ntot, int set_hold) {
   __shared__ double red7[7 * 16];
   StokesCtl* ctl = one.ctl;
   // The kernel is a chain of latencies: everything it reads (the stop words,
@@ -420,7 +420,7 @@ __global__ __launch_bounds__(1024) void k_slab_step4(StokesCellArgs one, int par
     stokes_step4(ctl, cur, tot, ntot, nx);
     stokes_history(ctl, cur, nx, one.hist);
     ctl->st[par ^ 1] = nx;
-    if (!nx.done && nx.psi[2] != cur.psi[2]) ctl->hold = 1 + (par ^ 1);
+    if (set_hold && !nx.done && nx.psi[2] != cur.psi[2]) ctl->hold = 1 + (par ^ 1);
   }
 }
 
@@ -440,7 +440,13 @@ hipError_t launch_slab_step4(const Geom& g, const StokesCellArgs& one, int par, 
     default:
       return hipErrorInvalidValue;
   }
-  ACM_LAUNCH(k_slab_step4, dim3(1), dim3(nt), 0, s, one, par, nrec, g.ntot);
+  ACM_LAUNCH(k_slab_step4, dim3(1), dim3(nt), 0, s, one, par, nrec, g.ntot, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_step4_nohold(const Geom& g, const StokesCellArgs& one, int par, int nrec,
+                               hipStream_t s) {
+  ACM_LAUNCH(k_slab_step4, dim3(1), dim3(1024), 0, s, one, par, nrec, g.ntot, 0);
   return hipGetLastError();
 }
 

@@ -17,7 +17,9 @@
 //           penalty update (eq. varying algorithm).
 //   rhs    (x rows): r = b^{n+1} ut^{n+1} - a^{n+1}, forward x transform.
 //   [y forward in 3D]
-#include "pass_common.hpp"
+#include <algorithm>
+
+#include "slab_common.hpp"
 #include "stokes_finalize.hpp"
 
 namespace acm {
@@ -314,6 +316,201 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_stokes_rhs(
 }
 
 
+// ------------------------------------------------------------ row-step pass
+// x-row form of the fused local pass, for cells whose xy-slab does not fit in
+// LDS (and 2D cells on request): a persistent grid walks the row blocks of one
+// field; for each block it loads the half-spectrum rows, takes them back to
+// real space (u^{n+1}, or its change in increment form), applies Steps 2-3,
+// forms the next Step 1's real-space input with the b of this iteration (r, or
+// X in increment form), forward-transforms it and stores it over the rows it
+// loaded.  One 7-value record per workgroup (its share of the green partials,
+// then its 4 partial sums) goes to the Step 4 kernel; no cross-workgroup
+// traffic, no fences.
+template <typename T, int M>
+__global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_rows_step(
+    StokesCellArgs ca, int par, int ngreen, int nfield, int nrows, int64_t ntot, int64_t nspec,
+    const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ rtw) {
+  using C = RowCfg<T, M>;
+  using V = typename Vec4<T>::type;
+  constexpr int NX = 2 * M;
+  constexpr int QR = NX / 4;  // quads per row
+  cplx<T>* __restrict__ spec = reinterpret_cast<cplx<T>*>(ca.spec);
+  T* __restrict__ u = reinterpret_cast<T*>(ca.u);
+  T* __restrict__ a = reinterpret_cast<T*>(ca.a);
+  const uint8_t* __restrict__ H = ca.H;
+  const double* __restrict__ gpart = ca.part;
+  const StokesCtl* ctl = ca.ctl;
+  extern __shared__ __align__(16) char smem_raw[];
+  __shared__ double red[4 * 16];
+  constexpr int kShare = 8;
+  __shared__ double gsh[3 * kShare];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  T* ldsr = reinterpret_cast<T*>(smem_raw);
+  if (stokes_skip(ctl)) return;
+  const StokesState& cur = ctl->st[par];
+  const double al = cur.psi[0], bb = cur.psi[2];
+  const double ccd = bb / (bb + al);
+  const T cc = (T)ccd;
+  const T cp = (T)cur.c_prev;
+  const T ka = (T)(bb * al / (bb + al));
+  const T rb = (T)bb;
+  const T rbc = (T)(bb * ccd);
+  const T rbcp = (T)(bb * cur.c_prev);
+  const bool incr = cur.incr != 0;
+  const bool xform = ctl->incr_enabled != 0;
+  const int nblk = gridDim.x, bid = blockIdx.x;
+  if (threadIdx.x < kShare) {
+    const int g0 = (int)((int64_t)ngreen * bid / nblk), g1 = (int)((int64_t)ngreen * (bid + 1) / nblk);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int j = g0 + (int)threadIdx.x; j < g1; j += kShare) {
+      s0 += gpart[j * 3 + 0];
+      s1 += gpart[j * 3 + 1];
+      s2 += gpart[j * 3 + 2];
+    }
+    gsh[threadIdx.x * 3 + 0] = s0;
+    gsh[threadIdx.x * 3 + 1] = s1;
+    gsh[threadIdx.x * 3 + 2] = s2;
+  }
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  // work list: (field, row block) pairs, field-major
+  const int nrb = (nrows + C::RB - 1) / C::RB;
+  const int row = threadIdx.x / C::TPP, t = threadIdx.x % C::TPP;
+  for (int w = blockIdx.x; w < nfield * nrb; w += gridDim.x) {
+    const int field = w / nrb, b = w - field * nrb;
+    const int row0 = b * C::RB;
+    const int nr = min(C::RB, nrows - row0);
+    cplx<T>* rows = spec + field * nspec + (int64_t)row0 * (M + 1);
+    for (int v = threadIdx.x; v < nr * (M + 1); v += C::NT) {
+      const int r = v / (M + 1), k = v - r * (M + 1);
+      lds[r * C::RP + k] = rows[v];
+    }
+    __syncthreads();
+    rows_c2r_lds<T, M>(lds, 0, row, t, row < nr, tw, rtw);
+    const int64_t off = field * ntot + (int64_t)row0 * NX;
+    V* uq = reinterpret_cast<V*>(u + off);
+    V* aq = reinterpret_cast<V*>(a + off);
+    const uint32_t* hq = reinterpret_cast<const uint32_t*>(H + (int64_t)row0 * NX);
+    for (int q = threadIdx.x; q < nr * QR; q += C::NT) {
+      const int r = q / QR, x = 4 * (q - r * QR);
+      // a is exactly zero in the pore, so it is loaded unconditionally
+      const V upj = uq[q];
+      const uint32_t hwj = hq[q];
+      V aoj = aq[q];
+      T* cell = ldsr + r * 2 * C::RP + x;
+      V un = lds_ld4<V>(cell);
+      if (incr) {
+        un.x += upj.x;
+        un.y += upj.y;
+        un.z += upj.z;
+        un.w += upj.w;
+      }
+      const T unv[4] = {un.x, un.y, un.z, un.w};
+      const T upv[4] = {upj.x, upj.y, upj.z, upj.w};
+      T dav[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double du = (double)unv[e] - (double)upv[e];
+        acc[3] += du * du;
+      }
+      uq[q] = un;
+      if (hwj) {
+        T aov[4] = {aoj.x, aoj.y, aoj.z, aoj.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if ((hwj >> (8 * e)) & 0xffu) {
+            const T an = aov[e] + ka * unv[e];
+            dav[e] = an - aov[e];
+            aov[e] = an;
+            const T dd = cc * unv[e] - cp * upv[e];
+            acc[0] += (double)unv[e] * unv[e];
+            acc[1] += (double)dd * dd;
+            acc[2] += (double)an * an;
+          }
+        }
+        aoj.x = aov[0];
+        aoj.y = aov[1];
+        aoj.z = aov[2];
+        aoj.w = aov[3];
+        aq[q] = aoj;
+      }
+      V r4;
+      if (xform) {
+        r4.x = ((hwj & 0xffu) ? rbc * un.x - rbcp * upj.x : rb * (un.x - upj.x)) - dav[0];
+        r4.y = ((hwj & 0xff00u) ? rbc * un.y - rbcp * upj.y : rb * (un.y - upj.y)) - dav[1];
+        r4.z = ((hwj & 0xff0000u) ? rbc * un.z - rbcp * upj.z : rb * (un.z - upj.z)) - dav[2];
+        r4.w = ((hwj & 0xff000000u) ? rbc * un.w - rbcp * upj.w : rb * (un.w - upj.w)) - dav[3];
+      } else {
+        r4.x = ((hwj & 0xffu) ? rbc : rb) * un.x - aoj.x;
+        r4.y = ((hwj & 0xff00u) ? rbc : rb) * un.y - aoj.y;
+        r4.z = ((hwj & 0xff0000u) ? rbc : rb) * un.z - aoj.z;
+        r4.w = ((hwj & 0xff000000u) ? rbc : rb) * un.w - aoj.w;
+      }
+      lds_st4(cell, r4);
+    }
+    __syncthreads();
+    rows_r2c_lds<T, M>(lds, 0, row, t, row < nr, tw, rtw);
+    for (int v = threadIdx.x; v < nr * (M + 1); v += C::NT) {
+      const int r = v / (M + 1), k = v - r * (M + 1);
+      rows[v] = lds[r * C::RP + k];
+    }
+    __syncthreads();
+  }
+  block_sum<4>(acc, red);
+  if (threadIdx.x == 0) {
+    double gs[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < kShare; ++k)
+      for (int c = 0; c < 3; ++c) gs[c] += gsh[k * 3 + c];
+    for (int c = 0; c < 3; ++c) ca.lpart[bid * 7 + c] = gs[c];
+    for (int c = 0; c < 4; ++c) ca.lpart[bid * 7 + 3 + c] = acc[c];
+  }
+}
+
+// After the Step 4 kernel: when Step 4 changed b, r = b' ut' - a' is formed
+// again from the stored u, a and H with the new penalties (and Step 1 of the
+// next iteration is in the paper's form); otherwise the rows already hold the
+// next right-hand side and every workgroup exits at once.
+template <typename T, int M>
+__global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_rows_rhs_cond(
+    StokesCellArgs ca, int par, int nfield, int nrows, int64_t ntot, int64_t nspec,
+    const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ rtw) {
+  using C = RowCfg<T, M>;
+  constexpr int NX = 2 * M;
+  cplx<T>* __restrict__ spec = reinterpret_cast<cplx<T>*>(ca.spec);
+  const T* __restrict__ u = reinterpret_cast<const T*>(ca.u);
+  const T* __restrict__ a = reinterpret_cast<const T*>(ca.a);
+  const uint8_t* __restrict__ H = ca.H;
+  const StokesCtl* __restrict__ ctl = ca.ctl;
+  extern __shared__ __align__(16) char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  T* ldsr = reinterpret_cast<T*>(smem_raw);
+  if (ctl->hold) return;
+  const StokesState& nx = ctl->st[par ^ 1];
+  if (nx.done || nx.psi[2] == ctl->st[par].psi[2]) return;
+  const T bb = (T)nx.psi[2];
+  const T bcp = (T)(nx.psi[2] * nx.c_prev);
+  const int nrb = (nrows + C::RB - 1) / C::RB;
+  const int row = threadIdx.x / C::TPP, t = threadIdx.x % C::TPP;
+  for (int w = blockIdx.x; w < nfield * nrb; w += gridDim.x) {
+    const int field = w / nrb, b = w - field * nrb;
+    const int row0 = b * C::RB;
+    const int nr = min(C::RB, nrows - row0);
+    const int64_t off = field * ntot + (int64_t)row0 * NX;
+    for (int v = threadIdx.x; v < nr * NX; v += C::NT) {
+      const int r = v / NX, x = v - r * NX;
+      const T un = u[off + v];
+      ldsr[r * 2 * C::RP + x] = H[(int64_t)row0 * NX + v] ? (bcp * un - a[off + v]) : (bb * un);
+    }
+    __syncthreads();
+    rows_r2c_lds<T, M>(lds, 0, row, t, row < nr, tw, rtw);
+    cplx<T>* dst = spec + field * nspec + (int64_t)row0 * (M + 1);
+    for (int v = threadIdx.x; v < nr * (M + 1); v += C::NT) {
+      const int r = v / (M + 1), k = v - r * (M + 1);
+      dst[v] = lds[r * C::RP + k];
+    }
+    __syncthreads();
+  }
+}
+
 // Register-resident variant of the green pass (lengths whose plan allows the
 // register FFT): every thread loads the pencil elements it owns straight from
 // global memory, the forward transform, the per-mode operator and the inverse
@@ -588,7 +785,76 @@ hipError_t launch_stokes_rhs(const Geom& g, const DevTables<T>& tb, const Stokes
   }
 }
 
+// Row-step pass: a persistent grid of kRowsStepWG workgroups (what the
+// device holds at once: 5 of the 256-thread workgroups per CU at the kernel's
+// register count, on 256 CUs) walks the (field, row block) work list, so
+// that the Step 4 kernel sums a bounded number of records.
+constexpr int kRowsStepWG = 1280;
+constexpr int kRowsRhsWG = 512;
+
+int rows_step_blocks(const Geom& g, int prec_bytes) {
+  switch (g.nx / 2) {
+#define CASE(M)                                                                               \
+  case M: {                                                                                   \
+    const int rb = prec_bytes == 8 ? RowCfg<double, M>::RB : RowCfg<float, M>::RB;            \
+    const int nrb = (int)((g.nrows + rb - 1) / rb);                                           \
+    return std::min(nrb * g.dim, kRowsStepWG);                                                \
+  }
+    ACM_ROW_LENGTHS(CASE)
+#undef CASE
+    default:
+      return -1;
+  }
+}
+
+template <typename T>
+hipError_t launch_rows_step(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
+                            int par, int green_blocks, hipStream_t s) {
+  const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
+  const int nb = rows_step_blocks(g, (int)sizeof(T));
+  if (nb <= 0) return hipErrorInvalidValue;
+  switch (g.nx / 2) {
+#define CASE(M)                                                                               \
+  case M: {                                                                                   \
+    using C = RowCfg<T, M>;                                                                   \
+    ACM_LAUNCH((k_rows_step<T, M>), dim3((unsigned)nb), dim3(C::NT), C::LDS_BYTES, s, one,   \
+               par, green_blocks, g.dim, (int)g.nrows, g.ntot, g.nspec, ct + tb.off.tw_x,     \
+               ct + tb.off.rtw);                                                              \
+    return hipGetLastError();                                                                 \
+  }
+    ACM_ROW_LENGTHS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_rows_rhs_cond(const Geom& g, const DevTables<T>& tb, const StokesCellArgs& one,
+                                int par, hipStream_t s) {
+  const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
+  switch (g.nx / 2) {
+#define CASE(M)                                                                               \
+  case M: {                                                                                   \
+    using C = RowCfg<T, M>;                                                                   \
+    const int nrb = (int)((g.nrows + C::RB - 1) / C::RB);                                     \
+    dim3 grid((unsigned)std::min(nrb * g.dim, kRowsRhsWG));                                   \
+    ACM_LAUNCH((k_rows_rhs_cond<T, M>), grid, dim3(C::NT), C::LDS_BYTES, s, one, par, g.dim, \
+               (int)g.nrows, g.ntot, g.nspec, ct + tb.off.tw_x, ct + tb.off.rtw);             \
+    return hipGetLastError();                                                                 \
+  }
+    ACM_ROW_LENGTHS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
 #define INST(T)                                                                                \
+  template hipError_t launch_rows_step<T>(const Geom&, const DevTables<T>&,                    \
+                                          const StokesCellArgs&, int, int, hipStream_t);       \
+  template hipError_t launch_rows_rhs_cond<T>(const Geom&, const DevTables<T>&,                \
+                                              const StokesCellArgs&, int, hipStream_t);        \
   template hipError_t launch_stokes_green<T>(const Geom&, const DevTables<T>&,                 \
                                              const StokesCellArgs&, const StokesCellArgs*, int, \
                                              int, int, int*, hipStream_t);                     \

@@ -337,6 +337,7 @@ struct StokesGroup {
   bool slab = false;
   bool fused = false;    // slab local + rhs in one launch (single resident cell)
   bool s4 = false;       // Step 4 in the green pass after the first iterations (single slab cell)
+  bool rows5 = false;    // row-step pass structure (single cell, pass mode 5)
   int green_var = 0;     // tile variant of the green pass
   int ngreen = 0;        // green workgroups per cell for that variant
   int ngreen_max = 0;    // partial-buffer capacity (largest variant)
@@ -392,6 +393,23 @@ static hipError_t enqueue_iteration(StokesGroup<T>& G, hipStream_t s, Profiler* 
   e = launch_stokes_green<T>(g, tb, one, many, n, par, G.green_var, nullptr, s);
   if (e != hipSuccess) return e;
   prof->end(KK_GREEN, ev0);
+  if (G.rows5) {
+    if (d == 3 && (e = cols(+1, KK_YINV)) != hipSuccess) return e;
+    prof->begin(KK_LOCAL, &ev0);
+    e = launch_rows_step<T>(g, tb, one, par, G.ngreen, s);
+    if (e != hipSuccess) return e;
+    prof->end(KK_LOCAL, ev0);
+    prof->begin(KK_RHS, &ev0);
+    e = launch_step4_nohold(g, one, par, rows_step_blocks(g, (int)sizeof(T)), s);
+    if (e != hipSuccess) return e;
+    prof->end(KK_RHS, ev0);
+    prof->begin(KK_RHS, &ev0);
+    e = launch_rows_rhs_cond<T>(g, tb, one, par, s);
+    if (e != hipSuccess) return e;
+    prof->end(KK_RHS, ev0);
+    if (d == 3 && (e = cols(-1, KK_YFWD)) != hipSuccess) return e;
+    return hipSuccess;
+  }
   if (mode == IT_STEP4) {
     prof->begin(KK_LOCAL, &ev0);
     e = launch_slab_local<T>(g, tb, one, many, n, par, G.ngreen, s);
@@ -492,14 +510,21 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
                     "resident on the device at once");
       G.slab = true;
       G.fused = o.pass_mode == 3;
+    } else if (o.pass_mode == 5) {
+      if (!one_cell) return fail(ACM_E_INVALID, "the row-step pass structure needs a single cell");
+      if (!aligned) return fail(ACM_E_INVALID, "the row-step passes need 32-byte aligned u and 16-byte aligned H");
+      G.rows5 = true;
     } else if (o.pass_mode == 0) {
       // the single-launch structure is not chosen automatically: its
       // device-wide gate has measured slower than the launch boundary; the
-      // Step 4 kernel form is (one cell)
+      // Step 4 kernel form is (one cell); a single 3D cell whose slab does
+      // not fit takes the row-step structure
       G.slab = slab_supported<T>(g) && aligned;
       G.s4 = G.slab && one_cell;
+      G.rows5 = !G.slab && one_cell && aligned && g.dim == 3;
     }
-    G.nlocal = std::max(G.pl->local_blocks, slab_local_blocks<T>(g));
+    G.nlocal = std::max(std::max(G.pl->local_blocks, slab_local_blocks<T>(g)),
+                        rows_step_blocks(g, (int)sizeof(T)));
     G.part_b = sizeof(double) * (size_t)(3 * G.ngreen_max + 7 * G.nlocal);
     G.cell_b = al256(G.spec_b) + 2 * al256(G.one_b) + al256(G.a_b) + al256(G.part_b);
     HIP_TRY(hipMalloc(&G.ws.p, G.cell_b * G.cells.size()));
@@ -573,11 +598,12 @@ static acm_status stokes_run(const std::vector<CellPlan*>& plans,
   // Step 1 in increment form: the two-launch slab passes form X in their
   // local pass (automatic for FP32 there; FP64 keeps the paper's form)
   for (auto& Gp : groups) {
-    const bool can = Gp->slab && !Gp->fused;
+    const bool can = (Gp->slab && !Gp->fused) || Gp->rows5;
     const int form = o.step1_form != 0 ? o.step1_form : (can && sizeof(T) == 4 ? 2 : 1);
     if (form == 2 && !can)
       return fail(ACM_E_INVALID,
-                  "the increment form of Step 1 needs the two-launch xy-slab passes (pass mode 2 or 4)");
+                  "the increment form of Step 1 needs the two-launch xy-slab passes or the "
+                  "row-step passes (pass mode 2, 4 or 5)");
     for (int i : Gp->cells) hc[i].incr_enabled = form == 2 ? 1 : 0;
   }
   HIP_TRY(hipMemcpyAsync(dctl, hc.data(), sizeof(StokesCtl) * ncell, hipMemcpyHostToDevice, s));
@@ -959,7 +985,7 @@ static acm_status stokes_all_solid(const CellPlan* pl, void* u, void* q, acm_sta
 static acm_status check_penalty_opts(const acm_penalty& P, const acm_opts& O, double nu) {
   if (!(nu > 0.0) || !isfinite(nu)) return fail(ACM_E_INVALID, "nu must be positive");
   if (!(O.eps >= 0.0) || O.max_iter < 1) return fail(ACM_E_INVALID, "eps >= 0 and max_iter >= 1 required");
-  if (O.pass_mode < 0 || O.pass_mode > 4) return fail(ACM_E_INVALID, "pass_mode must be 0 to 4");
+  if (O.pass_mode < 0 || O.pass_mode > 5) return fail(ACM_E_INVALID, "pass_mode must be 0 to 5");
   if (O.derivative != 0 && O.derivative != 1) return fail(ACM_E_INVALID, "derivative must be 0 or 1");
   if (O.step1_form < 0 || O.step1_form > 2) return fail(ACM_E_INVALID, "step1_form must be 0, 1 or 2");
   if (O.derivative == 1 && O.warm_start)

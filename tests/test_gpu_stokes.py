@@ -713,3 +713,102 @@ def test_fp32_increment_form_converges_where_the_paper_form_stalls():
     full = _solve(H, g, dtype=torch.float32, eps=1e-9, max_iter=2 * n_inc, step1_form=1)
     print(f"  FP32 paper form: converged {full['stats']['converged']}", flush=True)
     assert not full["stats"]["converged"]
+
+
+# ---------------------------------------------------------------- row-step pass structure
+
+ROWSTEP_SHAPES = [(16, 16), (24, 32), (8, 24, 16), (16, 16, 16), (24, 16, 48), (8, 16, 256),
+                  (8, 256, 16), (16, 8, 512)]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("shape", ROWSTEP_SHAPES)
+@pytest.mark.parametrize("dtype,form", [(torch.float64, 1), (torch.float64, 2), (torch.float32, 0)])
+def test_row_step_passes_match_oracle(shape, dtype, form):
+    """Pass mode 5 (x-row pass with the speculative right-hand side, Step 4
+    kernel, r formed again only when b changes) reproduces the oracle's
+    iterates with fixed penalties, in the paper's form and the increment form
+    of Step 1 (Section 3.1, Steps 1-4), over grids with 256- and 512-long
+    axes."""
+    require_gpu()
+    print(f"row-step parity shape={shape} dtype={dtype} form={form}", flush=True)
+    H = I.random_mask(shape, 21, 0.3)
+    g = (0.6, -0.3, 1.0)[:len(shape)]
+    M = 25
+    r = _solve(H, g, dtype=dtype, penalty=dict(alpha=30.0, beta=45.0, b=20.0, adaptive=0),
+               eps=0.0, max_iter=M, pass_mode=5, step1_form=form)
+    key = ("rows", shape)
+    if key not in _SLAB_ORACLE:
+        _SLAB_ORACLE[key] = O.stokes_admm(H, g, alpha=30.0, beta=45.0, b=20.0, adaptive=False,
+                                          eps=0.0, max_iter=M)
+    o = _SLAB_ORACLE[key]
+    assert r["stats"]["iters"] == M
+    tol = 1e-11 if dtype == torch.float64 else 2e-5
+    assert np.abs(host(r["u"]) - o["u"]).max() < tol * np.abs(o["u"]).max()
+    assert np.abs(host(r["q"]) - o["q"]).max() < tol * 10 * np.abs(o["q"]).max()
+    for k in range(3):
+        assert abs(r["stats"]["r_p"][k] - o["r_p"][k]) <= tol * 100 * o["r_p"][k] + 1e-12
+        assert abs(r["stats"]["r_d"][k] - o["r_d"][k]) <= tol * 100 * o["r_d"][k] + 1e-12
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("form", [1, 2])
+def test_row_step_passes_follow_oracle_with_adaptive_penalties(form):
+    """FP64, adaptive penalties, 240 iterations on a 24 x 16 x 48 cell: the
+    oracle's penalty decisions at every iteration, including those where Step
+    4 changes b and the right-hand side is formed again."""
+    require_gpu()
+    shape = (24, 16, 48)
+    H = I.overlapping_spheres(shape, 2.0, 0.45, seed=7)
+    g = (1.0, 0.3, -0.5)
+    M = 240
+    r = _solve(H, g, dtype=torch.float64, penalty=dict(tau=(5.0, 10.0, 5.0)), eps=0.0,
+               max_iter=M, check_every=8, pass_mode=5, history_cap=M, step1_form=form)
+    o = O.stokes_admm(H, g, tau=(5.0, 10.0, 5.0), eps=0.0, max_iter=M, history=True)
+    assert r["stats"]["iters"] == M
+    assert np.abs(host(r["u"]) - o["u"]).max() < 1e-10 * np.abs(o["u"]).max()
+    hp = np.array([h["psi"] for h in o["history"]])
+    hr = np.array([h["rp"] + h["rd"] for h in o["history"]])
+    assert np.array_equal(r["history"][:, 12:15], hp)
+    assert len(_b_changes_after(r["history"], 1)) >= 2
+    assert np.allclose(r["history"][:, 0:6], hr, rtol=1e-8, atol=1e-14)
+
+
+@pytest.mark.gpu
+def test_row_step_passes_converge_like_the_oracle():
+    """A converged adaptive solve in pass mode 5 (FP64, eps = 1e-8) takes the
+    oracle's number of iterations and gives its permeability."""
+    require_gpu()
+    H = I.overlapping_spheres((16, 24, 16), 1.5, 0.45, seed=11)
+    g = (1.0, 0.0, 0.0)
+    r = _solve(H, g, dtype=torch.float64, eps=1e-8, max_iter=100000, pass_mode=5)
+    o = O.stokes_admm(H, g, eps=1e-8, max_iter=100000)
+    assert r["stats"]["converged"] and o["status"] == "converged"
+    assert r["stats"]["iters"] == o["iters"]
+    k_gpu, k_ref = float(r["u"][0].mean()), o["u"][0].mean()
+    assert abs(k_gpu - k_ref) < 1e-10 * abs(k_ref)
+
+
+@pytest.mark.gpu
+@pytest.mark.timeout(900)
+def test_row_step_full_size_matches_oracle():
+    """The 256^3 test-cell workload (overlapping spheres, radius 16 voxels,
+    porosity 0.42, seed 20000) in the configuration the 256^3 solves run:
+    automatic pass structure (row-step passes), FP32, increment form, fixed
+    penalties nu/h, 8 iterations, against the FP64 oracle run here on the
+    host: u element by element within 2e-5 of its maximum and K^M within
+    1e-5."""
+    require_gpu()
+    from paper_2312_15554_amd import warmstart as W
+    print("256^3 row-step parity: building the cell", flush=True)
+    H = W.make_cells(256, 1, 20000, 16.0, 0.35, 0.50)[0]
+    M, p = 8, 256.0
+    r = _solve(H, (1.0, 0.0, 0.0), dtype=torch.float32,
+               penalty=dict(alpha=p, beta=p, b=p, adaptive=0), eps=0.0, max_iter=M, want_q=False)
+    assert r["stats"]["iters"] == M
+    u = host(r["u"]).astype(np.float64)
+    del r
+    print("oracle: 8 FP64 ADMM iterations at 256^3", flush=True)
+    o = O.stokes_admm(H, (1.0, 0.0, 0.0), alpha=p, beta=p, b=p, adaptive=False, eps=0.0, max_iter=M)
+    assert np.abs(u - o["u"]).max() < 2e-5 * np.abs(o["u"]).max()
+    assert abs(u[0].mean() - o["u"][0].mean()) < 1e-5 * abs(o["u"][0].mean())
