@@ -129,7 +129,8 @@ typedef struct {
                            FP32 transforms then round quantities that vanish at
                            convergence instead of the O(1) reaction in the solid,
                            so the residuals keep falling below the FP32 floor of
-                           form 1); an iteration after a change of b is in form 1.
+                           form 1); the first 64 iterations, and an iteration
+                           after a change of b, are in form 1.
                            Form 2 needs pass mode 2, 4 or 5 (ACM_E_INVALID otherwise). */
 } acm_opts;
 

@@ -87,6 +87,10 @@ __host__ __device__ inline bool stokes_skip(const StokesCtl* c) {
   return (c->st[0].done | c->st[1].done | c->hold) != 0;
 }
 
+// Iterations in the paper's form before the increment form of Step 1 may
+// start (see StokesState::incr).
+constexpr int64_t kIncrAfter = 64;
+
 // One history record per iteration: rp[3], rd[3], tp[3], td[3], psi[3].
 constexpr int kHistDoubles = 15;
 

@@ -68,19 +68,27 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_rows_c2r(const cplx<T>* 
   }
 }
 
+// Column tiles: lengths of 256 and more take the wider tile (16 columns of
+// FP32: whole 128-byte lines per row of the tile).
+template <int L>
+constexpr int cols_var() {
+  return L >= 256 ? 2 : 0;
+}
+
 template <typename T, int L, int SIGN>
-__global__ __launch_bounds__((ColCfg<T, L, 1>::NT)) void k_cols(ColCellArgs one,
-                                                              const ColCellArgs* __restrict__ many,
-                                                              int64_t field_stride, ColMap m,
-                                                              const cplx<T>* __restrict__ tw) {
-  using C = ColCfg<T, L, 1>;
+__global__ __launch_bounds__((ColCfg<T, L, 1, cols_var<L>()>::NT)) void k_cols(
+    ColCellArgs one, const ColCellArgs* __restrict__ many, int64_t field_stride, ColMap m,
+    const cplx<T>* __restrict__ tw) {
+  using C = ColCfg<T, L, 1, cols_var<L>()>;
   const ColCellArgs ca = many ? many[blockIdx.z] : one;
   if ((ca.skip != nullptr && *ca.skip) || (ca.skip2 != nullptr && *ca.skip2)) return;
   cplx<T>* data = reinterpret_cast<cplx<T>*>(ca.data);
   extern __shared__ __align__(16) char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* base = data + blockIdx.y * field_stride;
-  const int f0 = blockIdx.x * C::TX;
+  // neighbouring tiles share the cache lines at their edges (rows of the half
+  // spectrum are xh = nx/2 + 1 values apart): keep them on one XCD
+  const int f0 = xcd_tile(blockIdx.x, gridDim.x) * C::TX;
   for (int e = threadIdx.x; e < L * C::TX; e += C::NT) {
     const int i = e / C::TX, col = e - i * C::TX;
     const int f = f0 + col;
@@ -94,6 +102,41 @@ __global__ __launch_bounds__((ColCfg<T, L, 1>::NT)) void k_cols(ColCellArgs one,
     const int i = e / C::TX, col = e - i * C::TX;
     const int f = f0 + col;
     if (f < m.ncols) base[col_base(m, f) + i * m.as] = lds[e];
+  }
+}
+
+// Register-resident column transform (lengths whose plan allows the register
+// FFT): each thread loads the elements t + m TPP of its column straight from
+// global memory, the stages run on registers with LDS only between them, and
+// the results go straight back.
+template <typename T, int L, int SIGN>
+__global__ __launch_bounds__((ColCfg<T, L, 1, cols_var<L>()>::NT)) void k_cols_reg(
+    ColCellArgs one, const ColCellArgs* __restrict__ many, int64_t field_stride, ColMap m,
+    const cplx<T>* __restrict__ tw) {
+  using C = ColCfg<T, L, 1, cols_var<L>()>;
+  constexpr int TPP = C::TPP;
+  constexpr int EPT = L / TPP;
+  constexpr int PS = L * C::TX;
+  const ColCellArgs ca = many ? many[blockIdx.z] : one;
+  if ((ca.skip != nullptr && *ca.skip) || (ca.skip2 != nullptr && *ca.skip2)) return;
+  cplx<T>* data = reinterpret_cast<cplx<T>*>(ca.data);
+  extern __shared__ __align__(16) char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* base = data + blockIdx.y * field_stride;
+  const int f0 = xcd_tile(blockIdx.x, gridDim.x) * C::TX;
+  const int t = threadIdx.x / C::TX, col = threadIdx.x % C::TX;
+  const int f = f0 + col;
+  const bool act = t < TPP && f < m.ncols;
+  const int cb = act ? col_base(m, f) : 0;
+  cplx<T> v[1][EPT];
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) v[0][k] = base[cb + (t + k * TPP) * m.as];
+  }
+  RegFFT<T, L, 1, SIGN>::run(t, act, v, lds + col, PS, C::TX, tw);
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) base[cb + (t + k * TPP) * m.as] = v[0][k];
   }
 }
 
@@ -167,15 +210,24 @@ static hipError_t cols_impl(const Geom& g, const DevTables<T>& tb, int axis, int
   switch (L) {
 #define CASE(LL)                                                                            \
   case LL: {                                                                                \
-    using C = ColCfg<T, LL, 1>;                                                             \
+    using C = ColCfg<T, LL, 1, cols_var<LL>()>;                                             \
     dim3 grid((unsigned)((m.ncols + C::TX - 1) / C::TX), (unsigned)nfields,                 \
               (unsigned)ncells);                                                            \
-    if (sign < 0)                                                                           \
-      ACM_LAUNCH((k_cols<T, LL, -1>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many, \
-                         g.nspec, m, tw);                                                   \
-    else                                                                                    \
-      ACM_LAUNCH((k_cols<T, LL, 1>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many,  \
-                         g.nspec, m, tw);                                                   \
+    if constexpr (RegPlanOk<LL>::value()) {                                                 \
+      if (sign < 0)                                                                         \
+        ACM_LAUNCH((k_cols_reg<T, LL, -1>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many,  \
+                   g.nspec, m, tw);                                                         \
+      else                                                                                  \
+        ACM_LAUNCH((k_cols_reg<T, LL, 1>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many,   \
+                   g.nspec, m, tw);                                                         \
+    } else {                                                                                \
+      if (sign < 0)                                                                         \
+        ACM_LAUNCH((k_cols<T, LL, -1>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many,      \
+                   g.nspec, m, tw);                                                         \
+      else                                                                                  \
+        ACM_LAUNCH((k_cols<T, LL, 1>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many,       \
+                   g.nspec, m, tw);                                                         \
+    }                                                                                       \
     return hipGetLastError();                                                               \
   }
     ACM_COL_LENGTHS(CASE)

@@ -76,7 +76,9 @@ __attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
   // with ut = c u in the solid (c of the iteration that formed it) and the
   // change of a as stored
   const bool incr = cur.incr != 0;
-  const bool xform = !FUSED && ctl->incr_enabled != 0;
+  // X only where Step 4 may pass it on: the increment form starts after the
+  // first kIncrAfter iterations (Step 4 of this iteration completes cur.iter + 1)
+  const bool xform = !FUSED && ctl->incr_enabled != 0 && cur.iter + 1 >= kIncrAfter;
   const T rbcp = (T)(bb * cur.c_prev);
   const int z = blockIdx.x, field = blockIdx.y;
 

@@ -357,7 +357,8 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_rows_step(
   const T rbc = (T)(bb * ccd);
   const T rbcp = (T)(bb * cur.c_prev);
   const bool incr = cur.incr != 0;
-  const bool xform = ctl->incr_enabled != 0;
+  // X only where Step 4 may pass it on (see k_slab_local)
+  const bool xform = ctl->incr_enabled != 0 && cur.iter + 1 >= kIncrAfter;
   const int nblk = gridDim.x, bid = blockIdx.x;
   if (threadIdx.x < kShare) {
     const int g0 = (int)((int64_t)ngreen * bid / nblk), g1 = (int)((int64_t)ngreen * (bid + 1) / nblk);

@@ -119,8 +119,13 @@ __device__ __forceinline__ void stokes_step4(const StokesCtl* __restrict__ ctl,
         nx.psi[k] = fmax(cur.psi[k] / ctl->phi[k], ctl->psi_min[k]);
     }
   }
-  // the local pass formed X with this b: valid as long as b is kept
-  nx.incr = (ctl->incr_enabled && !nx.done && nx.psi[2] == cur.psi[2]) ? 1 : 0;
+  // the local pass formed X with this b: valid as long as b is kept.  The
+  // increment form starts after the first kIncrAfter iterations: in the
+  // increment form the rounding of each solve stays in u (it is never formed
+  // again from a and q), so the large early increments are left to the
+  // paper's form
+  nx.incr = (ctl->incr_enabled && !nx.done && nx.psi[2] == cur.psi[2] && nx.iter >= kIncrAfter)
+                ? 1 : 0;
 }
 
 // One record of the residual history ring: rp, rd, tp, td and the penalties

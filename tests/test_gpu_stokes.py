@@ -127,10 +127,13 @@ def test_poiseuille_closed_form(dtype):
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_converged_permeability_matches_kkt_solution(dtype):
     """Converged K tensor of a 16^3 overlapping-sphere cell against the exact
-    discrete fixed point (sparse KKT solve of the same discretisation)."""
+    discrete fixed point (sparse KKT solve of the same discretisation).  FP64
+    converges to eps = 1e-11; FP32 (increment form of Step 1) to 1e-9, where
+    the method's own band around the fixed point is about 1e-5 in K on this
+    cell (FP64 at 1e-9: 8.6e-6)."""
     require_gpu()
     H = I.overlapping_spheres(16, 1.0, 0.45, seed=3)
-    eps = 1e-11 if dtype == torch.float64 else 1e-8
+    eps = 1e-11 if dtype == torch.float64 else 1e-9
     us_gpu, us_ref = [], []
     for g in [(1, 0, 0), (0, 1, 0), (0, 0, 1)]:
         print(f"converged K dtype={dtype} g={g}", flush=True)
@@ -141,8 +144,8 @@ def test_converged_permeability_matches_kkt_solution(dtype):
     Kg = O.permeability_darcy(us_gpu)
     Kr = O.permeability_darcy(us_ref)
     rel = np.abs(Kg - Kr).max() / np.abs(Kr).max()
-    # FP32 transforms settle at a noise floor of a few 1e-5 in K on this cell
-    assert rel < (1e-7 if dtype == torch.float64 else 1e-4), rel
+    print(f"  K rel err vs KKT: {rel:.2e}", flush=True)
+    assert rel < (1e-7 if dtype == torch.float64 else 5e-5), rel
 
 
 @pytest.mark.gpu
@@ -604,20 +607,22 @@ def test_nan_initial_guess_reports_divergence(pass_mode):
 @pytest.mark.parametrize("pass_mode", [2, 4])
 def test_increment_form_matches_oracle(shape, dtype, pass_mode):
     """Step 1 in increment form (the spectra carry the change of its
-    right-hand side and the green pass solves for the change of u) gives the
-    oracle's iterates of the paper's form with fixed penalties: the two are
-    the same map in exact arithmetic (Section 3.1, Steps 1-3)."""
+    right-hand side and the green pass solves for the change of u; it takes
+    over after the first 64 iterations) gives the oracle's iterates of the
+    paper's form with fixed penalties: the two are the same map in exact
+    arithmetic (Section 3.1, Steps 1-3)."""
     require_gpu()
     print(f"increment form parity shape={shape} dtype={dtype} mode={pass_mode}", flush=True)
     H = I.overlapping_spheres(shape, shape[-1] / 16.0, 0.5, seed=5)
     g = (0.7, -0.2, 1.0)
-    M = 25
+    M = 100  # the increment form takes over after the first 64 iterations
     r = _solve(H, g, dtype=dtype, penalty=dict(alpha=40.0, beta=60.0, b=25.0, adaptive=0),
                eps=0.0, max_iter=M, pass_mode=pass_mode, step1_form=2)
-    if shape not in _SLAB_ORACLE:
-        _SLAB_ORACLE[shape] = O.stokes_admm(H, g, alpha=40.0, beta=60.0, b=25.0, adaptive=False,
-                                            eps=0.0, max_iter=M)
-    o = _SLAB_ORACLE[shape]
+    key = ("incr", shape)
+    if key not in _SLAB_ORACLE:
+        _SLAB_ORACLE[key] = O.stokes_admm(H, g, alpha=40.0, beta=60.0, b=25.0, adaptive=False,
+                                          eps=0.0, max_iter=M)
+    o = _SLAB_ORACLE[key]
     tol = 1e-11 if dtype == torch.float64 else 2e-5
     assert np.abs(host(r["u"]) - o["u"]).max() < tol * np.abs(o["u"]).max()
     assert np.abs(host(r["q"]) - o["q"]).max() < tol * 10 * np.abs(o["q"]).max()
@@ -734,7 +739,7 @@ def test_row_step_passes_match_oracle(shape, dtype, form):
     print(f"row-step parity shape={shape} dtype={dtype} form={form}", flush=True)
     H = I.random_mask(shape, 21, 0.3)
     g = (0.6, -0.3, 1.0)[:len(shape)]
-    M = 25
+    M = 100  # past the first 64 iterations, after which the increment form may start
     r = _solve(H, g, dtype=dtype, penalty=dict(alpha=30.0, beta=45.0, b=20.0, adaptive=0),
                eps=0.0, max_iter=M, pass_mode=5, step1_form=form)
     key = ("rows", shape)
