@@ -288,9 +288,30 @@ def pore_mean_velocity(H, u):
     return np.array([(pore * u[c]).sum() / pore.sum() for c in range(u.shape[0])])
 
 
+def face_harmonic_mean(A, c):
+    """Diffusivity on the face between x and x + h e_c: the harmonic mean
+    2 A(x) A(x + h e_c) / (A(x) + A(x + h e_c)), the coefficient of a flux
+    through two voxels in series."""
+    ax = A.ndim - 1 - c
+    Ap = np.roll(A, -1, axis=ax)
+    return 2.0 * A * Ap / (A + Ap)
+
+
+def forward_diff(f, c):
+    """(f(x + h e_c) - f(x)) / h_c, periodic."""
+    ax = f.ndim - 1 - c
+    return (np.roll(f, -1, axis=ax) - f) * f.shape[ax]
+
+
+def backward_diff(f, c):
+    """(f(x) - f(x - h e_c)) / h_c, periodic."""
+    ax = f.ndim - 1 - c
+    return (f - np.roll(f, 1, axis=ax)) * f.shape[ax]
+
+
 def transport_ls(H, u, g, Pe, A0=0.55, B0=None, eta=0.01, diffusivity=1.0,
                  eps=1e-6, max_iter=100000, dt=math.inf, n_steps=1,
-                 chi_init=None, history=False, derivative="central"):
+                 chi_init=None, history=False, derivative="central", form="central"):
     """Penalised advection-diffusion (eq. penalization) by the LS iteration
     (eq. iter, solved in Fourier by eq. fft_solute with the symbols of
     eq. fft_app; derivative="spectral" takes the exact symbols instead).
@@ -300,8 +321,21 @@ def transport_ls(H, u, g, Pe, A0=0.55, B0=None, eta=0.01, diffusivity=1.0,
     finite dt: n_steps backward-Euler steps of d chi/dt + [operator] = calF,
     each solved by the LS iteration with comparison symbol
     1/dt + A0 L + i B0 . s.
+    form="central" (the literal reading): the diffusive term of the residual
+    is the central divergence of (A - A0)(grad_c chi + g), so the fixed point
+    keeps an O(h^2) term A0 (L - |s|^2) chi.  form="flux": the diffusive flux
+    through the face between x and x + h e_c is A_f (D+_c chi + g_c) with the
+    face's harmonic-mean diffusivity A_f and the forward difference D+, and
+    its divergence is the backward difference D-; since -D-.(A0 D+) has the
+    symbol A0 L of the comparison medium exactly, A0 drops out of the fixed
+    point, and the diffusive part of the operator conserves mass exactly.
+    The advective term B . (grad_c chi + g) keeps the central gradient in both.
     Returns chi, grad chi, per-step iteration counts and the status.
     """
+    if form not in ("central", "flux"):
+        raise ValueError("form must be 'central' or 'flux'")
+    if form == "flux" and derivative != "central":
+        raise ValueError("the flux form is built on difference operators (derivative='central')")
     H = np.asarray(H)
     shape = H.shape
     d = len(shape)
@@ -339,8 +373,12 @@ def transport_ls(H, u, g, Pe, A0=0.55, B0=None, eta=0.01, diffusivity=1.0,
         for it in range(1, max_iter + 1):
             # Step 1: residual F^n in real space
             e = grad + gvec.reshape((d,) + (1,) * d)
-            tau_f = (A - A0) * e
-            div_tau = _ifft(div_spectral_hat(np.stack([_fft(tau_f[c]) for c in range(d)]), s))
+            if form == "flux":
+                div_tau = sum(backward_diff((face_harmonic_mean(A, c) - A0)
+                                            * (forward_diff(chi, c) + gvec[c]), c) for c in range(d))
+            else:
+                tau_f = (A - A0) * e
+                div_tau = _ifft(div_spectral_hat(np.stack([_fft(tau_f[c]) for c in range(d)]), s))
             F = calF + div_tau - sum((Bf[c] - B0[c]) * e[c] for c in range(d))
             # Step 2: solve eq. iter in Fourier (eq. fft_solute)
             num = _fft(F) - B0g_hat + inv_dt * chi_m_hat
@@ -492,13 +530,18 @@ def brute_force_stokes(H, g, nu=1.0):
 
 
 def brute_force_transport(H, u, g, Pe, A0=0.55, eta=0.01, diffusivity=1.0,
-                          dt=math.inf, chi_prev=None):
+                          dt=math.inf, chi_prev=None, form="central"):
     """Fixed point of the LS iteration as one sparse linear system.
 
     Substituting the symbols of eq. fft_app into eq. iter gives, in real space,
       A0 (-Delta_h - div_c grad_c) chi - div_c(A (grad_c chi + g))
         + B . (grad_c chi + g) [+ (chi - chi_prev)/dt] = calF,
-    independent of B0.  Steady: bordered with the mean-zero constraint.
+    independent of B0 (form="central").  form="flux":
+      - sum_c D-_c (A_f,c (D+_c chi + g_c)) + B . (grad_c chi + g)
+        [+ (chi - chi_prev)/dt] = calF,
+    with forward and backward difference matrices and the face harmonic
+    means, independent of A0 and B0.  Steady: bordered with the mean-zero
+    constraint.
     """
     H = np.asarray(H)
     shape = H.shape
@@ -511,13 +554,24 @@ def brute_force_transport(H, u, g, Pe, A0=0.55, eta=0.01, diffusivity=1.0,
     Bf = [Pe * (1.0 - Hf) * u[c].ravel() for c in range(nd)]
     ubar = pore_mean_velocity(H, u)
     calF = Pe * (1.0 - Hf) * float(sum(ubar[c] * g[c] for c in range(nd)))
-    DivGrad = sum(G[c] @ G[c] for c in range(nd))
-    Op = A0 * (Lap + DivGrad)
-    Adiag = sp.diags(A)
     rhs = calF.copy()
-    for c in range(nd):
-        Op = Op - G[c] @ (Adiag @ G[c]) + sp.diags(Bf[c]) @ G[c]
-        rhs = rhs + G[c] @ (A * float(g[c])) - Bf[c] * float(g[c])
+    if form == "flux":
+        Op = sp.csr_matrix((n, n))
+        for c in range(nd):
+            N = shape[nd - 1 - c]
+            Ieye = sp.identity(n, format="csr")
+            Dp = (_shift_matrix(shape, c, 1) - Ieye) * N
+            Dm = (Ieye - _shift_matrix(shape, c, -1)) * N
+            Af = face_harmonic_mean(A.reshape(shape), c).ravel()
+            Op = Op - Dm @ (sp.diags(Af) @ Dp) + sp.diags(Bf[c]) @ G[c]
+            rhs = rhs + Dm @ (Af * float(g[c])) - Bf[c] * float(g[c])
+    else:
+        DivGrad = sum(G[c] @ G[c] for c in range(nd))
+        Op = A0 * (Lap + DivGrad)
+        Adiag = sp.diags(A)
+        for c in range(nd):
+            Op = Op - G[c] @ (Adiag @ G[c]) + sp.diags(Bf[c]) @ G[c]
+            rhs = rhs + G[c] @ (A * float(g[c])) - Bf[c] * float(g[c])
     if math.isfinite(dt):
         Op = Op + sp.identity(n) / dt
         cp = np.zeros(n) if chi_prev is None else np.asarray(chi_prev, dtype=np.float64).ravel()
@@ -552,10 +606,11 @@ def poiseuille_profile(n_rows, solid_rows, g=1.0, nu=1.0):
     return u
 
 
-def diffusion_mode_amplitude(shape, mode, dt, n_steps, A0):
+def diffusion_mode_amplitude(shape, mode, dt, n_steps, A0, form="central"):
     """Amplitude after n backward-Euler steps of a single cosine mode with
     H = 0, Pe = 0: (1 + dt lambda)^(-n), lambda = (1-A0)|s|^2 + A0 L under
-    the central/compact symbols of eq. fft_app."""
+    the central/compact symbols of eq. fft_app, or lambda = L in the flux
+    form (-D- D+ has the symbol L)."""
     nd = len(shape)
     s2 = 0.0
     Lm = 0.0
@@ -564,5 +619,5 @@ def diffusion_mode_amplitude(shape, mode, dt, n_steps, A0):
         th = 2.0 * np.pi * mode[c] / N
         s2 += (np.sin(th) * N) ** 2
         Lm += 4.0 * np.sin(th / 2.0) ** 2 * N * N
-    lam = (1.0 - A0) * s2 + A0 * Lm
+    lam = Lm if form == "flux" else (1.0 - A0) * s2 + A0 * Lm
     return (1.0 + dt * lam) ** (-n_steps)
