@@ -132,6 +132,17 @@ typedef struct {
                            form 1); the first 64 iterations, and an iteration
                            after a change of b, are in form 1.
                            Form 2 needs pass mode 2, 4 or 5 (ACM_E_INVALID otherwise). */
+  int32_t transport_form; /* transport: 0 the literal form (Section 3.2 with the
+                           central symbols: the divergence of (A - A0)(grad chi +
+                           g) by central differences, so A0 leaves an O(h^2) term
+                           in the fixed point); 1 the flux form: the diffusive
+                           flux through each face is A_f (D+ chi + g) with the
+                           forward difference D+ and the harmonic mean A_f of the
+                           two voxels' diffusivities, its divergence the backward
+                           difference, so the fixed point does not depend on A0
+                           or B0 and pure diffusion conserves solute mass exactly
+                           (advection keeps the central gradient).  Form 1 needs
+                           derivative 0 and runs the row form of the passes. */
 } acm_opts;
 
 /* Kernel kinds reported in acm_stats.kernel_ms (with opts.profile = 1).  Each
@@ -173,7 +184,7 @@ void acm_default_opts(acm_opts* o);
  * the next call on the same thread. */
 const char* acm_last_error(void);
 
-/* ABI version (incremented on any signature or struct change): 5. */
+/* ABI version (incremented on any signature or struct change): 6. */
 int32_t acm_version(void);
 
 /*

@@ -31,7 +31,8 @@ class acm_opts(C.Structure):
     _fields_ = [("eps", C.c_double), ("max_iter", C.c_int64), ("precision", C.c_int32),
                 ("check_every", C.c_int32), ("warm_start", C.c_int32), ("use_graph", C.c_int32),
                 ("profile", C.c_int32), ("history_cap", C.c_int32), ("pass_mode", C.c_int32),
-                ("green_variant", C.c_int32), ("derivative", C.c_int32), ("step1_form", C.c_int32)]
+                ("green_variant", C.c_int32), ("derivative", C.c_int32), ("step1_form", C.c_int32),
+                ("transport_form", C.c_int32)]
 
 
 class acm_stats(C.Structure):
@@ -90,7 +91,7 @@ SIGNATURES = {
 _lib = None
 
 
-ABI_VERSION = 5  # must equal acm_version() of the loaded library
+ABI_VERSION = 6  # must equal acm_version() of the loaded library
 
 
 def load(path: str = LIB_PATH):

@@ -231,10 +231,14 @@ def acm_transport_step(H: torch.Tensor, u: torch.Tensor, g_chi, Pe: float, *,
                        B0=(0.0, 0.0, 0.0), dt: float = math.inf, n_steps: int = 1,
                        eps: float = 1e-6, max_iter: int = 1_000_000, chi: torch.Tensor | None = None,
                        check_every: int = 0, use_graph: bool = True, profile: bool = False,
-                       derivative: str = "central", stream=None) -> dict:
+                       derivative: str = "central", form: str = "central", stream=None) -> dict:
     """Penalised advection-diffusion by the LS iteration (acm_transport_step).
     u: flow field (d, *shape) in the working precision.  chi (optional) holds
-    the initial value and receives the result.  Returns dict(chi, status, stats)."""
+    the initial value and receives the result.  form: "central" (the literal
+    discretisation) or "flux" (face fluxes with harmonic-mean diffusivity;
+    acm_opts.transport_form = 1).  Returns dict(chi, status, stats)."""
+    if form not in ("central", "flux"):
+        raise ValueError(f"form must be 'central' or 'flux', not {form!r}")
     lib = abi.load()
     _check_H(H)
     shape = tuple(H.shape)
@@ -245,7 +249,7 @@ def acm_transport_step(H: torch.Tensor, u: torch.Tensor, g_chi, Pe: float, *,
     _expect(chi, shape, u.dtype, "chi")
     opts = default_opts(eps=eps, max_iter=max_iter, precision=_prec(u.dtype),
                         check_every=check_every, use_graph=int(use_graph), profile=int(profile),
-                        derivative=_deriv(derivative))
+                        derivative=_deriv(derivative), transport_form=1 if form == "flux" else 0)
     st = abi.acm_stats()
     gr = _grid(shape)
     d = len(shape)

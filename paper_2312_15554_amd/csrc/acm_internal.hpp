@@ -129,7 +129,7 @@ struct TransportCtl {
   double calF;          // Pe * ubar . g  (multiplied by (1-H) per voxel)
   int64_t max_iter;
   int32_t steady;
-  int32_t pad_;
+  int32_t flux;         // flux form of the diffusive term (face harmonic means, D+ / D-)
   TransportState st[2];
   alignas(256) uint32_t counter;  // on its own cache line (see StokesCtl)
 };
@@ -269,11 +269,12 @@ hipError_t launch_stokes_rhs(const Geom& g, const DevTables<T>& tb, const Stokes
 // `par`: iteration parity.  judge = 1: the last workgroup applies the stop
 // test (writes slot par ^ 1); judge = 0: only the partial sums are posted and
 // the next slab pass judges them.
+// flux = 1: flux form (row input form only; see k_transport_green).
 template <typename T>
 hipError_t launch_transport_green(const Geom& g, const DevTables<T>& tb, int mode, void* spec,
                                   void* chat, const void* chat_m, double* partials,
                                   TransportCtl* ctl, int slab, int par, int judge,
-                                  hipStream_t s);
+                                  hipStream_t s, int flux = 0);
 // Slab form of the local pass (3D, nx == ny <= 128, u 16-byte aligned): reads
 // grad chi-hat from fields 0..2 and writes G_x, G_y, f_z (fields 0..2) and
 // tau_z (field 3) for the green pass's slab input form (slab = 1).
@@ -286,10 +287,11 @@ hipError_t launch_transport_slab(const Geom& g, const DevTables<T>& tb, void* sp
                                  int ngreen, int par, hipStream_t s);
 template <typename T>
 hipError_t launch_transport_local(const Geom& g, const DevTables<T>& tb, void* spec, const T* u,
-                                  const uint8_t* H, const TransportCtl* ctl, hipStream_t s);
+                                  const uint8_t* H, const TransportCtl* ctl, hipStream_t s,
+                                  int flux = 0);
 // Green workgroups per cell (= partial-sum records) for the row (slab = false)
-// or slab input form.
-int transport_green_blocks(const Geom& g, int precision_bytes, bool slab);
+// or slab input form, or the flux form (row input form).
+int transport_green_blocks(const Geom& g, int precision_bytes, bool slab, bool flux = false);
 
 // FP64 reductions (per-block partials; the host adds them in order).
 template <typename T>

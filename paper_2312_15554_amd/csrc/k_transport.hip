@@ -20,6 +20,7 @@ namespace acm {
 struct TGreenGeom {
   int dim;
   int nx, xh;
+  int ny, nz;
   int plane;
   int64_t nspec;
   int64_t ntot;
@@ -39,22 +40,28 @@ using TGCfg = ColCfg<T, L, NC, kTGVar, kTGSpl>;
 // fields) and f-hat; the slab form (SL) brings S = G_x + G_y + f_z as three
 // partial spectra (fields 0, 1, 4), summed on load, and tau_z (field 3; see
 // k_transport_slab).
+// Flux form (FL, row form only): the inputs are the spectra of the face
+// fluxes tau_c = (A_f,c - A0)(D+_c chi + g_c) and of f, whose divergence takes
+// the backward-difference symbol (1 - e^{-i theta_c})/h_c = l_c h_c/2 + i s_c;
+// the outputs are the central gradient (advection) and the forward difference
+// D+_c chi-hat = (i s_c - l_c h_c/2) chi-hat (2 D fields).
 template <int D, bool SL>
 constexpr int tg_inputs() { return SL ? 2 : D + 1; }
-template <int D, bool SL>
-constexpr int tg_fields() { return SL ? D : D + 1; }
+template <int D, bool SL, bool FL = false>
+constexpr int tg_fields() { return FL ? 2 * D : (SL ? D : D + 1); }
 
 // MODE 0: LS update.  MODE 1: only form grad chi-hat from chi-hat (set-up).
-template <typename T, int L, int D, int MODE, bool SL>
-__global__ __launch_bounds__((TGCfg<T, L, tg_fields<D, SL>()>::NT)) void k_transport_green(
+template <typename T, int L, int D, int MODE, bool SL, bool FL>
+__global__ __launch_bounds__((TGCfg<T, L, tg_fields<D, SL, FL>()>::NT)) void k_transport_green(
     cplx<T>* __restrict__ spec, cplx<T>* __restrict__ chat, const cplx<T>* __restrict__ chat_m,
     double* __restrict__ partials, TransportCtl* ctl, TGreenGeom gg, int par, int judge,
     const cplx<T>* __restrict__ tw, const T* __restrict__ sx, const T* __restrict__ lx,
     const T* __restrict__ sy, const T* __restrict__ ly, const T* __restrict__ sz,
     const T* __restrict__ lz) {
-  using C = TGCfg<T, L, tg_fields<D, SL>()>;
+  using C = TGCfg<T, L, tg_fields<D, SL, FL>()>;
   constexpr int PS = L * C::TX;
   constexpr int NIN = tg_inputs<D, SL>();
+  constexpr int NOUT = FL ? 2 * D : D;
   extern __shared__ __align__(16) char smem_raw[];
   __shared__ double red[2 * 16];
   __shared__ int s_last;
@@ -126,6 +133,13 @@ __global__ __launch_bounds__((TGCfg<T, L, tg_fields<D, SL>()>::NT)) void k_trans
       s[2] = sz[kz];
       Lk += lz[kz];
     }
+    // l_c h_c / 2: real part of the backward-difference symbol (flux form)
+    T lh[D];
+    if constexpr (FL) {
+      lh[0] = lx[kx] * T(0.5 / gg.nx);
+      lh[1] = ly[ky] * T(0.5 / gg.ny);
+      if constexpr (D == 3) lh[2] = lz[kz] * T(0.5 / gg.nz);
+    }
     const int64_t mi = (int64_t)i * P + f;
     cplx<T> cn;
     if constexpr (MODE == 0) {
@@ -148,6 +162,10 @@ __global__ __launch_bounds__((TGCfg<T, L, tg_fields<D, SL>()>::NT)) void k_trans
           const cplx<T> tc = lds[c * PS + e];
           F.x -= s[c] * tc.y;
           F.y += s[c] * tc.x;
+          if constexpr (FL) {
+            F.x += lh[c] * tc.x;
+            F.y += lh[c] * tc.y;
+          }
         }
       }
       if (k0) {
@@ -178,18 +196,23 @@ __global__ __launch_bounds__((TGCfg<T, L, tg_fields<D, SL>()>::NT)) void k_trans
     } else {
       cn = chat[mi];
     }
-    // grad chi-hat / N = i s chi-hat / N
+    // grad chi-hat / N = i s chi-hat / N (and D+ chi-hat / N in the flux form)
 #pragma unroll
-    for (int c = 0; c < D; ++c) lds[c * PS + e] = cmake<T>(-s[c] * cn.y * inv_ntot, s[c] * cn.x * inv_ntot);
+    for (int c = 0; c < D; ++c) {
+      lds[c * PS + e] = cmake<T>(-s[c] * cn.y * inv_ntot, s[c] * cn.x * inv_ntot);
+      if constexpr (FL)
+        lds[(D + c) * PS + e] = cmake<T>((-s[c] * cn.y - lh[c] * cn.x) * inv_ntot,
+                                         (s[c] * cn.x - lh[c] * cn.y) * inv_ntot);
+    }
   }
   __syncthreads();
   if constexpr (kTGSpl)
-    PencilFFT<T, L, 1, 1>::run_lds(t, act && fc < D, lds + (fc < D ? fc : 0) * PS + colt, PS, C::TX,
-                                   tw);
+    PencilFFT<T, L, 1, 1>::run_lds(t, act && fc < NOUT, lds + (fc < NOUT ? fc : 0) * PS + colt, PS,
+                                   C::TX, tw);
   else
-    PencilFFT<T, L, D, 1>::run_lds(t, act, lds + colt, PS, C::TX, tw);
+    PencilFFT<T, L, NOUT, 1>::run_lds(t, act, lds + colt, PS, C::TX, tw);
   __syncthreads();
-  for (int e = threadIdx.x; e < D * PS; e += C::NT) {
+  for (int e = threadIdx.x; e < NOUT * PS; e += C::NT) {
     const int c = e / PS, rem = e - c * PS;
     const int i = rem / C::TX, col = rem - i * C::TX;
     const int f = f0 + col;
@@ -229,12 +252,18 @@ __global__ __launch_bounds__((TGCfg<T, L, tg_fields<D, SL>()>::NT)) void k_trans
   }
 }
 
-template <typename T, int M, int D>
-__global__ __launch_bounds__((RowCfgN<T, M, D + 1>::NT)) void k_transport_local(
+// FL: flux form.  The row brings the central gradient (fields 0..D-1) and the
+// forward difference D+ chi (fields D..2D-1); tau_c is the flux through the
+// face between x and x + h e_c, (A_f,c - A0)(D+_c chi + g_c), with A_f,c the
+// harmonic mean of A on the two sides (H of the neighbour is read from
+// memory: along y and z it lies in another row).
+template <typename T, int M, int D, bool FL>
+__global__ __launch_bounds__((RowCfgN<T, M, FL ? 2 * D : D + 1>::NT)) void k_transport_local(
     cplx<T>* __restrict__ spec, const T* __restrict__ u, const uint8_t* __restrict__ H,
-    const TransportCtl* __restrict__ ctl, int nrows, int64_t ntot, int64_t nspec,
+    const TransportCtl* __restrict__ ctl, int nrows, int ny, int nz, int64_t ntot, int64_t nspec,
     const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ rtw) {
-  using C = RowCfgN<T, M, D + 1>;
+  using C = RowCfgN<T, M, FL ? 2 * D : D + 1>;
+  constexpr int NIN = FL ? 2 * D : D;
   constexpr int NX = 2 * M;
   extern __shared__ __align__(16) char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -242,13 +271,13 @@ __global__ __launch_bounds__((RowCfgN<T, M, D + 1>::NT)) void k_transport_local(
   if (transport_done(ctl)) return;
   const int row0 = blockIdx.x * C::RB;
   const int nr = min(C::RB, nrows - row0);
-  for (int c = 0; c < D; ++c) {
+  for (int c = 0; c < NIN; ++c) {
     const cplx<T>* src = spec + c * nspec + (int64_t)row0 * (M + 1);
     for (int v = threadIdx.x; v < nr * (M + 1); v += C::NT) lds[c * C::FS + v] = src[v];
   }
   __syncthreads();
   const int row = threadIdx.x / C::TPP, t = threadIdx.x % C::TPP;
-  rows_c2r_lds<T, M, D>(lds, C::FS, row, t, row < nr, tw, rtw);
+  rows_c2r_lds<T, M, NIN>(lds, C::FS, row, t, row < nr, tw, rtw);
 
   const T g[3] = {(T)ctl->g[0], (T)ctl->g[1], (T)ctl->g[2]};
   const T B0[3] = {(T)ctl->B0[0], (T)ctl->B0[1], (T)ctl->B0[2]};
@@ -261,12 +290,34 @@ __global__ __launch_bounds__((RowCfgN<T, M, D + 1>::NT)) void k_transport_local(
     const bool solid = H[off + v] != 0;
     const T Aa = solid ? eta : dif;
     T fval = solid ? T(0) : calF;
+    if constexpr (FL) {
+      // neighbours x + h e_c of this voxel (row R = z ny + y of the cell)
+      const int R = row0 + r;
+      const int y = R % ny, z = R / ny;
+      int64_t nb[3];
+      nb[0] = off + (int64_t)r * NX + (x + 1 == NX ? 0 : x + 1);
+      nb[1] = ((int64_t)z * ny + (y + 1 == ny ? 0 : y + 1)) * NX + x;
+      nb[2] = ((int64_t)(z + 1 == nz ? 0 : z + 1) * ny + y) * NX + x;
+      T tau[D];
 #pragma unroll
-    for (int c = 0; c < D; ++c) {
-      const T e = ldsr[2 * c * C::FS + li] + g[c];
-      const T Bc = solid ? T(0) : Pe * u[c * ntot + off + v];
-      fval -= (Bc - B0[c]) * e;
-      ldsr[2 * c * C::FS + li] = (Aa - A0) * e;
+      for (int c = 0; c < D; ++c) {
+        const T e = ldsr[2 * c * C::FS + li] + g[c];
+        const T Bc = solid ? T(0) : Pe * u[c * ntot + off + v];
+        fval -= (Bc - B0[c]) * e;
+        const T An = H[nb[c]] != 0 ? eta : dif;
+        const T Af = T(2) * Aa * An / (Aa + An);
+        tau[c] = (Af - A0) * (ldsr[2 * (D + c) * C::FS + li] + g[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < D; ++c) ldsr[2 * c * C::FS + li] = tau[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const T e = ldsr[2 * c * C::FS + li] + g[c];
+        const T Bc = solid ? T(0) : Pe * u[c * ntot + off + v];
+        fval -= (Bc - B0[c]) * e;
+        ldsr[2 * c * C::FS + li] = (Aa - A0) * e;
+      }
     }
     ldsr[2 * D * C::FS + li] = fval;
   }
@@ -427,20 +478,22 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, N, N>::WPE_ONE))) void k_transport
 
 // ------------------------------------------------------------------ launchers
 template <typename T, int LL>
-static int tg_blocks(const Geom& g, bool slab) {
+static int tg_blocks(const Geom& g, bool slab, bool flux) {
   int tx;
   if (g.dim == 3)
-    tx = slab ? TGCfg<T, LL, tg_fields<3, true>()>::TX : TGCfg<T, LL, tg_fields<3, false>()>::TX;
+    tx = flux ? TGCfg<T, LL, tg_fields<3, false, true>()>::TX
+              : (slab ? TGCfg<T, LL, tg_fields<3, true>()>::TX
+                      : TGCfg<T, LL, tg_fields<3, false>()>::TX);
   else
-    tx = TGCfg<T, LL, tg_fields<2, false>()>::TX;
+    tx = flux ? TGCfg<T, LL, tg_fields<2, false, true>()>::TX : TGCfg<T, LL, tg_fields<2, false>()>::TX;
   return (int)((g.plane + tx - 1) / tx);
 }
 
-int transport_green_blocks(const Geom& g, int prec_bytes, bool slab) {
+int transport_green_blocks(const Geom& g, int prec_bytes, bool slab, bool flux) {
   switch (g.last_n) {
 #define CASE(LL) \
   case LL:       \
-    return prec_bytes == 8 ? tg_blocks<double, LL>(g, slab) : tg_blocks<float, LL>(g, slab);
+    return prec_bytes == 8 ? tg_blocks<double, LL>(g, slab, flux) : tg_blocks<float, LL>(g, slab, flux);
     ACM_COL_LENGTHS(CASE)
 #undef CASE
     default:
@@ -452,19 +505,20 @@ template <typename T>
 hipError_t launch_transport_green(const Geom& g, const DevTables<T>& tb, int mode, void* spec,
                                   void* chat, const void* chat_m, double* partials,
                                   TransportCtl* ctl, int slab, int par, int judge,
-                                  hipStream_t s) {
+                                  hipStream_t s, int flux) {
   const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
   const T* rt = tb.rtab;
-  TGreenGeom gg{g.dim, g.nx, g.xh, (int)g.plane, g.nspec, g.ntot};
+  if (flux && slab) return hipErrorInvalidValue;
+  TGreenGeom gg{g.dim, g.nx, g.xh, g.ny, g.nz, (int)g.plane, g.nspec, g.ntot};
   const cplx<T>* tw = ct + (g.dim == 3 ? tb.off.tw_z : tb.off.tw_y);
   auto* sp = reinterpret_cast<cplx<T>*>(spec);
   auto* cp = reinterpret_cast<cplx<T>*>(chat);
   auto* cm = reinterpret_cast<const cplx<T>*>(chat_m);
-#define LAUNCH_TG(LL, DD, MM, SLB)                                                           \
+#define LAUNCH_TG1(LL, DD, MM, SLB, FLX)                                                     \
   {                                                                                          \
-    using C = TGCfg<T, LL, tg_fields<DD, SLB>()>;                                            \
+    using C = TGCfg<T, LL, tg_fields<DD, SLB, FLX>()>;                                       \
     const int nb = (int)((g.plane + C::TX - 1) / C::TX);                                     \
-    ACM_LAUNCH((k_transport_green<T, LL, DD, MM, SLB>), dim3(nb), dim3(C::NT),               \
+    ACM_LAUNCH((k_transport_green<T, LL, DD, MM, SLB, FLX>), dim3(nb), dim3(C::NT),          \
                        C::LDS_BYTES, s, sp, cp, cm, partials, ctl, gg, par, judge,             \
                        tw,                                                                   \
                        rt + tb.off.sx,                                                       \
@@ -472,45 +526,54 @@ hipError_t launch_transport_green(const Geom& g, const DevTables<T>& tb, int mod
                        rt + tb.off.lz);                                                      \
   }
   switch (g.last_n) {
-#define CASE(LL)                            \
-  case LL:                                  \
-    if (g.dim == 3) {                       \
-      if (mode == 0 && slab) LAUNCH_TG(LL, 3, 0, true)      \
-      else if (mode == 0) LAUNCH_TG(LL, 3, 0, false)        \
-      else LAUNCH_TG(LL, 3, 1, false)                       \
-    } else {                                                \
-      if (mode == 0) LAUNCH_TG(LL, 2, 0, false)             \
-      else LAUNCH_TG(LL, 2, 1, false)                       \
-    }                                                       \
+#define CASE(LL)                                                      \
+  case LL:                                                            \
+    if (g.dim == 3) {                                                 \
+      if (mode == 0 && slab) LAUNCH_TG1(LL, 3, 0, true, false)        \
+      else if (mode == 0 && flux) LAUNCH_TG1(LL, 3, 0, false, true)   \
+      else if (mode == 0) LAUNCH_TG1(LL, 3, 0, false, false)          \
+      else if (flux) LAUNCH_TG1(LL, 3, 1, false, true)                \
+      else LAUNCH_TG1(LL, 3, 1, false, false)                         \
+    } else {                                                          \
+      if (mode == 0 && flux) LAUNCH_TG1(LL, 2, 0, false, true)        \
+      else if (mode == 0) LAUNCH_TG1(LL, 2, 0, false, false)          \
+      else if (flux) LAUNCH_TG1(LL, 2, 1, false, true)                \
+      else LAUNCH_TG1(LL, 2, 1, false, false)                         \
+    }                                                                 \
     return hipGetLastError();
     ACM_COL_LENGTHS(CASE)
 #undef CASE
     default:
       return hipErrorInvalidValue;
   }
-#undef LAUNCH_TG
+#undef LAUNCH_TG1
 }
 
 template <typename T>
 hipError_t launch_transport_local(const Geom& g, const DevTables<T>& tb, void* spec, const T* u,
-                                  const uint8_t* H, const TransportCtl* ctl, hipStream_t s) {
+                                  const uint8_t* H, const TransportCtl* ctl, hipStream_t s,
+                                  int flux) {
   const cplx<T>* ct = reinterpret_cast<const cplx<T>*>(tb.ctab);
   auto* sp = reinterpret_cast<cplx<T>*>(spec);
-#define LAUNCH_TL(MM, DD)                                                                     \
+#define LAUNCH_TL(MM, DD, FLX)                                                                \
   {                                                                                           \
-    using C = RowCfgN<T, MM, DD + 1>;                                                         \
+    using C = RowCfgN<T, MM, FLX ? 2 * DD : DD + 1>;                                          \
     dim3 grid((unsigned)((g.nrows + C::RB - 1) / C::RB));                                     \
-    ACM_LAUNCH((k_transport_local<T, MM, DD>), grid, dim3(C::NT), C::LDS_BYTES, s, sp, \
-                       u, H, ctl, (int)g.nrows, g.ntot, g.nspec, ct + tb.off.tw_x,            \
-                       ct + tb.off.rtw);                                                      \
+    ACM_LAUNCH((k_transport_local<T, MM, DD, FLX>), grid, dim3(C::NT), C::LDS_BYTES, s, sp,   \
+               u, H, ctl, (int)g.nrows, g.ny, g.nz, g.ntot, g.nspec, ct + tb.off.tw_x,        \
+               ct + tb.off.rtw);                                                              \
   }
   switch (g.nx / 2) {
 #define CASE(MM)                    \
   case MM:                          \
-    if (g.dim == 3)                 \
-      LAUNCH_TL(MM, 3)              \
+    if (g.dim == 3 && flux)         \
+      LAUNCH_TL(MM, 3, true)        \
+    else if (g.dim == 3)            \
+      LAUNCH_TL(MM, 3, false)       \
+    else if (flux)                  \
+      LAUNCH_TL(MM, 2, true)        \
     else                            \
-      LAUNCH_TL(MM, 2)              \
+      LAUNCH_TL(MM, 2, false)       \
     return hipGetLastError();
     ACM_ROW_LENGTHS(CASE)
 #undef CASE
@@ -547,13 +610,13 @@ hipError_t launch_transport_slab(const Geom& g, const DevTables<T>& tb, void* sp
 #define INST(T)                                                                              \
   template hipError_t launch_transport_green<T>(const Geom&, const DevTables<T>&, int, void*, \
                                                 void*, const void*, double*, TransportCtl*,  \
-                                                int, int, int, hipStream_t);                 \
+                                                int, int, int, hipStream_t, int);            \
   template hipError_t launch_transport_slab<T>(const Geom&, const DevTables<T>&, void*,       \
                                                const T*, const uint8_t*, TransportCtl*,      \
                                                const double*, int, int, hipStream_t);        \
   template hipError_t launch_transport_local<T>(const Geom&, const DevTables<T>&, void*,      \
                                                 const T*, const uint8_t*,                    \
-                                                const TransportCtl*, hipStream_t);
+                                                const TransportCtl*, hipStream_t, int);
 INST(float)
 INST(double)
 #undef INST

@@ -1044,14 +1044,21 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
   // passes; f arrives as d partial spectra)
   // (the slab form folds the x and y divergence in as central differences, so
   // the exact symbols take the row form)
-  const bool tslab = d == 3 && pl->deriv == 0 && slab_supported<T>(g) &&
+  // The flux form (face fluxes with harmonic-mean diffusivity) takes the row
+  // form: its green pass returns the central gradient and the forward
+  // difference (2 d fields).
+  const bool flux = o.transport_form == 1;
+  if (flux && pl->deriv != 0)
+    return fail(ACM_E_INVALID, "the flux form is built on differences: derivative must be 0");
+  const bool tslab = !flux && d == 3 && pl->deriv == 0 && slab_supported<T>(g) &&
                      ((uintptr_t)u % 16 == 0) && ((uintptr_t)H % 4 == 0);
   const size_t cb = sizeof(T) * 2;
   // slab form: a fifth field holds f_z (see k_transport_slab)
-  const size_t spec_b = cb * (size_t)g.nspec * (d + (tslab ? 2 : 1));
+  const size_t spec_b = cb * (size_t)g.nspec * (flux ? 2 * d : d + (tslab ? 2 : 1));
   const size_t one_b = cb * (size_t)g.nspec;
-  const int ngreen = std::max(transport_green_blocks(g, pl->prec, false),
-                              transport_green_blocks(g, pl->prec, tslab));
+  const int ngreen = std::max(std::max(transport_green_blocks(g, pl->prec, false),
+                                       transport_green_blocks(g, pl->prec, tslab)),
+                              transport_green_blocks(g, pl->prec, false, flux));
   const size_t part_b = sizeof(double) * 2 * (size_t)ngreen;
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   DevBuf ws;
@@ -1085,6 +1092,7 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
   c.calF = Pe * ubar_g;
   c.max_iter = o.max_iter;
   c.steady = steady ? 1 : 0;
+  c.flux = flux ? 1 : 0;
   c.st[0].status = 1;
   c.st[1] = c.st[0];
   HIP_TRY(hipMemcpyAsync(dctl, &c, sizeof(c), hipMemcpyHostToDevice, s));
@@ -1095,7 +1103,7 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
     if (e == hipSuccess) e = launch_cols<T>(g, tb, 1, -1, 1, chat, s);
     if (e == hipSuccess && d == 3) e = launch_cols<T>(g, tb, 2, -1, 1, chat, s);
     if (e == hipSuccess)
-      e = launch_transport_green<T>(g, tb, 1, spec, chat, chat_m, part, dctl, 0, 0, 1, s);
+      e = launch_transport_green<T>(g, tb, 1, spec, chat, chat_m, part, dctl, 0, 0, 1, s, flux);
     if (e != hipSuccess) return fail(ACM_E_HIP, std::string("set-up: ") + hipGetErrorString(e));
   }
 
@@ -1126,12 +1134,13 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
     }
     if (d == 3) {
       prof.begin(KK_YINV, &ev0);
-      e = launch_cols<T>(g, tb, 1, +1, d, spec, s, &dctl->st[0].done, &dctl->st[1].done);
+      e = launch_cols<T>(g, tb, 1, +1, flux ? 2 * d : d, spec, s, &dctl->st[0].done,
+                         &dctl->st[1].done);
       if (e != hipSuccess) return e;
       prof.end(KK_YINV, ev0);
     }
     prof.begin(KK_T_LOCAL, &ev0);
-    e = launch_transport_local<T>(g, tb, spec, u, H, dctl, s);
+    e = launch_transport_local<T>(g, tb, spec, u, H, dctl, s, flux);
     if (e != hipSuccess) return e;
     prof.end(KK_T_LOCAL, ev0);
     if (d == 3) {
@@ -1141,7 +1150,7 @@ static acm_status transport_impl(CellPlan* pl, const uint8_t* H, const T* u, con
       prof.end(KK_YFWD, ev0);
     }
     prof.begin(KK_T_GREEN, &ev0);
-    e = launch_transport_green<T>(g, tb, 0, spec, chat, chat_m, part, dctl, 0, par, 1, s);
+    e = launch_transport_green<T>(g, tb, 0, spec, chat, chat_m, part, dctl, 0, par, 1, s, flux);
     if (e != hipSuccess) return e;
     prof.end(KK_T_GREEN, ev0);
     return hipSuccess;
@@ -1671,7 +1680,7 @@ void acm_default_opts(acm_opts* o) {
 
 const char* acm_last_error(void) { return g_err.c_str(); }
 
-int32_t acm_version(void) { return 5; }
+int32_t acm_version(void) { return 6; }
 
 acm_status acm_stokes_solve(const acm_grid* grid, const uint8_t* H, const double* g_p, double nu,
                             const acm_penalty* pen, const acm_opts* opts, void* u, void* q,
@@ -1790,6 +1799,8 @@ acm_status acm_transport_step(const acm_grid* grid, const uint8_t* H, const void
   if (isfinite(dt) ? !(dt > 0.0) : !(dt > 0.0)) return fail(ACM_E_INVALID, "dt must be > 0 or +INFINITY");
   if (!isfinite(dt) && n_steps != 1) return fail(ACM_E_INVALID, "the steady problem takes n_steps = 1");
   if (!(O.eps >= 0.0) || O.max_iter < 1) return fail(ACM_E_INVALID, "eps >= 0 and max_iter >= 1 required");
+  if (O.transport_form != 0 && O.transport_form != 1)
+    return fail(ACM_E_INVALID, "transport_form must be 0 or 1");
   CellPlan* pl = nullptr;
   acm_status r = get_plan(grid, O.precision, &pl, O.derivative);
   if (r != ACM_OK) return r;

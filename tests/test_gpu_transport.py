@@ -198,3 +198,95 @@ def test_nan_flow_reports_divergence():
         acm_transport_step(dev(H), dev(u, torch.float32), (1.0, 0.0, 0.0), 5.0, A0=0.55,
                            B0=(1.0, 0.0, 0.0), eta=0.01, eps=1e-6, max_iter=3000)
     assert e.value.status == abi.ACM_E_DIVERGED
+
+
+# ------------------------------------------------------------ flux form (Section 3.2, second reading)
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("shape", [(16, 16), (8, 24), (16, 24, 32), (16, 32, 32), (8, 16, 64)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("dt", [math.inf, 5e-3])
+def test_flux_form_iterates_match_oracle(shape, dtype, dt):
+    """Flux form (face fluxes with harmonic-mean diffusivity, forward and
+    backward differences): chi after the same LS iterations as the oracle's
+    flux form, steady and time-stepped, 2D and 3D (a cube that would take
+    the slab form runs the row form here)."""
+    require_gpu()
+    from paper_2312_15554_amd.api import acm_transport_step
+    print(f"flux-form parity shape={shape} dtype={dtype} dt={dt}", flush=True)
+    d = len(shape)
+    H = I.random_mask(shape, 23, 0.3)
+    u = I.random_field((d,) + shape, 29) * (1 - H)
+    g = (0.3, 1.0, -0.5)[:d]
+    B0 = (0.6, 0.0, 0.1)[:d]
+    M, steps = 12, (1 if math.isinf(dt) else 3)
+    r = acm_transport_step(dev(H), dev(u, dtype), g, 4.0, A0=1.2, B0=B0, eta=0.05, dt=dt,
+                           n_steps=steps, eps=0.0, max_iter=M, form="flux")
+    o = O.transport_ls(H, u, g, 4.0, A0=1.2, B0=B0, eta=0.05, dt=dt, n_steps=steps, eps=0.0,
+                       max_iter=M, form="flux")
+    assert r["stats"]["iters"] == M * steps
+    tol = 1e-11 if dtype == torch.float64 else 3e-5
+    assert np.abs(host(r["chi"]) - o["chi"]).max() < tol * np.abs(o["chi"]).max()
+
+
+@pytest.mark.gpu
+def test_flux_form_fixed_point_matches_direct_solve_whatever_the_medium():
+    """Converged flux-form solves (FP64) with two comparison media equal the
+    sparse direct solve of the flux-form equations, which has no A0 in it."""
+    require_gpu()
+    from paper_2312_15554_amd.api import acm_transport_step
+    shape = (8, 16, 16)
+    H = I.random_mask(shape, 11, 0.3)
+    u = I.random_field((3,) + shape, 12) * (1 - H)
+    u = u / np.abs(u).max()
+    g = (0.0, 1.0, 0.0)
+    ref = O.brute_force_transport(H, u, g, 3.0, eta=0.02, form="flux")
+    for A0, B0 in ((1.1, (0.0, 0.0, 0.0)), (2.5, (0.3, -0.2, 0.1))):
+        r = acm_transport_step(dev(H), dev(u, torch.float64), g, 3.0, A0=A0, B0=B0, eta=0.02,
+                               eps=1e-12, max_iter=40000, form="flux")
+        assert r["stats"]["converged"]
+        assert np.abs(host(r["chi"]) - ref).max() < 1e-9 * np.abs(ref).max()
+
+
+@pytest.mark.gpu
+def test_flux_form_laminate_flux_and_mass_conservation():
+    """Voxel-aligned laminate across x, Pe = 0, g = e_x (FP64): the face flux
+    A_f (D+ chi + 1) equals the series conductance 1/mean(1/A) on every face.
+    Then, from a random chi with g = 0, backward-Euler steps keep the solute
+    mass to rounding."""
+    require_gpu()
+    from paper_2312_15554_amd.api import acm_effective_props, acm_transport_step
+    n = 16
+    x = np.arange(n)
+    H = np.zeros((8, 8, n), np.uint8)
+    H[:, :, x < n // 4] = 1
+    eta = 0.05
+    A = (1.0 - H) + eta * H
+    u = np.zeros((3,) + H.shape)
+    r = acm_transport_step(dev(H), dev(u, torch.float64), (1.0, 0.0, 0.0), 0.0, A0=1.0,
+                           B0=(0.0, 0.0, 0.0), eta=eta, eps=1e-13, max_iter=40000, form="flux")
+    assert r["stats"]["converged"]
+    chi = host(r["chi"])
+    J = O.face_harmonic_mean(A, 0) * (O.forward_diff(chi, 0) + 1.0)
+    assert np.abs(J - 1.0 / np.mean(1.0 / A[0, 0])).max() < 1e-9
+    Hm = I.random_mask((8, 16, 16), 3, 0.4)
+    chi0 = I.random_field(Hm.shape, 4)
+    c = dev(chi0, torch.float64)
+    m0 = float(c.sum())
+    acm_transport_step(dev(Hm), dev(np.zeros((3,) + Hm.shape), torch.float64), (0.0, 0.0, 0.0),
+                       0.0, A0=1.0, B0=(0.0, 0.0, 0.0), eta=0.01, dt=1e-3, n_steps=6, eps=1e-12,
+                       max_iter=20000, chi=c, form="flux")
+    assert abs(float(c.sum()) - m0) < 1e-12 * float(c.abs().sum())
+
+
+@pytest.mark.gpu
+def test_flux_form_refuses_exact_symbols():
+    require_gpu()
+    from paper_2312_15554_amd import abi
+    from paper_2312_15554_amd.api import acm_transport_step
+    H = np.zeros((16, 16), np.uint8)
+    H[:4] = 1
+    with pytest.raises(abi.AcmError) as e:
+        acm_transport_step(dev(H), dev(np.zeros((2, 16, 16)), torch.float32), (1.0, 0.0), 1.0,
+                           max_iter=10, derivative="spectral", form="flux")
+    assert e.value.status == abi.ACM_E_INVALID
