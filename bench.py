@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--fno-held", type=int, default=64,
                     help="held-out 64^3 cells of the batched + warm-started comparison")
     ap.add_argument("--no-256", action="store_true", help="skip the 256^3 section")
+    ap.add_argument("--no-scaling", action="store_true", help="skip the size-scaling section")
     ap.add_argument("--batch-cells", type=int, default=64)
     return ap.parse_args()
 
@@ -268,6 +269,44 @@ def fno_section(args, log, cells):
                 batched_warm_vs_plain_64=batched_warm, tests=tests, judge_fp64_eps1e10=tight,
                 iters_saved=[t["plain_iters"] - t["warm_iters"] for t in tests],
                 time_ratio_warm_over_plain=[t["warm_s"] / t["plain_s"] for t in tests])
+
+
+def scaling_section(log):
+    """Size scaling on the whole chip, the one-GPU counterpart of the paper's
+    scaling study (Section 4): the 2D model cell (disc of radius 0.2 L) at
+    128^2 ... 1024^2 and 3D overlapping-sphere cells (porosity 0.40, radius
+    N/16) at 32^3 ... 256^3, FP32, a fixed number of ADMM iterations each
+    (the captured-graph loop, adaptive penalties).  Reported: time per
+    iteration and voxel-iterations/s; at fixed work per CU the paper's weak
+    scaling corresponds to constant voxel-iterations/s per CU."""
+    import torch
+    from paper_2312_15554_amd import inputs as I
+    from paper_2312_15554_amd.api import acm_stokes_solve
+    rows = []
+    for dim, ns, iters in ((2, (128, 256, 512, 1024), 4000), (3, (32, 64, 128, 256), 600)):
+        for n in ns:
+            if dim == 2:
+                Hn = I.centred_disc(n, 0.2)
+            else:
+                Hn = I.overlapping_spheres(n, n / 16.0, 0.40, seed=1)
+            H = torch.from_numpy(Hn).cuda()
+            g = (1.0, 0.0, 0.0)[:dim]
+            kw = dict(penalty=dict(tau=(5.0, 10.0, 5.0)), eps=0.0, want_q=False)
+            acm_stokes_solve(H, g, max_iter=400, **kw)  # tunes the plan
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = acm_stokes_solve(H, g, max_iter=iters, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            vox = Hn.size
+            rows.append(dict(dim=dim, n=n, voxels=vox, iterations=r["stats"]["iters"],
+                             iter_us=round(dt / iters * 1e6, 2),
+                             voxel_iters_per_s=vox * iters / dt,
+                             voxels_per_cu=vox / 256.0))
+            log(f"scaling: {dim}D {n}: {rows[-1]['iter_us']} us per iteration, "
+                f"{rows[-1]['voxel_iters_per_s'] / 1e9:.2f} G voxel-iter/s")
+            del H, r
+    return rows
 
 
 def stokes256_section(log):
@@ -583,6 +622,9 @@ def main():
     s256 = None
     if not args.no_256 and not args.fixed_iters:
         s256 = stokes256_section(log)
+    scaling = None
+    if not args.no_scaling and not args.fixed_iters:
+        scaling = scaling_section(log)
     transport = None
     if not args.no_transport and not args.fixed_iters:
         transport = transport_section(H, us[0], log)
@@ -620,6 +662,7 @@ def main():
         "cpu_baseline": cpu,
         "directions_batched": dirs_batched,
         "stokes_256": s256,
+        "size_scaling": scaling,
         "transport": transport,
         "batched": batched,
         "fno_warm_start": fno,

@@ -26,8 +26,8 @@ namespace acm {
 
 // Supported lengths.  Row kernels take the complex half length M = nx/2,
 // column kernels the full axis length.
-#define ACM_ROW_LENGTHS(X) X(4) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(256)
-#define ACM_COL_LENGTHS(X) X(8) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(512)
+#define ACM_ROW_LENGTHS(X) X(4) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(256) X(512)
+#define ACM_COL_LENGTHS(X) X(8) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(512) X(1024)
 
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }

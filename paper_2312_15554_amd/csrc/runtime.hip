@@ -85,11 +85,11 @@ static bool make_geom(const acm_grid* grid, Geom* g, const char** why) {
 }
 
 static const char* const kUnsupportedSizeMsg =
-    "grid lengths must be in {8,16,24,32,48,64,96,128,192,256,512} (nx <= 512)";
+    "grid lengths must be in {8,16,24,32,48,64,96,128,192,256,512,1024}";
 
 static bool size_supported(const Geom& g) {
   auto ok = [](int n) { return fft_length_supported(n); };
-  if (!ok(g.nx) || g.nx > 512 || !ok(g.ny)) return false;
+  if (!ok(g.nx) || !ok(g.ny)) return false;
   if (g.dim == 3 && !ok(g.nz)) return false;
   return true;
 }

@@ -23,7 +23,8 @@ def _solve(H, g, **kw):
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("shape", [(16, 16), (24, 32), (8, 24, 16), (16, 16, 16), (24, 16, 48),
-                                   (8, 16, 256), (8, 256, 16), (256, 16, 8), (16, 256)])
+                                   (8, 16, 256), (8, 256, 16), (256, 16, 8), (16, 256),
+                                   (16, 1024), (1024, 16)])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_fixed_penalty_iterates_match_oracle(shape, dtype):
     """Same fixed penalties, same number of iterations: u and the six
