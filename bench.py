@@ -52,6 +52,7 @@ def parse():
                     help="held-out 64^3 cells of the batched + warm-started comparison")
     ap.add_argument("--no-256", action="store_true", help="skip the 256^3 section")
     ap.add_argument("--no-scaling", action="store_true", help="skip the size-scaling section")
+    ap.add_argument("--no-sweeps", action="store_true", help="skip the parameter sweeps")
     ap.add_argument("--batch-cells", type=int, default=64)
     return ap.parse_args()
 
@@ -625,6 +626,10 @@ def main():
     scaling = None
     if not args.no_scaling and not args.fixed_iters:
         scaling = scaling_section(log)
+    sweeps = None
+    if not args.no_sweeps and not args.fixed_iters:
+        from paper_2312_15554_amd import sweeps as SW
+        sweeps = SW.run_all(log=log)
     transport = None
     if not args.no_transport and not args.fixed_iters:
         transport = transport_section(H, us[0], log)
@@ -663,6 +668,7 @@ def main():
         "directions_batched": dirs_batched,
         "stokes_256": s256,
         "size_scaling": scaling,
+        "sweeps": sweeps,
         "transport": transport,
         "batched": batched,
         "fno_warm_start": fno,
