@@ -127,7 +127,7 @@ struct Dft;
 
 template <int SIGN, typename T>
 struct Dft<2, SIGN, T> {
-  __device__ static void run(cplx<T>* v) {
+  __device__ __forceinline__ static void run(cplx<T>* v) {
     cplx<T> a = v[0], b = v[1];
     v[0] = cadd(a, b);
     v[1] = csub(a, b);
@@ -136,7 +136,7 @@ struct Dft<2, SIGN, T> {
 
 template <int SIGN, typename T>
 struct Dft<3, SIGN, T> {
-  __device__ static void run(cplx<T>* v) {
+  __device__ __forceinline__ static void run(cplx<T>* v) {
     const T c1 = T(-0.5);
     const T s1 = T(SIGN) * T(0.86602540378443864676372317075293618);
     cplx<T> a = v[0], b = v[1], c = v[2];
@@ -153,7 +153,7 @@ struct Dft<3, SIGN, T> {
 
 template <int SIGN, typename T>
 struct Dft<4, SIGN, T> {
-  __device__ static void run(cplx<T>* v) {
+  __device__ __forceinline__ static void run(cplx<T>* v) {
     cplx<T> a0 = cadd(v[0], v[2]);
     cplx<T> a1 = csub(v[0], v[2]);
     cplx<T> b0 = cadd(v[1], v[3]);
@@ -167,7 +167,7 @@ struct Dft<4, SIGN, T> {
 
 template <int SIGN, typename T>
 struct Dft<8, SIGN, T> {
-  __device__ static void run(cplx<T>* v) {
+  __device__ __forceinline__ static void run(cplx<T>* v) {
     const T r2 = T(0.70710678118654752440084436210484904);
     // split even/odd radix-4
     cplx<T> e[4] = {v[0], v[2], v[4], v[6]};
@@ -207,16 +207,16 @@ struct PencilFFT {
   struct LdsLoad {
     const cplx<T>* lds;
     int pstride, estride;
-    __device__ cplx<T> operator()(int p, int i) const { return lds[p * pstride + i * estride]; }
+    __device__ __forceinline__ cplx<T> operator()(int p, int i) const { return lds[p * pstride + i * estride]; }
   };
   struct LdsStore {
     cplx<T>* lds;
     int pstride, estride;
-    __device__ void operator()(int p, int i, cplx<T> v) const { lds[p * pstride + i * estride] = v; }
+    __device__ __forceinline__ void operator()(int p, int i, cplx<T> v) const { lds[p * pstride + i * estride] = v; }
   };
 
   template <int S, class LoadF, class StoreF>
-  __device__ static void stage(int t, bool active, cplx<T>* lds, int pstride, int estride,
+  __device__ __forceinline__ static void stage(int t, bool active, cplx<T>* lds, int pstride, int estride,
                                const cplx<T>* __restrict__ tw, const LoadF& load, const StoreF& store) {
     constexpr int R = PL::radix(S);
     constexpr int NS = PL::ns(S);
@@ -287,13 +287,13 @@ struct PencilFFT {
   // Generic entry: first stage reads via load, last stage writes via store,
   // intermediate stages use the LDS pencils.
   template <class LoadF, class StoreF>
-  __device__ static void run(int t, bool active, cplx<T>* lds, int pstride, int estride,
+  __device__ __forceinline__ static void run(int t, bool active, cplx<T>* lds, int pstride, int estride,
                              const cplx<T>* __restrict__ tw, const LoadF& load, const StoreF& store) {
     stage<0>(t, active, lds, pstride, estride, tw, load, store);
   }
 
   // In-place on LDS pencils.
-  __device__ static void run_lds(int t, bool active, cplx<T>* lds, int pstride, int estride,
+  __device__ __forceinline__ static void run_lds(int t, bool active, cplx<T>* lds, int pstride, int estride,
                                  const cplx<T>* __restrict__ tw) {
     LdsLoad ld{lds, pstride, estride};
     LdsStore st{lds, pstride, estride};
@@ -329,7 +329,7 @@ struct RegFFT {
 
   // LDS exchange buffer: pencil p element i at lds[p*pstride + i*estride].
   template <int S>
-  __device__ static void stage(int t, bool active, cplx<T> (&v)[NP][EPT], cplx<T>* lds,
+  __device__ __forceinline__ static void stage(int t, bool active, cplx<T> (&v)[NP][EPT], cplx<T>* lds,
                                int pstride, int estride, const cplx<T>* __restrict__ tw) {
     constexpr int R = PL::radix(S);
     constexpr int NS = PL::ns(S);
@@ -395,7 +395,7 @@ struct RegFFT {
 
   // The whole workgroup calls run() together; it contains workgroup barriers
   // (and ends with none: the caller synchronises before reusing `lds`).
-  __device__ static void run(int t, bool active, cplx<T> (&v)[NP][EPT], cplx<T>* lds,
+  __device__ __forceinline__ static void run(int t, bool active, cplx<T> (&v)[NP][EPT], cplx<T>* lds,
                              int pstride, int estride, const cplx<T>* __restrict__ tw) {
     stage<0>(t, active, v, lds, pstride, estride, tw);
   }

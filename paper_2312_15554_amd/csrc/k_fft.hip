@@ -30,16 +30,19 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_rows_r2c(const T* __rest
   const int field = blockIdx.y;
   const int row0 = blockIdx.x * C::RB;
   const int nr = min(C::RB, nrows - row0);
-  const T* src = in + field * ntot + (int64_t)row0 * (2 * M);
-  for (int v = threadIdx.x; v < nr * 2 * M; v += C::NT) {
-    const int r = v / (2 * M), x = v - r * (2 * M);
-    ldsr[r * 2 * C::RP + x] = src[v];
-  }
+  const gmem<T>* src = as_global(in + field * ntot + (int64_t)row0 * (2 * M));
+  batched_copy<T, C::NT, C::RB * 2 * M>(
+      nr * 2 * M, [&](int v) { return src[v]; },
+      [&](int v, T x) {
+        const int r = v / (2 * M);
+        ldsr[r * 2 * C::RP + (v - r * 2 * M)] = x;
+      });
   __syncthreads();
   const int row = threadIdx.x / C::TPP, t = threadIdx.x % C::TPP;
   rows_r2c_lds<T, M>(lds, 0, row, t, row < nr, tw, rtw);
-  cplx<T>* dst = out + field * nspec + (int64_t)row0 * (M + 1);
-  for (int v = threadIdx.x; v < nr * (M + 1); v += C::NT) dst[v] = lds[v];
+  gmem<cplx<T>>* dst = as_global(out + field * nspec + (int64_t)row0 * (M + 1));
+  scatter_from_lds<cplx<T>, C::NT, C::RB * (M + 1)>(lds, nr * (M + 1),
+                                                    [&](int v, const cplx<T>& x) { dst[v] = x; });
 }
 
 template <typename T, int M>
@@ -56,8 +59,8 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_rows_c2r(const cplx<T>* 
   const int field = blockIdx.y;
   const int row0 = blockIdx.x * C::RB;
   const int nr = min(C::RB, nrows - row0);
-  const cplx<T>* src = in + field * nspec + (int64_t)row0 * (M + 1);
-  for (int v = threadIdx.x; v < nr * (M + 1); v += C::NT) lds[v] = src[v];
+  const gmem<cplx<T>>* src = as_global(in + field * nspec + (int64_t)row0 * (M + 1));
+  gather_to_lds<cplx<T>, C::NT, C::RB * (M + 1)>(lds, nr * (M + 1), [&](int v) { return src[v]; });
   __syncthreads();
   const int row = threadIdx.x / C::TPP, t = threadIdx.x % C::TPP;
   rows_c2r_lds<T, M>(lds, 0, row, t, row < nr, tw, rtw);
@@ -85,24 +88,26 @@ __global__ __launch_bounds__((ColCfg<T, L, 1, cols_var<L>()>::NT)) void k_cols(
   cplx<T>* data = reinterpret_cast<cplx<T>*>(ca.data);
   extern __shared__ __align__(16) char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-  cplx<T>* base = data + blockIdx.y * field_stride;
+  gmem<cplx<T>>* base = as_global(data + blockIdx.y * field_stride);
   // neighbouring tiles share the cache lines at their edges (rows of the half
   // spectrum are xh = nx/2 + 1 values apart): keep them on one XCD
   const int f0 = xcd_tile(blockIdx.x, gridDim.x) * C::TX;
-  for (int e = threadIdx.x; e < L * C::TX; e += C::NT) {
+  gather_to_lds<cplx<T>, C::NT, L * C::TX>(lds, L * C::TX, [&](int e) {
     const int i = e / C::TX, col = e - i * C::TX;
     const int f = f0 + col;
-    if (f < m.ncols) lds[e] = base[col_base(m, f) + i * m.as];
-  }
+    cplx<T> v = cmake<T>(T(0), T(0));
+    if (f < m.ncols) v = base[col_base(m, f) + i * m.as];
+    return v;
+  });
   __syncthreads();
   const int t = threadIdx.x / C::TX, col = threadIdx.x % C::TX;
   PencilFFT<T, L, 1, SIGN>::run_lds(t, t < C::TPP && f0 + col < m.ncols, lds + col, 0, C::TX, tw);
   __syncthreads();
-  for (int e = threadIdx.x; e < L * C::TX; e += C::NT) {
+  scatter_from_lds<cplx<T>, C::NT, L * C::TX>(lds, L * C::TX, [&](int e, const cplx<T>& v) {
     const int i = e / C::TX, col = e - i * C::TX;
     const int f = f0 + col;
-    if (f < m.ncols) base[col_base(m, f) + i * m.as] = lds[e];
-  }
+    if (f < m.ncols) base[col_base(m, f) + i * m.as] = v;
+  });
 }
 
 // Register-resident column transform (lengths whose plan allows the register
@@ -122,7 +127,7 @@ __global__ __launch_bounds__((ColCfg<T, L, 1, cols_var<L>()>::NT)) void k_cols_r
   cplx<T>* data = reinterpret_cast<cplx<T>*>(ca.data);
   extern __shared__ __align__(16) char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-  cplx<T>* base = data + blockIdx.y * field_stride;
+  gmem<cplx<T>>* base = as_global(data + blockIdx.y * field_stride);
   const int f0 = xcd_tile(blockIdx.x, gridDim.x) * C::TX;
   const int t = threadIdx.x / C::TX, col = threadIdx.x % C::TX;
   const int f = f0 + col;

@@ -83,9 +83,9 @@ __attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
   const int z = blockIdx.x, field = blockIdx.y;
 
   const int64_t off = field * ntot + (int64_t)z * S::NV;
-  V* uq = reinterpret_cast<V*>(u + off);
-  V* aq = reinterpret_cast<V*>(a + off);
-  const uint32_t* hq = reinterpret_cast<const uint32_t*>(H + (int64_t)z * S::NV);
+  gmem<V>* uq = as_global(reinterpret_cast<V*>(u + off));
+  gmem<V>* aq = as_global(reinterpret_cast<V*>(a + off));
+  const gmem<uint32_t>* hq = as_global(reinterpret_cast<const uint32_t*>(H + (int64_t)z * S::NV));
   // a is exactly zero in the pore (it is only ever written in the solid), so
   // it is loaded unconditionally: no load waits on the value of H.
   V up[S::QPT], ao[S::QPT];
@@ -102,10 +102,7 @@ __attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
   }
 
   cplx<T>* slab = spec + field * nspec + (int64_t)z * NY * S::XH;
-  for (int v = threadIdx.x; v < NY * S::XH; v += S::NT) {
-    const int y = v / S::XH, k = v - y * S::XH;
-    lds[y * S::P2 + k] = slab[v];
-  }
+  slab_load_lds<T, NX, NY>(lds, slab);
   if constexpr (!FUSED) {
     if (threadIdx.x < kShare) {
       const int nb = gridDim.x * gridDim.y, b = blockIdx.y * gridDim.x + blockIdx.x;
@@ -330,9 +327,9 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_rhs(
   if (stokes_skip(ctl)) return;
   const int z = blockIdx.x, field = blockIdx.y;
   const int64_t off = field * ntot + (int64_t)z * S::NV;
-  const V* uq = reinterpret_cast<const V*>(u + off);
-  const V* aq = reinterpret_cast<const V*>(a + off);
-  const uint32_t* hq = reinterpret_cast<const uint32_t*>(H + (int64_t)z * S::NV);
+  const gmem<V>* uq = as_global(reinterpret_cast<const V*>(u + off));
+  const gmem<V>* aq = as_global(reinterpret_cast<const V*>(a + off));
+  const gmem<uint32_t>* hq = as_global(reinterpret_cast<const uint32_t*>(H + (int64_t)z * S::NV));
   // Step 4 of this iteration, formed from all partial sums by every
   // workgroup (same order, same bits); workgroup 0 of the cell stores the new
   // state in the other slot.  Without step4 the current slot is used as is.

@@ -62,10 +62,10 @@ __global__ __launch_bounds__((ColCfg<T, L, NC, VAR, SPL>::NT)) void k_stokes_gre
     const T* __restrict__ lz) {
   using C = ColCfg<T, L, NC, VAR, SPL>;
   const StokesCellArgs ca = many ? many[blockIdx.z] : one;
-  cplx<T>* __restrict__ spec = reinterpret_cast<cplx<T>*>(ca.spec);
-  cplx<T>* __restrict__ qhat = reinterpret_cast<cplx<T>*>(ca.qhat);
-  cplx<T>* __restrict__ dhat = reinterpret_cast<cplx<T>*>(ca.dhat);
-  double* __restrict__ partials = ca.part;
+  gmem<cplx<T>>* __restrict__ spec = as_global(reinterpret_cast<cplx<T>*>(ca.spec));
+  gmem<cplx<T>>* __restrict__ qhat = as_global(reinterpret_cast<cplx<T>*>(ca.qhat));
+  gmem<cplx<T>>* __restrict__ dhat = as_global(reinterpret_cast<cplx<T>*>(ca.dhat));
+  gmem<double>* __restrict__ partials = as_global(ca.part);
   const StokesCtl* __restrict__ ctl = ca.ctl;
   constexpr int PS = L * C::TX;  // LDS pencil-set stride per field
   extern __shared__ __align__(16) char smem_raw[];
@@ -80,14 +80,14 @@ __global__ __launch_bounds__((ColCfg<T, L, NC, VAR, SPL>::NT)) void k_stokes_gre
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int f0 = tile * C::TX;
 
-  for (int e = threadIdx.x; e < NC * PS; e += C::NT) {
+  gather_to_lds<cplx<T>, C::NT, NC * PS>(lds, NC * PS, [&](int e) {
     const int c = e / PS, rem = e - c * PS;
     const int i = rem / C::TX, col = rem - i * C::TX;
     const int f = f0 + col;
     cplx<T> v = cmake<T>(T(0), T(0));
     if (f < P) v = spec[c * gg.nspec + (int64_t)i * P + f];
-    lds[e] = v;
-  }
+    return v;
+  });
   // q-hat and the previous div-hat of this thread's modes, fetched before the
   // forward transform so that their latency overlaps it
   constexpr int MPT = (PS + C::NT - 1) / C::NT;
@@ -188,12 +188,12 @@ __global__ __launch_bounds__((ColCfg<T, L, NC, VAR, SPL>::NT)) void k_stokes_gre
   else
     PencilFFT<T, L, NC, 1>::run_lds(t, act, pen, PS, C::TX, tw);
   __syncthreads();
-  for (int e = threadIdx.x; e < NC * PS; e += C::NT) {
+  scatter_from_lds<cplx<T>, C::NT, NC * PS>(lds, NC * PS, [&](int e, const cplx<T>& v) {
     const int c = e / PS, rem = e - c * PS;
     const int i = rem / C::TX, col = rem - i * C::TX;
     const int f = f0 + col;
-    if (f < P) spec[c * gg.nspec + (int64_t)i * P + f] = lds[e];
-  }
+    if (f < P) spec[c * gg.nspec + (int64_t)i * P + f] = v;
+  });
   block_sum<3>(acc, red);
   if (threadIdx.x == 0) {
     partials[tile * 3 + 0] = acc[0];
@@ -231,16 +231,16 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_stokes_local(
   const int field = blockIdx.y;
   const int row0 = blockIdx.x * C::RB;
   const int nr = min(C::RB, nrows - row0);
-  const cplx<T>* src = spec + field * nspec + (int64_t)row0 * (M + 1);
-  for (int v = threadIdx.x; v < nr * (M + 1); v += C::NT) lds[v] = src[v];
+  const gmem<cplx<T>>* src = as_global(spec + field * nspec + (int64_t)row0 * (M + 1));
+  gather_to_lds<cplx<T>, C::NT, C::RB * (M + 1)>(lds, nr * (M + 1), [&](int v) { return src[v]; });
   __syncthreads();
   const int row = threadIdx.x / C::TPP, t = threadIdx.x % C::TPP;
   rows_c2r_lds<T, M>(lds, 0, row, t, row < nr, tw, rtw);
 
   const int64_t off = field * ntot + (int64_t)row0 * NX;
-  T* ur = u + off;
-  T* ar = a + off;
-  const uint8_t* hr = H + (int64_t)row0 * NX;
+  gmem<T>* ur = as_global(u + off);
+  gmem<T>* ar = as_global(a + off);
+  const gmem<uint8_t>* hr = as_global(H + (int64_t)row0 * NX);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int v = threadIdx.x; v < nr * NX; v += C::NT) {
     const int r = v / NX, x = v - r * NX;
@@ -300,9 +300,9 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_stokes_rhs(
   const int row0 = blockIdx.x * C::RB;
   const int nr = min(C::RB, nrows - row0);
   const int64_t off = field * ntot + (int64_t)row0 * NX;
-  const T* ur = u + off;
-  const T* ar = a + off;
-  const uint8_t* hr = H + (int64_t)row0 * NX;
+  const gmem<T>* ur = as_global(u + off);
+  const gmem<T>* ar = as_global(a + off);
+  const gmem<uint8_t>* hr = as_global(H + (int64_t)row0 * NX);
   for (int v = threadIdx.x; v < nr * NX; v += C::NT) {
     const int r = v / NX, x = v - r * NX;
     const T un = ur[v];
@@ -311,8 +311,9 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_stokes_rhs(
   __syncthreads();
   const int row = threadIdx.x / C::TPP, t = threadIdx.x % C::TPP;
   rows_r2c_lds<T, M>(lds, 0, row, t, row < nr, tw, rtw);
-  cplx<T>* dst = spec + field * nspec + (int64_t)row0 * (M + 1);
-  for (int v = threadIdx.x; v < nr * (M + 1); v += C::NT) dst[v] = lds[v];
+  gmem<cplx<T>>* dst = as_global(spec + field * nspec + (int64_t)row0 * (M + 1));
+  scatter_from_lds<cplx<T>, C::NT, C::RB * (M + 1)>(lds, nr * (M + 1),
+                                                    [&](int v, const cplx<T>& x) { dst[v] = x; });
 }
 
 
@@ -381,10 +382,9 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_rows_step(
     const int row0 = b * C::RB;
     const int nr = min(C::RB, nrows - row0);
     cplx<T>* rows = spec + field * nspec + (int64_t)row0 * (M + 1);
-    for (int v = threadIdx.x; v < nr * (M + 1); v += C::NT) {
-      const int r = v / (M + 1), k = v - r * (M + 1);
-      lds[r * C::RP + k] = rows[v];
-    }
+    static_assert(C::RP == M + 1, "rows are copied as one contiguous block");
+    gather_to_lds<cplx<T>, C::NT, C::RB * (M + 1)>(lds, nr * (M + 1),
+                                                   [&](int v) { return rows[v]; });
     __syncthreads();
     rows_c2r_lds<T, M>(lds, 0, row, t, row < nr, tw, rtw);
     const int64_t off = field * ntot + (int64_t)row0 * NX;
@@ -528,10 +528,10 @@ __global__ __launch_bounds__((ColCfg<T, L, NC, VAR>::NT)) void k_stokes_green_re
   constexpr int TPP = C::TPP;
   constexpr int EPT = L / TPP;
   const StokesCellArgs ca = many ? many[blockIdx.z] : one;
-  cplx<T>* __restrict__ spec = reinterpret_cast<cplx<T>*>(ca.spec);
-  cplx<T>* __restrict__ qhat = reinterpret_cast<cplx<T>*>(ca.qhat);
-  cplx<T>* __restrict__ dhat = reinterpret_cast<cplx<T>*>(ca.dhat);
-  double* __restrict__ partials = ca.part;
+  gmem<cplx<T>>* __restrict__ spec = as_global(reinterpret_cast<cplx<T>*>(ca.spec));
+  gmem<cplx<T>>* __restrict__ qhat = as_global(reinterpret_cast<cplx<T>*>(ca.qhat));
+  gmem<cplx<T>>* __restrict__ dhat = as_global(reinterpret_cast<cplx<T>*>(ca.dhat));
+  gmem<double>* __restrict__ partials = as_global(ca.part);
   const StokesCtl* __restrict__ ctl = ca.ctl;
   extern __shared__ __align__(16) char smem_raw[];
   __shared__ double red[3 * 16];

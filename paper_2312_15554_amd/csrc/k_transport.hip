@@ -76,7 +76,7 @@ __global__ __launch_bounds__((TGCfg<T, L, tg_fields<D, SL, FL>()>::NT)) void k_t
   const bool act = t < C::TPP && f0 + colt < P;
 
   if constexpr (MODE == 0) {
-    for (int e = threadIdx.x; e < NIN * PS; e += C::NT) {
+    gather_to_lds<cplx<T>, C::NT, NIN * PS>(lds, NIN * PS, [&](int e) {
       const int c = e / PS, rem = e - c * PS;
       const int i = rem / C::TX, col = rem - i * C::TX;
       const int f = f0 + col;
@@ -94,8 +94,8 @@ __global__ __launch_bounds__((TGCfg<T, L, tg_fields<D, SL, FL>()>::NT)) void k_t
           v = spec[c * gg.nspec + mi];
         }
       }
-      lds[e] = v;
-    }
+      return v;
+    });
     __syncthreads();
     if constexpr (kTGSpl)
       PencilFFT<T, L, 1, -1>::run_lds(t, act && fc < NIN, lds + (fc < NIN ? fc : 0) * PS + colt, PS,
@@ -212,12 +212,12 @@ __global__ __launch_bounds__((TGCfg<T, L, tg_fields<D, SL, FL>()>::NT)) void k_t
   else
     PencilFFT<T, L, NOUT, 1>::run_lds(t, act, lds + colt, PS, C::TX, tw);
   __syncthreads();
-  for (int e = threadIdx.x; e < NOUT * PS; e += C::NT) {
+  scatter_from_lds<cplx<T>, C::NT, NOUT * PS>(lds, NOUT * PS, [&](int e, const cplx<T>& v) {
     const int c = e / PS, rem = e - c * PS;
     const int i = rem / C::TX, col = rem - i * C::TX;
     const int f = f0 + col;
-    if (f < P) spec[c * gg.nspec + (int64_t)i * P + f] = lds[e];
-  }
+    if (f < P) spec[c * gg.nspec + (int64_t)i * P + f] = v;
+  });
   if constexpr (MODE == 0) {
     block_sum<2>(acc, red);
     if (!judge) {
@@ -273,7 +273,8 @@ __global__ __launch_bounds__((RowCfgN<T, M, FL ? 2 * D : D + 1>::NT)) void k_tra
   const int nr = min(C::RB, nrows - row0);
   for (int c = 0; c < NIN; ++c) {
     const cplx<T>* src = spec + c * nspec + (int64_t)row0 * (M + 1);
-    for (int v = threadIdx.x; v < nr * (M + 1); v += C::NT) lds[c * C::FS + v] = src[v];
+    gather_to_lds<cplx<T>, C::NT, C::RB * (M + 1)>(lds + c * C::FS, nr * (M + 1),
+                                                   [&](int v) { return src[v]; });
   }
   __syncthreads();
   const int row = threadIdx.x / C::TPP, t = threadIdx.x % C::TPP;
@@ -325,7 +326,8 @@ __global__ __launch_bounds__((RowCfgN<T, M, FL ? 2 * D : D + 1>::NT)) void k_tra
   rows_r2c_lds<T, M, D + 1>(lds, C::FS, row, t, row < nr, tw, rtw);
   for (int c = 0; c <= D; ++c) {
     cplx<T>* dst = spec + c * nspec + (int64_t)row0 * (M + 1);
-    for (int v = threadIdx.x; v < nr * (M + 1); v += C::NT) dst[v] = lds[c * C::FS + v];
+    scatter_from_lds<cplx<T>, C::NT, C::RB * (M + 1)>(lds + c * C::FS, nr * (M + 1),
+                                                      [&](int v, const cplx<T>& x) { dst[v] = x; });
   }
 }
 
@@ -340,6 +342,15 @@ __global__ __launch_bounds__((RowCfgN<T, M, FL ? 2 * D : D + 1>::NT)) void k_tra
 // and one forward transform.  The green pass then transforms S = G_x + G_y +
 // f_z and tau_z.  Compared with the row pass this saves the separate y passes
 // and three of the seven forward transforms of the iteration.
+//
+// D_c is the central difference along x (c = 0) or y (c = 1) of the periodic
+// slab, exactly the i s_c of the spectral derivative.  Each G_c is formed in
+// one sweep with no value held across a barrier: along x the quads of a row
+// sit on consecutive lanes of one row group (R <= RG lanes, RG a power of two
+// dividing 64), so the neighbours' tau come by cross-lane exchange; along y
+// each thread walks a strip of rows of one quad column, taking the tau of the
+// two rows that bound its strip before the barrier after which strips are
+// overwritten.
 template <typename T, int N>
 __global__ __launch_bounds__((SlabCfg<T, N, N>::NT))
 __attribute__((amdgpu_waves_per_eu(SlabCfg<T, N, N>::WPE_ONE))) void k_transport_slab(
@@ -349,7 +360,12 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, N, N>::WPE_ONE))) void k_transport
     const cplx<T>* __restrict__ rtw) {
   using S = SlabCfg<T, N, N>;
   using V = typename Vec4<T>::type;
-  constexpr int D = 3;
+  constexpr int R = N / 4;  // quads per row
+  constexpr int RG = R <= 8 ? 8 : (R <= 16 ? 16 : (R <= 32 ? 32 : 64));
+  static_assert(R <= RG && RG <= 64 && S::NT % RG == 0, "row groups must tile the workgroup");
+  constexpr int NG = S::NT / RG;           // row groups per workgroup
+  constexpr int PX = (N + NG - 1) / NG;    // sweeps of the x workgroup
+  constexpr int RPS = (N + NG - 1) / NG;   // rows per strip of the y workgroup
   extern __shared__ __align__(32) char smem_raw[];
   __shared__ double red[2 * 16];
   __shared__ int s_stop;
@@ -387,93 +403,120 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, N, N>::WPE_ONE))) void k_transport
   const T gc = (T)ctl->g[ax], B0c = (T)ctl->B0[ax];
   const T A0 = (T)ctl->A0, Pe = (T)ctl->Pe, eta = (T)ctl->eta, dif = (T)ctl->diff;
   const T calF = c == 0 ? (T)ctl->calF : T(0);
+  const T hs = T(0.5 * (double)N);  // 1 / (2 h) with h = 1 / N
   const int64_t off = (int64_t)z * S::NV;
-  const V* uq = reinterpret_cast<const V*>(u + ax * ntot + off);
-  const uint32_t* hq = reinterpret_cast<const uint32_t*>(H + off);
-  V fr[S::QPT];
-#pragma unroll
-  for (int j = 0; j < S::QPT; ++j) {
-    const int q = threadIdx.x + j * S::NT;
-    if (!S::FULL && q >= S::NQ) continue;
-    const int v = 4 * q;
-    const int y = v / N, x = v - y * N;
-    T* cell = ldsr + y * 2 * S::P2 + x;
-    const V ev = lds_ld4<V>(cell);
-    const V uv = uq[q];
-    const uint32_t hw = hq[q];
+  const gmem<V>* uq = as_global(reinterpret_cast<const V*>(u + ax * ntot + off));
+  const gmem<uint32_t>* hq = as_global(reinterpret_cast<const uint32_t*>(H + off));
+  V zero;
+  zero.x = zero.y = zero.z = zero.w = T(0);
+  // tau and f of a quad from its d chi (ev), flow component (uv) and H bytes
+  auto quad = [&](const V& ev, const V& uv, uint32_t hw, V& tau, V& f) {
     const T e4[4] = {ev.x + gc, ev.y + gc, ev.z + gc, ev.w + gc};
     const T u4[4] = {uv.x, uv.y, uv.z, uv.w};
-    T tau[4], f[4];
+    T t4[4], f4[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const bool solid = ((hw >> (8 * k)) & 0xffu) != 0;
       const T Aa = solid ? eta : dif;
       const T Bc = solid ? T(0) : Pe * u4[k];
-      f[k] = (solid ? T(0) : calF) - (Bc - B0c) * e4[k];
-      tau[k] = (Aa - A0) * e4[k];
+      f4[k] = (solid ? T(0) : calF) - (Bc - B0c) * e4[k];
+      t4[k] = (Aa - A0) * e4[k];
     }
-    V tv;
-    tv.x = tau[0];
-    tv.y = tau[1];
-    tv.z = tau[2];
-    tv.w = tau[3];
-    lds_st4(cell, tv);
-    fr[j].x = f[0];
-    fr[j].y = f[1];
-    fr[j].z = f[2];
-    fr[j].w = f[3];
-  }
-  __syncthreads();
-  if (c < 2) {
-    // G_c = f_c + D_c tau_c with D_c the central difference along x (c = 0)
-    // or y (c = 1) of the periodic slab: exactly the i s_c of the spectral
-    // derivative, so only G_c needs a forward transform
-    const T hs = T(0.5 * (double)N);  // 1 / (2 h) with h = 1 / N
+    tau.x = t4[0];
+    tau.y = t4[1];
+    tau.z = t4[2];
+    tau.w = t4[3];
+    f.x = f4[0];
+    f.y = f4[1];
+    f.z = f4[2];
+    f.w = f4[3];
+  };
+  const int xq = threadIdx.x % RG, grp = threadIdx.x / RG;
+  const bool xin = xq < R;
+  if (c == 0) {
+    // G_x = f_x + D_x tau_x, row group grp taking rows p NG + grp
+    const int gb = (threadIdx.x & 63) & ~(RG - 1);  // first lane of the row group
+    const int src_l = gb + (xq == 0 ? R - 1 : xq - 1), src_r = gb + (xq >= R - 1 ? 0 : xq + 1);
+#pragma unroll
+    for (int p = 0; p < PX; ++p) {
+      const int y = p * NG + grp;
+      const bool act = xin && y < N;
+      V tau = zero, f = zero;
+      T* cell = ldsr + (act ? y : 0) * 2 * S::P2 + 4 * (act ? xq : 0);
+      if (act) {
+        const int q = y * R + xq;
+        quad(lds_ld4<V>(cell), uq[q], hq[q], tau, f);
+      }
+      const T left = __shfl(tau.w, src_l, 64), right = __shfl(tau.x, src_r, 64);
+      if (act) {
+        V G;
+        G.x = f.x + hs * (tau.y - left);
+        G.y = f.y + hs * (tau.z - tau.x);
+        G.z = f.z + hs * (tau.w - tau.y);
+        G.w = f.w + hs * (right - tau.z);
+        lds_st4(cell, G);
+      }
+    }
+  } else if (c == 1) {
+    // G_y = f_y + D_y tau_y, each thread walking rows y0 .. y1-1 of quad
+    // column xq with a window of three rows
+    const int y0 = grp * RPS, y1 = min(N, y0 + RPS);
+    const bool act = xin && y0 < N;
+    V tlo = zero, thi = zero;
+    if (act) {
+      const int ylo = y0 == 0 ? N - 1 : y0 - 1, yhi = y1 == N ? 0 : y1;
+      V f;
+      quad(lds_ld4<V>(ldsr + ylo * 2 * S::P2 + 4 * xq), zero, hq[ylo * R + xq], tlo, f);
+      quad(lds_ld4<V>(ldsr + yhi * 2 * S::P2 + 4 * xq), zero, hq[yhi * R + xq], thi, f);
+    }
+    __syncthreads();  // the bounding rows are read before any strip is overwritten
+    if (act) {
+      V tm = tlo, tc, fc;
+      {
+        const int q = y0 * R + xq;
+        quad(lds_ld4<V>(ldsr + y0 * 2 * S::P2 + 4 * xq), uq[q], hq[q], tc, fc);
+      }
+#pragma unroll
+      for (int k = 0; k < RPS; ++k) {
+        const int y = y0 + k;
+        if (y < y1) {
+          V tn = thi, fn = zero;
+          if (y + 1 < y1) {
+            const int q = (y + 1) * R + xq;
+            quad(lds_ld4<V>(ldsr + (y + 1) * 2 * S::P2 + 4 * xq), uq[q], hq[q], tn, fn);
+          }
+          V G;
+          G.x = fc.x + hs * (tn.x - tm.x);
+          G.y = fc.y + hs * (tn.y - tm.y);
+          G.z = fc.z + hs * (tn.z - tm.z);
+          G.w = fc.w + hs * (tn.w - tm.w);
+          lds_st4(ldsr + y * 2 * S::P2 + 4 * xq, G);
+          tm = tc;
+          tc = tn;
+          fc = fn;
+        }
+      }
+    }
+  } else {
+    // f_z (c = 2) or tau_z (c = 3) in place
 #pragma unroll
     for (int j = 0; j < S::QPT; ++j) {
       const int q = threadIdx.x + j * S::NT;
       if (!S::FULL && q >= S::NQ) continue;
       const int v = 4 * q;
       const int y = v / N, x = v - y * N;
-      T d[4];
-      if (c == 0) {
-        const T* row = ldsr + y * 2 * S::P2;
-        const T left = row[x == 0 ? N - 1 : x - 1], right = row[x + 4 == N ? 0 : x + 4];
-        const V mid = lds_ld4<V>(row + x);
-        d[0] = mid.y - left;
-        d[1] = mid.z - mid.x;
-        d[2] = mid.w - mid.y;
-        d[3] = right - mid.z;
-      } else {
-        const V up = lds_ld4<V>(ldsr + (y + 1 == N ? 0 : y + 1) * 2 * S::P2 + x);
-        const V dn = lds_ld4<V>(ldsr + (y == 0 ? N - 1 : y - 1) * 2 * S::P2 + x);
-        d[0] = up.x - dn.x;
-        d[1] = up.y - dn.y;
-        d[2] = up.z - dn.z;
-        d[3] = up.w - dn.w;
-      }
-      fr[j].x += hs * d[0];
-      fr[j].y += hs * d[1];
-      fr[j].z += hs * d[2];
-      fr[j].w += hs * d[3];
+      T* cell = ldsr + y * 2 * S::P2 + x;
+      V tau, f, uv = zero;
+      if (c == 2) uv = uq[q];
+      quad(lds_ld4<V>(cell), uv, hq[q], tau, f);
+      lds_st4(cell, c == 3 ? tau : f);
     }
-    __syncthreads();  // every tau neighbour has been read
-  } else if (c == 3) {
-    slab_forward_store<T, N, N>(lds, spec + 3 * nspec + soff, twx, twy, rtw);  // tau_z
-    return;
-  }
-#pragma unroll
-  for (int j = 0; j < S::QPT; ++j) {
-    const int q = threadIdx.x + j * S::NT;
-    if (!S::FULL && q >= S::NQ) continue;
-    const int v = 4 * q;
-    const int y = v / N, x = v - y * N;
-    lds_st4(ldsr + y * 2 * S::P2 + x, fr[j]);
   }
   __syncthreads();
-  // G_x, G_y into the field this workgroup read; f_z into field 4 (field 2 is
-  // still read by the tau_z workgroup of this slab)
-  slab_forward_store<T, N, N>(lds, spec + (c < 2 ? c : 4) * nspec + soff, twx, twy, rtw);
+  // G_x, G_y into the field this workgroup read; tau_z into field 3 and f_z
+  // into field 4 (field 2 is read by both z workgroups of this slab)
+  slab_forward_store<T, N, N>(lds, spec + (c < 2 ? c : (c == 3 ? 3 : 4)) * nspec + soff, twx, twy,
+                              rtw);
 }
 
 // ------------------------------------------------------------------ launchers

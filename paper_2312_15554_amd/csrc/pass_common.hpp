@@ -32,6 +32,75 @@ namespace acm {
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
+// Global-memory view of a pointer.  A pointer read from memory at run time
+// (the per-cell argument array of batched launches) is generic to the
+// compiler, which then emits flat accesses: slower to issue, and waiting on
+// them also waits on every LDS access in flight.  Kernels index the arrays
+// of a cell through this view.  (The host pass, which only parses kernel
+// bodies, sees the plain type: it has no address space 1 for class types.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+#else
+template <typename T>
+using gmem = T;
+#endif
+template <typename T>
+__device__ __forceinline__ gmem<T>* as_global(T* p) {
+  return (gmem<T>*)p;
+}
+
+// Workgroup-wide copy of n <= MAXN elements by NT threads: put(e, ld(e))
+// for every e < n, each thread issuing all of its loads before its first
+// put.  Copying into LDS this way brings the block in one memory round trip:
+// a loop that writes each loaded element to LDS before loading the next
+// waits on every load in turn, which leaves a workgroup idle for most of its
+// load phase.
+template <typename E, int NT, int MAXN, typename F, typename P>
+__device__ __forceinline__ void batched_copy(int n, F ld, P put) {
+  constexpr int PT = (MAXN + NT - 1) / NT;
+  E b[PT];
+#pragma unroll
+  for (int j = 0; j < PT; ++j) {
+    const int e = (int)threadIdx.x + j * NT;
+    b[j] = E{};  // defined on every path: a conditional first write puts b in scratch memory
+    if (e < n) b[j] = ld(e);
+  }
+#pragma unroll
+  for (int j = 0; j < PT; ++j) {
+    const int e = (int)threadIdx.x + j * NT;
+    if (e < n) put(e, b[j]);
+  }
+}
+
+// lds[e] = ld(e) for e < n <= MAXN (batched_copy into LDS).
+template <typename E, int NT, int MAXN, typename F>
+__device__ __forceinline__ void gather_to_lds(E* lds, int n, F ld) {
+  batched_copy<E, NT, MAXN>(n, ld, [&](int e, const E& v) { lds[e] = v; });
+}
+
+// The reverse: st(e, lds[e]) for e < n <= MAXN, the LDS reads of U elements
+// per thread issued together.
+template <typename E, int NT, int MAXN, int U = 4, typename F>
+__device__ __forceinline__ void scatter_from_lds(const E* lds, int n, F st) {
+  constexpr int PT = (MAXN + NT - 1) / NT;
+#pragma unroll
+  for (int j0 = 0; j0 < PT; j0 += U) {
+    E b[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int e = (int)threadIdx.x + (j0 + k) * NT;
+      b[k] = E{};
+      if (j0 + k < PT && e < n) b[k] = lds[e];
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int e = (int)threadIdx.x + (j0 + k) * NT;
+      if (j0 + k < PT && e < n) st(e, b[k]);
+    }
+  }
+}
+
 // --------------------------------------------------------------------- rows
 // A workgroup holds RB consecutive x rows of one field, each with pitch RP
 // complex values.  TPP threads cooperate on one row.

@@ -78,6 +78,70 @@ struct SlabCfg {
   static constexpr int WPE_ONE = cmax(1, cmin(8, (cmin(BLK_LDS, 2) * (NT / 64) + 3) / 4));
 };
 
+// Geometry of the contiguous copies of a whole half-spectrum slab (NY * XH
+// complex values; in LDS its pitch P2 equals XH) in 16-byte vectors.
+template <typename T, int NX, int NY>
+struct SlabCopy {
+  using S = SlabCfg<T, NX, NY>;
+  static constexpr int BYTES = NY * S::XH * (int)sizeof(cplx<T>);
+  static_assert(BYTES % 16 == 0, "slab size must be a multiple of 16 bytes");
+  static constexpr int NV = BYTES / 16;
+  static constexpr int PT = (NV + S::NT - 1) / S::NT;
+  static constexpr bool EVEN = (NV % S::NT) == 0;
+};
+
+// Load the half-spectrum slab `src` into LDS with 16-byte accesses, every
+// load of a thread issued before the first LDS write: the slab arrives in one
+// memory round trip rather than one per element (a loop that stores each
+// loaded value to LDS waits on every load in turn).
+template <typename T, int NX, int NY>
+__device__ __forceinline__ void slab_load_lds(cplx<T>* lds, const cplx<T>* __restrict__ src) {
+  using C = SlabCopy<T, NX, NY>;
+  constexpr int NT = SlabCfg<T, NX, NY>::NT;
+  const gmem<float4>* s = as_global(reinterpret_cast<const float4*>(src));
+  float4* d = reinterpret_cast<float4*>(lds);
+  // every element is defined on every path (a conditional first write puts
+  // the array in scratch memory)
+  float4 b[C::PT];
+#pragma unroll
+  for (int j = 0; j < C::PT; ++j) {
+    const int i = threadIdx.x + j * NT;
+    b[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (C::EVEN || i < C::NV) b[j] = s[i];
+  }
+#pragma unroll
+  for (int j = 0; j < C::PT; ++j) {
+    const int i = threadIdx.x + j * NT;
+    if (C::EVEN || i < C::NV) d[i] = b[j];
+  }
+}
+
+// Store the half-spectrum slab held in LDS (contiguous, pitch XH) to `dst`
+// with 16-byte accesses, the LDS reads of a chunk of U vectors issued
+// together (LDS latency is short: small chunks keep few registers live).
+template <typename T, int NX, int NY, int U = 4>
+__device__ __forceinline__ void slab_store_lds(cplx<T>* __restrict__ dst, const cplx<T>* lds) {
+  using St = SlabCopy<T, NX, NY>;
+  constexpr int NT = SlabCfg<T, NX, NY>::NT;
+  const float4* s = reinterpret_cast<const float4*>(lds);
+  gmem<float4>* d = as_global(reinterpret_cast<float4*>(dst));
+#pragma unroll
+  for (int j0 = 0; j0 < St::PT; j0 += U) {
+    float4 b[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int i = threadIdx.x + (j0 + k) * NT;
+      b[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (j0 + k < St::PT && (St::EVEN || i < St::NV)) b[k] = s[i];
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int i = threadIdx.x + (j0 + k) * NT;
+      if (j0 + k < St::PT && (St::EVEN || i < St::NV)) d[i] = b[k];
+    }
+  }
+}
+
 // y transform of all XH columns of the slab held in LDS ([y][k], pitch P2).
 template <typename T, int NX, int NY, int SIGN>
 __device__ __forceinline__ void slab_cols(cplx<T>* lds, const cplx<T>* __restrict__ tw) {
@@ -116,10 +180,7 @@ __device__ __forceinline__ void slab_forward_store(cplx<T>* lds, cplx<T>* __rest
     }
   }
   slab_cols<T, NX, NY, -1>(lds, twy);
-  for (int v = threadIdx.x; v < NY * S::XH; v += S::NT) {
-    const int y = v / S::XH, k = v - y * S::XH;
-    dst[v] = lds[y * S::P2 + k];
-  }
+  slab_store_lds<T, NX, NY>(dst, lds);
 }
 
 // Load the half-spectrum slab `src` ([y][k], k < XH) into LDS and take it back
@@ -132,10 +193,7 @@ __device__ __forceinline__ void slab_load_inverse(cplx<T>* lds, const cplx<T>* _
                                                   const cplx<T>* __restrict__ twy,
                                                   const cplx<T>* __restrict__ rtw) {
   using S = SlabCfg<T, NX, NY>;
-  for (int v = threadIdx.x; v < NY * S::XH; v += S::NT) {
-    const int y = v / S::XH, k = v - y * S::XH;
-    lds[y * S::P2 + k] = src[v];
-  }
+  slab_load_lds<T, NX, NY>(lds, src);
   __syncthreads();
   slab_cols<T, NX, NY, +1>(lds, twy);
   const int grp = threadIdx.x % S::GX, t = threadIdx.x / S::GX;  // row index fastest

@@ -17,6 +17,8 @@ template <int U = 2>
 __device__ __forceinline__ void stokes_sum_partials(const double* __restrict__ gpart, int ngreen,
                                                     const double* __restrict__ lpart, int nlocal,
                                                     double (&acc)[7], double* red) {
+  const gmem<double>* gp = as_global(gpart);
+  const gmem<double>* lp = as_global(lpart);
   for (int k = 0; k < 7; ++k) acc[k] = 0.0;
   const int nmax = ngreen > nlocal ? ngreen : nlocal;
   for (int j0 = threadIdx.x; j0 < nmax; j0 += U * blockDim.x) {
@@ -26,9 +28,9 @@ __device__ __forceinline__ void stokes_sum_partials(const double* __restrict__ g
       const int j = j0 + k * blockDim.x;
       const bool ig = j < ngreen, il = j < nlocal;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) vg[k][c] = ig ? gpart[j * 3 + c] : 0.0;
+      for (int c = 0; c < 3; ++c) vg[k][c] = ig ? gp[j * 3 + c] : 0.0;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) vl[k][c] = il ? lpart[j * 4 + c] : 0.0;
+      for (int c = 0; c < 4; ++c) vl[k][c] = il ? lp[j * 4 + c] : 0.0;
     }
 #pragma unroll
     for (int k = 0; k < U; ++k) {
@@ -47,6 +49,7 @@ __device__ __forceinline__ void stokes_sum_partials(const double* __restrict__ g
 template <int U>
 __device__ __forceinline__ void stokes_sum_records(const double* __restrict__ rec, int nrec,
                                                    double (&acc)[7], double* red) {
+  const gmem<double>* rp = as_global(rec);
   for (int k = 0; k < 7; ++k) acc[k] = 0.0;
   for (int j0 = threadIdx.x; j0 < nrec; j0 += U * blockDim.x) {
     double v[U][7];
@@ -54,7 +57,7 @@ __device__ __forceinline__ void stokes_sum_records(const double* __restrict__ re
     for (int k = 0; k < U; ++k) {
       const int j = j0 + k * blockDim.x;
 #pragma unroll
-      for (int c = 0; c < 7; ++c) v[k][c] = j < nrec ? rec[j * 7 + c] : 0.0;
+      for (int c = 0; c < 7; ++c) v[k][c] = j < nrec ? rp[j * 7 + c] : 0.0;
     }
 #pragma unroll
     for (int k = 0; k < U; ++k)
