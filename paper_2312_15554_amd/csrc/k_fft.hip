@@ -133,12 +133,13 @@ __global__ __launch_bounds__((ColCfg<T, L, 1, cols_var<L>()>::NT)) void k_cols_r
   const int f = f0 + col;
   const bool act = t < TPP && f < m.ncols;
   const int cb = act ? col_base(m, f) : 0;
+  const cplx<T>* twl = twiddles_to_lds<T, C::NT, Plan<L>::tw_total>(lds + PS, tw);
   cplx<T> v[1][EPT];
   if (act) {
 #pragma unroll
     for (int k = 0; k < EPT; ++k) v[0][k] = base[cb + (t + k * TPP) * m.as];
   }
-  RegFFT<T, L, 1, SIGN>::run(t, act, v, lds + col, PS, C::TX, tw);
+  RegFFT<T, L, 1, SIGN>::run(t, act, v, lds + col, PS, C::TX, twl);
   if (act) {
 #pragma unroll
     for (int k = 0; k < EPT; ++k) base[cb + (t + k * TPP) * m.as] = v[0][k];
@@ -219,11 +220,12 @@ static hipError_t cols_impl(const Geom& g, const DevTables<T>& tb, int axis, int
     dim3 grid((unsigned)((m.ncols + C::TX - 1) / C::TX), (unsigned)nfields,                 \
               (unsigned)ncells);                                                            \
     if constexpr (RegPlanOk<LL>::value()) {                                                 \
+      constexpr int lds_reg = C::LDS_BYTES + Plan<LL>::tw_total * (int)sizeof(cplx<T>);     \
       if (sign < 0)                                                                         \
-        ACM_LAUNCH((k_cols_reg<T, LL, -1>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many,  \
+        ACM_LAUNCH((k_cols_reg<T, LL, -1>), grid, dim3(C::NT), lds_reg, s, one, many,       \
                    g.nspec, m, tw);                                                         \
       else                                                                                  \
-        ACM_LAUNCH((k_cols_reg<T, LL, 1>), grid, dim3(C::NT), C::LDS_BYTES, s, one, many,   \
+        ACM_LAUNCH((k_cols_reg<T, LL, 1>), grid, dim3(C::NT), lds_reg, s, one, many,        \
                    g.nspec, m, tw);                                                         \
     } else {                                                                                \
       if (sign < 0)                                                                         \

@@ -32,8 +32,8 @@ __global__ __launch_bounds__((SlabCfg<T, NX, NY>::NT))
 __attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
                                           : SlabCfg<T, NX, NY>::WPE))) void k_slab_local(
     StokesCellArgs one, const StokesCellArgs* __restrict__ many, int par, int ngreen,
-    int64_t ntot, int64_t nspec, const cplx<T>* __restrict__ twx,
-    const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__ rtw) {
+    int64_t ntot, int64_t nspec, const cplx<T>* __restrict__ twx_g,
+    const cplx<T>* __restrict__ twy_g, const cplx<T>* __restrict__ rtw_g) {
   using S = SlabCfg<T, NX, NY>;
   const StokesCellArgs ca = many ? many[blockIdx.z] : one;
   cplx<T>* __restrict__ spec = reinterpret_cast<cplx<T>*>(ca.spec);
@@ -102,6 +102,8 @@ __attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
   }
 
   cplx<T>* slab = spec + field * nspec + (int64_t)z * NY * S::XH;
+  const SlabTw<T> tws = slab_twiddles<T, NX, NY>(lds, twx_g, twy_g, rtw_g);
+  const cplx<T>*twx = tws.x, *twy = tws.y, *rtw = tws.r;
   slab_load_lds<T, NX, NY>(lds, slab);
   if constexpr (!FUSED) {
     if (threadIdx.x < kShare) {
@@ -308,8 +310,8 @@ template <typename T, int NX, int NY>
 __global__ __launch_bounds__((SlabCfg<T, NX, NY>::NT))
 __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_rhs(
     StokesCellArgs one, const StokesCellArgs* __restrict__ many, int par, int step4, int ngreen,
-    int64_t ntot, int64_t nspec, const cplx<T>* __restrict__ twx,
-    const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__ rtw) {
+    int64_t ntot, int64_t nspec, const cplx<T>* __restrict__ twx_g,
+    const cplx<T>* __restrict__ twy_g, const cplx<T>* __restrict__ rtw_g) {
   using S = SlabCfg<T, NX, NY>;
   const StokesCellArgs ca = many ? many[blockIdx.z] : one;
   cplx<T>* __restrict__ spec = reinterpret_cast<cplx<T>*>(ca.spec);
@@ -325,6 +327,8 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, NX, NY>::WPE))) void k_slab_rhs(
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   T* ldsr = reinterpret_cast<T*>(smem_raw);
   if (stokes_skip(ctl)) return;
+  const SlabTw<T> tws = slab_twiddles<T, NX, NY>(lds, twx_g, twy_g, rtw_g);
+  const cplx<T>*twx = tws.x, *twy = tws.y, *rtw = tws.r;
   const int z = blockIdx.x, field = blockIdx.y;
   const int64_t off = field * ntot + (int64_t)z * S::NV;
   const gmem<V>* uq = as_global(reinterpret_cast<const V*>(u + off));

@@ -57,7 +57,7 @@ __device__ __forceinline__ cplx<T> step1_rhs(cplx<T> r, T s, const cplx<T>& q, c
 template <typename T, int L, int NC, int VAR, int SPL>
 __global__ __launch_bounds__((ColCfg<T, L, NC, VAR, SPL>::NT)) void k_stokes_green(
     StokesCellArgs one, const StokesCellArgs* __restrict__ many, GreenGeom gg, int par,
-    const cplx<T>* __restrict__ tw, const T* __restrict__ sx, const T* __restrict__ lx,
+    const cplx<T>* __restrict__ tw_g, const T* __restrict__ sx, const T* __restrict__ lx,
     const T* __restrict__ sy, const T* __restrict__ ly, const T* __restrict__ sz,
     const T* __restrict__ lz) {
   using C = ColCfg<T, L, NC, VAR, SPL>;
@@ -72,6 +72,7 @@ __global__ __launch_bounds__((ColCfg<T, L, NC, VAR, SPL>::NT)) void k_stokes_gre
   __shared__ double red[3 * 16];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   if (stokes_skip(ctl)) return;
+  const cplx<T>* tw = twiddles_to_lds<T, C::NT, Plan<L>::tw_total>(lds + NC * PS, tw_g);
   const T beta = (T)ctl->st[par].psi[1];
   const T bpen = (T)ctl->st[par].psi[2];
   const T nu = (T)ctl->nu;
@@ -374,6 +375,16 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_rows_step(
     gsh[threadIdx.x * 3 + 2] = s2;
   }
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  // the twiddles of the row transforms, read by every stage of every row
+  // block, copied once into LDS after the rows (made visible by the first
+  // barrier of the loop)
+  constexpr int TWN = Plan<M>::tw_total + M + 1;
+  cplx<T>* const ltw = lds + C::RB * C::RP;
+  batched_copy<cplx<T>, C::NT, TWN>(
+      TWN, [&](int e) { return e < Plan<M>::tw_total ? tw[e] : rtw[e - Plan<M>::tw_total]; },
+      [&](int e, const cplx<T>& v) { ltw[e] = v; });
+  const cplx<T>* const twl = ltw;
+  const cplx<T>* const rtwl = ltw + Plan<M>::tw_total;
   // work list: (field, row block) pairs, field-major
   const int nrb = (nrows + C::RB - 1) / C::RB;
   const int row = threadIdx.x / C::TPP, t = threadIdx.x % C::TPP;
@@ -386,7 +397,7 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_rows_step(
     gather_to_lds<cplx<T>, C::NT, C::RB * (M + 1)>(lds, nr * (M + 1),
                                                    [&](int v) { return rows[v]; });
     __syncthreads();
-    rows_c2r_lds<T, M>(lds, 0, row, t, row < nr, tw, rtw);
+    rows_c2r_lds<T, M>(lds, 0, row, t, row < nr, twl, rtwl);
     const int64_t off = field * ntot + (int64_t)row0 * NX;
     V* uq = reinterpret_cast<V*>(u + off);
     V* aq = reinterpret_cast<V*>(a + off);
@@ -449,7 +460,7 @@ __global__ __launch_bounds__((RowCfg<T, M>::NT)) void k_rows_step(
       lds_st4(cell, r4);
     }
     __syncthreads();
-    rows_r2c_lds<T, M>(lds, 0, row, t, row < nr, tw, rtw);
+    rows_r2c_lds<T, M>(lds, 0, row, t, row < nr, twl, rtwl);
     for (int v = threadIdx.x; v < nr * (M + 1); v += C::NT) {
       const int r = v / (M + 1), k = v - r * (M + 1);
       rows[v] = lds[r * C::RP + k];
@@ -548,8 +559,23 @@ __global__ __launch_bounds__((ColCfg<T, L, NC, VAR>::NT)) void k_stokes_green_re
   const int f = f0 + col;
   const bool act = t < TPP && f < P;
 
+  const cplx<T>* twl = twiddles_to_lds<T, C::NT, Plan<L>::tw_total>(lds + NC * PS, tw);
+  // the column's modes and, per element, the symbols of the transformed axis
+  // are loaded with the data, before the forward transform hides their latency
+  int kx = f, ky = 0;
+  if (NC == 3) {
+    kx = f % gg.xh;
+    ky = f / gg.xh;
+  }
+  const T* sl = NC == 3 ? sz : sy;  // symbols of the transformed axis
+  const T* ll = NC == 3 ? lz : ly;
   cplx<T> v[NC][EPT], qv[EPT], dv[EPT];
+  T sv[EPT], lv[EPT];
+  T sx0 = T(0), sy0 = T(0), L01 = T(0);
   if (act) {
+    sx0 = sx[kx];
+    sy0 = sy[ky];
+    L01 = lx[kx] + (NC == 3 ? ly[ky] : T(0));
 #pragma unroll
     for (int m = 0; m < EPT; ++m) {
       const int64_t mi = (int64_t)(t + m * TPP) * P + f;
@@ -557,21 +583,15 @@ __global__ __launch_bounds__((ColCfg<T, L, NC, VAR>::NT)) void k_stokes_green_re
       for (int c = 0; c < NC; ++c) v[c][m] = spec[c * gg.nspec + mi];
       qv[m] = qhat[mi];
       dv[m] = dhat[mi];
+      sv[m] = sl[t + m * TPP];
+      lv[m] = ll[t + m * TPP];
     }
   }
-  RegFFT<T, L, NC, -1>::run(t, act, v, lds + col, PS, C::TX, tw);
+  RegFFT<T, L, NC, -1>::run(t, act, v, lds + col, PS, C::TX, twl);
 
   double acc[3] = {0.0, 0.0, 0.0};
   const T inv_ntot = T(1.0 / (double)gg.ntot);
   if (act) {
-    int kx, ky;
-    if (NC == 3) {
-      kx = f % gg.xh;
-      ky = f / gg.xh;
-    } else {
-      kx = f;
-      ky = 0;
-    }
     const double w = (kx == 0 || 2 * kx == gg.nx) ? 1.0 : 2.0;
 #pragma unroll
     for (int m = 0; m < EPT; ++m) {
@@ -579,12 +599,15 @@ __global__ __launch_bounds__((ColCfg<T, L, NC, VAR>::NT)) void k_stokes_green_re
       const int kz = NC == 3 ? i : 0;
       if (NC != 3) ky = i;
       T s[NC];
-      s[0] = sx[kx];
-      s[1] = sy[ky];
-      T Lk = lx[kx] + ly[ky];
+      s[0] = sx0;
+      T Lk;
       if constexpr (NC == 3) {
-        s[2] = sz[kz];
-        Lk += lz[kz];
+        s[1] = sy0;
+        s[2] = sv[m];
+        Lk = L01 + lv[m];
+      } else {
+        s[1] = sv[m];
+        Lk = L01 + lv[m];
       }
       const cplx<T> q = qv[m];
       const cplx<T> dp = dv[m];
@@ -624,7 +647,7 @@ __global__ __launch_bounds__((ColCfg<T, L, NC, VAR>::NT)) void k_stokes_green_re
     }
   }
   __syncthreads();  // the forward transform's last LDS reads are complete
-  RegFFT<T, L, NC, 1>::run(t, act, v, lds + col, PS, C::TX, tw);
+  RegFFT<T, L, NC, 1>::run(t, act, v, lds + col, PS, C::TX, twl);
   if (act) {
 #pragma unroll
     for (int m = 0; m < EPT; ++m) {
@@ -700,12 +723,14 @@ static hipError_t green_launch(const Geom& g, const DevTables<T>& tb, const Stok
   if (nblocks) *nblocks = nb;
   if constexpr (REG)
     ACM_LAUNCH((k_stokes_green_reg<T, LL, NC, VAR>), dim3(nb, 1, ncells), dim3(C::NT),
-                       C::LDS_BYTES, s, one, many, gg, par, tw, rt + tb.off.sx, rt + tb.off.lx,
-                       rt + tb.off.sy, rt + tb.off.ly, rt + tb.off.sz, rt + tb.off.lz);
+                       C::LDS_BYTES + Plan<LL>::tw_total * (int)sizeof(cplx<T>), s, one, many, gg,
+                       par, tw, rt + tb.off.sx, rt + tb.off.lx, rt + tb.off.sy, rt + tb.off.ly,
+                       rt + tb.off.sz, rt + tb.off.lz);
   else
     ACM_LAUNCH((k_stokes_green<T, LL, NC, VAR, SPL>), dim3(nb, 1, ncells), dim3(C::NT),
-                       C::LDS_BYTES, s, one, many, gg, par, tw, rt + tb.off.sx, rt + tb.off.lx,
-                       rt + tb.off.sy, rt + tb.off.ly, rt + tb.off.sz, rt + tb.off.lz);
+                       C::LDS_BYTES + Plan<LL>::tw_total * (int)sizeof(cplx<T>), s, one, many, gg,
+                       par, tw, rt + tb.off.sx, rt + tb.off.lx, rt + tb.off.sy, rt + tb.off.ly,
+                       rt + tb.off.sz, rt + tb.off.lz);
   return hipGetLastError();
 }
 
@@ -818,7 +843,8 @@ hipError_t launch_rows_step(const Geom& g, const DevTables<T>& tb, const StokesC
 #define CASE(M)                                                                               \
   case M: {                                                                                   \
     using C = RowCfg<T, M>;                                                                   \
-    ACM_LAUNCH((k_rows_step<T, M>), dim3((unsigned)nb), dim3(C::NT), C::LDS_BYTES, s, one,   \
+    constexpr int lds_bytes = C::LDS_BYTES + (Plan<M>::tw_total + M + 1) * (int)sizeof(cplx<T>); \
+    ACM_LAUNCH((k_rows_step<T, M>), dim3((unsigned)nb), dim3(C::NT), lds_bytes, s, one,      \
                par, green_blocks, g.dim, (int)g.nrows, g.ntot, g.nspec, ct + tb.off.tw_x,     \
                ct + tb.off.rtw);                                                              \
     return hipGetLastError();                                                                 \

@@ -55,7 +55,7 @@ template <typename T, int L, int D, int MODE, bool SL, bool FL>
 __global__ __launch_bounds__((TGCfg<T, L, tg_fields<D, SL, FL>()>::NT)) void k_transport_green(
     cplx<T>* __restrict__ spec, cplx<T>* __restrict__ chat, const cplx<T>* __restrict__ chat_m,
     double* __restrict__ partials, TransportCtl* ctl, TGreenGeom gg, int par, int judge,
-    const cplx<T>* __restrict__ tw, const T* __restrict__ sx, const T* __restrict__ lx,
+    const cplx<T>* __restrict__ tw_g, const T* __restrict__ sx, const T* __restrict__ lx,
     const T* __restrict__ sy, const T* __restrict__ ly, const T* __restrict__ sz,
     const T* __restrict__ lz) {
   using C = TGCfg<T, L, tg_fields<D, SL, FL>()>;
@@ -67,6 +67,8 @@ __global__ __launch_bounds__((TGCfg<T, L, tg_fields<D, SL, FL>()>::NT)) void k_t
   __shared__ int s_last;
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   if (MODE == 0 && transport_done(ctl)) return;
+  const cplx<T>* tw =
+      twiddles_to_lds<T, C::NT, Plan<L>::tw_total>(lds + tg_fields<D, SL, FL>() * PS, tw_g);
   const int P = gg.plane;
   const int f0 = blockIdx.x * C::TX;
   // transform threads: (field, t, column) when each field has its own threads
@@ -356,8 +358,8 @@ __global__ __launch_bounds__((SlabCfg<T, N, N>::NT))
 __attribute__((amdgpu_waves_per_eu(SlabCfg<T, N, N>::WPE_ONE))) void k_transport_slab(
     cplx<T>* __restrict__ spec, const T* __restrict__ u, const uint8_t* __restrict__ H,
     TransportCtl* ctl, const double* __restrict__ partials, int ngreen, int par, int64_t ntot,
-    int64_t nspec, const cplx<T>* __restrict__ twx, const cplx<T>* __restrict__ twy,
-    const cplx<T>* __restrict__ rtw) {
+    int64_t nspec, const cplx<T>* __restrict__ twx_g, const cplx<T>* __restrict__ twy_g,
+    const cplx<T>* __restrict__ rtw_g) {
   using S = SlabCfg<T, N, N>;
   using V = typename Vec4<T>::type;
   constexpr int R = N / 4;  // quads per row
@@ -398,6 +400,8 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, N, N>::WPE_ONE))) void k_transport
   // forward slab transform each)
   const int z = blockIdx.x, c = blockIdx.y, ax = c < 2 ? c : 2;
   const int64_t soff = (int64_t)z * N * S::XH;
+  const SlabTw<T> tws = slab_twiddles<T, N, N>(lds, twx_g, twy_g, rtw_g);
+  const cplx<T>*twx = tws.x, *twy = tws.y, *rtw = tws.r;
   slab_load_inverse<T, N, N>(lds, spec + ax * nspec + soff, twx, twy, rtw);
 
   const T gc = (T)ctl->g[ax], B0c = (T)ctl->B0[ax];
@@ -562,7 +566,8 @@ hipError_t launch_transport_green(const Geom& g, const DevTables<T>& tb, int mod
     using C = TGCfg<T, LL, tg_fields<DD, SLB, FLX>()>;                                       \
     const int nb = (int)((g.plane + C::TX - 1) / C::TX);                                     \
     ACM_LAUNCH((k_transport_green<T, LL, DD, MM, SLB, FLX>), dim3(nb), dim3(C::NT),          \
-                       C::LDS_BYTES, s, sp, cp, cm, partials, ctl, gg, par, judge,             \
+                       C::LDS_BYTES + Plan<LL>::tw_total * (int)sizeof(cplx<T>), s, sp, cp, cm,  \
+                       partials, ctl, gg, par, judge,                                          \
                        tw,                                                                   \
                        rt + tb.off.sx,                                                       \
                        rt + tb.off.lx, rt + tb.off.sy, rt + tb.off.ly, rt + tb.off.sz,       \

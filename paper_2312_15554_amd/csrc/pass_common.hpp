@@ -79,6 +79,18 @@ __device__ __forceinline__ void gather_to_lds(E* lds, int n, F ld) {
   batched_copy<E, NT, MAXN>(n, ld, [&](int e, const E& v) { lds[e] = v; });
 }
 
+// Copy the N twiddles of a pencil transform into LDS at dst; the stages then
+// read them there rather than waiting on global loads.  Visible after the
+// next barrier (the transforms read twiddles from their second stage on,
+// after the barrier that ends the first).
+template <typename T, int NT, int N>
+__device__ __forceinline__ const cplx<T>* twiddles_to_lds(cplx<T>* dst,
+                                                          const cplx<T>* __restrict__ tw) {
+  batched_copy<cplx<T>, NT, N>(
+      N, [&](int e) { return tw[e]; }, [&](int e, const cplx<T>& v) { dst[e] = v; });
+  return dst;
+}
+
 // The reverse: st(e, lds[e]) for e < n <= MAXN, the LDS reads of U elements
 // per thread issued together.
 template <typename E, int NT, int MAXN, int U = 4, typename F>

@@ -60,7 +60,11 @@ struct SlabCfg {
   static constexpr int NT = NT0 < 64 ? 64 : (NT0 > 1024 ? 1024 : NT0);
   static constexpr int GY = NT / TPPY;  // column groups per round
   static constexpr int GX = NT / TPPX;  // row groups per round
-  static constexpr int LDS_BYTES = NY * P2 * (int)sizeof(cplx<T>);
+  // the slab, then the twiddles of the x rows, the y columns and the
+  // real-pair step of the row transforms
+  static constexpr int TWX = Plan<M>::tw_total, TWY = Plan<NY>::tw_total, TWR = M + 1;
+  static constexpr int SLAB_BYTES = NY * P2 * (int)sizeof(cplx<T>);
+  static constexpr int LDS_BYTES = SLAB_BYTES + (TWX + TWY + TWR) * (int)sizeof(cplx<T>);
   static constexpr int NV = NX * NY;                     // voxels per slab
   static constexpr int NQ = NV / 4;                       // quads per slab
   static constexpr int QPT = (NQ + NT - 1) / NT;          // quads per thread
@@ -100,20 +104,46 @@ __device__ __forceinline__ void slab_load_lds(cplx<T>* lds, const cplx<T>* __res
   constexpr int NT = SlabCfg<T, NX, NY>::NT;
   const gmem<float4>* s = as_global(reinterpret_cast<const float4*>(src));
   float4* d = reinterpret_cast<float4*>(lds);
-  // every element is defined on every path (a conditional first write puts
-  // the array in scratch memory)
+  // every load is unconditional (the tail re-reads the last vector), so
+  // none waits inside a branch for the loads before it
   float4 b[C::PT];
 #pragma unroll
   for (int j = 0; j < C::PT; ++j) {
     const int i = threadIdx.x + j * NT;
-    b[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (C::EVEN || i < C::NV) b[j] = s[i];
+    b[j] = s[(C::EVEN || i < C::NV) ? i : C::NV - 1];
   }
 #pragma unroll
   for (int j = 0; j < C::PT; ++j) {
     const int i = threadIdx.x + j * NT;
     if (C::EVEN || i < C::NV) d[i] = b[j];
   }
+}
+
+// The twiddle tables of a slab pass, copied into LDS after the slab.  Every
+// butterfly stage of every column or row round reads its twiddles; from
+// global memory each stage waited on their loads, from LDS they arrive with
+// the stage's data (and lanes at the same pencil position read the same
+// address).  The copy needs a barrier before the first transform.
+template <typename T>
+struct SlabTw {
+  const cplx<T>* x;
+  const cplx<T>* y;
+  const cplx<T>* r;
+};
+template <typename T, int NX, int NY>
+__device__ __forceinline__ SlabTw<T> slab_twiddles(cplx<T>* lds, const cplx<T>* __restrict__ twx,
+                                                   const cplx<T>* __restrict__ twy,
+                                                   const cplx<T>* __restrict__ rtw) {
+  using S = SlabCfg<T, NX, NY>;
+  constexpr int NTW = S::TWX + S::TWY + S::TWR;
+  cplx<T>* t = lds + NY * S::P2;
+  batched_copy<cplx<T>, S::NT, NTW>(
+      NTW,
+      [&](int e) {
+        return e < S::TWX ? twx[e] : (e < S::TWX + S::TWY ? twy[e - S::TWX] : rtw[e - S::TWX - S::TWY]);
+      },
+      [&](int e, const cplx<T>& v) { t[e] = v; });
+  return SlabTw<T>{t, t + S::TWX, t + S::TWX + S::TWY};
 }
 
 // Store the half-spectrum slab held in LDS (contiguous, pitch XH) to `dst`
