@@ -118,7 +118,9 @@ def transport_section(H, u_flow, log):
         if st["kernel_calls"][k]:
             ms = st["kernel_ms"][k] / st["kernel_calls"][k]
             kern[k] = dict(avg_us=round(ms * 1e3, 2), calls=st["kernel_calls"][k],
-                           GBps=gbps(kernel_bytes(kind, nn3, 3, 0), ms))
+                           GBps=gbps(kernel_bytes(kind, nn3, 3, 0), ms),
+                           algorithmic_bytes=kernel_bytes(kind, nn3, 3, 0),
+                           traffic=counter_traffic(k, "transport128") if nn3 == 128 else None)
     out["kernels"] = kern
     # Flux form (face fluxes with harmonic-mean diffusivity): its fixed point
     # carries no A0, so the same problem at two comparison media gives the
@@ -350,7 +352,7 @@ def stokes256_section(log):
                kernels=per,
                roofline={"bound": "hbm", "kernel": dom, "achieved": round(ach, 1),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                         "traffic": None})
+                         "traffic": counter_traffic(dom, "stokes256")})
     log(f"256^3: {its} iterations in {t1 - t0:.2f} s, {out['voxel_iters_per_s'] / 1e9:.1f} G voxel-iter/s, "
         f"kernels {per}")
     return out
@@ -424,12 +426,21 @@ def kernel_bytes(kind: str, n: int, d: int, nsolid: int, real_bytes: int = 4) ->
     return float("nan")
 
 
-COUNTER_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                               "stokes3d_128_hbm_counters.md")
-# kernel kind -> symbol prefix of the 128^3 FP32 instance in the counter summary
-KERNEL_SYMBOL = {"local": "k_slab_local<float, 128, 128, false>",
-                 "local+rhs": "k_slab_local<float, 128, 128, true>",
-                 "rhs": "k_slab_rhs<float, 128, 128>"}
+_PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
+# workload -> (counter summary, kernel kind -> symbol prefix of its FP32 instance)
+COUNTER_SUMMARIES = {
+    "stokes128": (os.path.join(_PROFILES, "stokes3d_128_hbm_counters.md"),
+                  {"local": "k_slab_local<float, 128, 128, false>",
+                   "local+rhs": "k_slab_local<float, 128, 128, true>",
+                   "rhs": "k_slab_rhs<float, 128, 128>"}),
+    "stokes256": (os.path.join(_PROFILES, "stokes3d_256_hbm_counters.md"),
+                  {"local": "k_rows_step<float, 128>",
+                   "y_inv": "k_cols_reg<float, 256, 1>",
+                   "y_fwd": "k_cols_reg<float, 256, -1>"}),
+    "transport128": (os.path.join(_PROFILES, "transport3d_128_hbm_counters.md"),
+                     {"t_local": "k_transport_slab<float, 128>",
+                      "t_green": "k_transport_green<float, 128, 3, 0, true, false>"}),
+}
 
 
 def kernel_source_hash() -> str:
@@ -445,13 +456,15 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def counter_traffic(kind: str):
+def counter_traffic(kind: str, workload: str = "stokes128"):
     """HBM bytes per launch of `kind` from the committed rocprofv3 counter
-    summary: FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by the
-    ratio known bytes / counter reading of a plain device copy.  None when the
-    summary is missing, lacks the kernel, or was taken on other kernel sources."""
+    summary of `workload`: FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each
+    scaled by the ratio known bytes / counter reading of a plain device copy.
+    None when the summary is missing, lacks the kernel, or was taken on other
+    kernel sources."""
+    path, symbols = COUNTER_SUMMARIES[workload]
     try:
-        text = open(COUNTER_SUMMARY).read()
+        text = open(path).read()
     except OSError:
         return None
     meta = {}
@@ -469,7 +482,7 @@ def counter_traffic(kind: str):
                 pass
     if meta.get("source-sha256") != kernel_source_hash():
         return None
-    sym = KERNEL_SYMBOL.get(kind)
+    sym = symbols.get(kind)
     hits = [v for k, v in rows.items() if sym and k.startswith(f"acm::{sym}")]
     if len(hits) != 1 or "fetch-scale" not in meta or "write-scale" not in meta:
         return None

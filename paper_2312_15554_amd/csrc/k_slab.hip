@@ -121,7 +121,7 @@ __attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
     }
   }
   __syncthreads();
-  slab_cols<T, NX, NY, +1>(lds, twy);
+  slab_cols_inverse<T, NX, NY>(lds, twy);
   if constexpr (S::PF == 1) {
     // a is issued here: its latency overlaps the row transforms, and fewer
     // registers stay live across the column transforms
@@ -131,15 +131,7 @@ __attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
       if (S::FULL || q < S::NQ) ao[j] = aq[q];
     }
   }
-  {
-    const int grp = threadIdx.x % S::GX, t = threadIdx.x / S::GX;  // row index fastest
-#pragma unroll 1
-    for (int r0 = 0; r0 < NY; r0 += S::GX) {
-      const int row = r0 + grp;
-      const bool act = t < S::TPPX && row < NY;
-      rows_c2r_lds<T, S::M, 1, S::P2>(lds, 0, act ? row : 0, t, act, twx, rtw);
-    }
-  }
+  slab_rows_inverse<T, NX, NY>(lds, twx, rtw);
 
   // Steps 2-3 on 4 consecutive voxels per quad.  The fused pass keeps the new
   // a and the solid flags of its quads for the rhs half (u stays in LDS).

@@ -145,7 +145,9 @@ struct RowCfgN {
 // Turn half spectra X[0..M] of row `row` of NF fields into real rows x[0..2M)
 // in place (imaginary parts of X[0] and X[M] are ignored) (the row then reads as T[2M]).  The inverse is unnormalised along
 // x, so the real row equals nx * (inverse DFT of X).  Ends with a barrier.
-template <typename T, int M, int NF = 1, int RP = M + 1>
+// PK: the row holds its (real) DC and Nyquist values packed in X[0] as
+// (X_0, X_M), and X[M] is not read.
+template <typename T, int M, int NF = 1, int RP = M + 1, bool PK = false>
 __device__ __forceinline__ void rows_c2r_lds(cplx<T>* lds, int fstride, int row, int t,
                                              bool active, const cplx<T>* __restrict__ tw,
                                              const cplx<T>* __restrict__ rtw) {
@@ -159,7 +161,7 @@ __device__ __forceinline__ void rows_c2r_lds(cplx<T>* lds, int fstride, int row,
         if (k == 0) {
           // DC and Nyquist bins of a real row are real: their imaginary parts
           // are ignored (the usual inverse real transform)
-          const T x0 = r[0].x, xm = r[M].x;
+          const T x0 = r[0].x, xm = PK ? r[0].y : r[M].x;
           r[0] = cmake<T>(x0 + xm, x0 - xm);
         } else if (2 * k == M) {
           r[k] = cscale(cconj(r[k]), T(2));
@@ -181,7 +183,9 @@ __device__ __forceinline__ void rows_c2r_lds(cplx<T>* lds, int fstride, int row,
 
 // Turn real rows x[0..2M) (stored as M complex) of NF fields into half spectra
 // X[0..M] in place (forward, unnormalised).  Ends with a barrier.
-template <typename T, int M, int NF = 1, int RP = M + 1>
+// PK: the real DC and Nyquist values go packed into X[0] as (X_0, X_M), and
+// X[M] is not written.
+template <typename T, int M, int NF = 1, int RP = M + 1, bool PK = false>
 __device__ __forceinline__ void rows_r2c_lds(cplx<T>* lds, int fstride, int row, int t,
                                              bool active, const cplx<T>* __restrict__ tw,
                                              const cplx<T>* __restrict__ rtw) {
@@ -196,8 +200,12 @@ __device__ __forceinline__ void rows_r2c_lds(cplx<T>* lds, int fstride, int row,
         cplx<T>* r = lds + fi * fstride + row * RP;
         if (k == 0) {
           cplx<T> z = r[0];
-          r[0] = cmake<T>(z.x + z.y, T(0));
-          r[M] = cmake<T>(z.x - z.y, T(0));
+          if constexpr (PK) {
+            r[0] = cmake<T>(z.x + z.y, z.x - z.y);
+          } else {
+            r[0] = cmake<T>(z.x + z.y, T(0));
+            r[M] = cmake<T>(z.x - z.y, T(0));
+          }
         } else if (2 * k == M) {
           r[k] = cconj(r[k]);
         } else {

@@ -60,6 +60,13 @@ struct SlabCfg {
   static constexpr int NT = NT0 < 64 ? 64 : (NT0 > 1024 ? 1024 : NT0);
   static constexpr int GY = NT / TPPY;  // column groups per round
   static constexpr int GX = NT / TPPX;  // row groups per round
+  // PACK: the DC and Nyquist columns (k = 0 and M), whose y transforms are
+  // Hermitian in the inverse direction and real in the forward one, share
+  // one complex column transform (column 0 carries X_0 + i X_M) where that
+  // saves a round of column transforms (XH = M + 1 columns in rounds of GY:
+  // at 128^2, 64 columns in two rounds instead of 65 in three).
+  static constexpr bool PACK = (XH - 1 + GY - 1) / GY < (XH + GY - 1) / GY;
+  static constexpr int XC = PACK ? XH - 1 : XH;  // columns transformed
   // the slab, then the twiddles of the x rows, the y columns and the
   // real-pair step of the row transforms
   static constexpr int TWX = Plan<M>::tw_total, TWY = Plan<NY>::tw_total, TWR = M + 1;
@@ -172,7 +179,7 @@ __device__ __forceinline__ void slab_store_lds(cplx<T>* __restrict__ dst, const 
   }
 }
 
-// y transform of all XH columns of the slab held in LDS ([y][k], pitch P2).
+// y transform of the XC columns of the slab held in LDS ([y][k], pitch P2).
 template <typename T, int NX, int NY, int SIGN>
 __device__ __forceinline__ void slab_cols(cplx<T>* lds, const cplx<T>* __restrict__ tw) {
   using S = SlabCfg<T, NX, NY>;
@@ -182,11 +189,83 @@ __device__ __forceinline__ void slab_cols(cplx<T>* lds, const cplx<T>* __restric
   // uniform across the wave
   const int grp = threadIdx.x % S::GY, t = threadIdx.x / S::GY;
 #pragma unroll 1
-  for (int c0 = 0; c0 < S::XH; c0 += S::GY) {
+  for (int c0 = 0; c0 < S::XC; c0 += S::GY) {
     const int col = c0 + grp;
-    const bool act = t < S::TPPY && col < S::XH;
+    const bool act = t < S::TPPY && col < S::XC;
     PencilFFT<T, NY, 1, SIGN>::run_lds(t, act, lds + (act ? col : 0), 0, S::P2, tw);
     __syncthreads();
+  }
+}
+
+// Inverse y transforms of a half-spectrum slab in LDS (after a barrier that
+// follows its load).  With PACK, column 0 first takes X_0 + i X_M: both
+// columns are Hermitian in y, so their inverse transforms are real and come
+// out as the real and imaginary parts of column 0, which is how the row
+// transforms then read them.
+template <typename T, int NX, int NY>
+__device__ __forceinline__ void slab_cols_inverse(cplx<T>* lds, const cplx<T>* __restrict__ twy) {
+  using S = SlabCfg<T, NX, NY>;
+  if constexpr (S::PACK) {
+    for (int y = threadIdx.x; y < NY; y += S::NT) {
+      cplx<T>* r = lds + y * S::P2;
+      const cplx<T> a = r[0], b = r[S::M];
+      r[0] = cmake<T>(a.x - b.y, a.y + b.x);
+    }
+    __syncthreads();
+  }
+  slab_cols<T, NX, NY, +1>(lds, twy);
+}
+
+// Forward y transforms of the slab in LDS after the row transforms.  With
+// PACK, column 0 holds z = X_0 + i X_M of two real columns; their transforms
+// are (Z_k + conj Z_-k) / 2 and (Z_k - conj Z_-k) / 2i, written to columns 0
+// and M.  Ends with a barrier.
+template <typename T, int NX, int NY>
+__device__ __forceinline__ void slab_cols_forward(cplx<T>* lds, const cplx<T>* __restrict__ twy) {
+  using S = SlabCfg<T, NX, NY>;
+  slab_cols<T, NX, NY, -1>(lds, twy);
+  if constexpr (S::PACK) {
+    for (int k = threadIdx.x; k <= NY / 2; k += S::NT) {
+      const int km = k == 0 ? 0 : NY - k;
+      cplx<T>* rk = lds + k * S::P2;
+      cplx<T>* rm = lds + km * S::P2;
+      const cplx<T> zk = rk[0], zm = rm[0];
+      const cplx<T> e = cmake<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));  // (Z_k + conj Z_-k)/2
+      const cplx<T> o = cmake<T>(T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x));  // (Z_k - conj Z_-k)/2i
+      rk[0] = e;
+      rk[S::M] = o;
+      rm[0] = cconj(e);
+      rm[S::M] = cconj(o);
+    }
+    __syncthreads();
+  }
+}
+
+// x transforms of the NY rows of a slab in LDS (row index fastest across the
+// lanes: rows are an odd number of banks apart, so every stage is
+// conflict-free).  Inverse: half spectra to real rows; forward: the reverse.
+template <typename T, int NX, int NY>
+__device__ __forceinline__ void slab_rows_inverse(cplx<T>* lds, const cplx<T>* __restrict__ twx,
+                                                  const cplx<T>* __restrict__ rtw) {
+  using S = SlabCfg<T, NX, NY>;
+  const int grp = threadIdx.x % S::GX, t = threadIdx.x / S::GX;
+#pragma unroll 1
+  for (int r0 = 0; r0 < NY; r0 += S::GX) {
+    const int row = r0 + grp;
+    const bool act = t < S::TPPX && row < NY;
+    rows_c2r_lds<T, S::M, 1, S::P2, S::PACK>(lds, 0, act ? row : 0, t, act, twx, rtw);
+  }
+}
+template <typename T, int NX, int NY>
+__device__ __forceinline__ void slab_rows_forward(cplx<T>* lds, const cplx<T>* __restrict__ twx,
+                                                  const cplx<T>* __restrict__ rtw) {
+  using S = SlabCfg<T, NX, NY>;
+  const int grp = threadIdx.x % S::GX, t = threadIdx.x / S::GX;
+#pragma unroll 1
+  for (int r0 = 0; r0 < NY; r0 += S::GX) {
+    const int row = r0 + grp;
+    const bool act = t < S::TPPX && row < NY;
+    rows_r2c_lds<T, S::M, 1, S::P2, S::PACK>(lds, 0, act ? row : 0, t, act, twx, rtw);
   }
 }
 
@@ -197,19 +276,8 @@ __device__ __forceinline__ void slab_forward_store(cplx<T>* lds, cplx<T>* __rest
                                                    const cplx<T>* __restrict__ twx,
                                                    const cplx<T>* __restrict__ twy,
                                                    const cplx<T>* __restrict__ rtw) {
-  using S = SlabCfg<T, NX, NY>;
-  {
-    // row index fastest across the lanes (rows are an odd number of banks
-    // apart): conflict-free at every stage
-    const int grp = threadIdx.x % S::GX, t = threadIdx.x / S::GX;
-#pragma unroll 1
-    for (int r0 = 0; r0 < NY; r0 += S::GX) {
-      const int row = r0 + grp;
-      const bool act = t < S::TPPX && row < NY;
-      rows_r2c_lds<T, S::M, 1, S::P2>(lds, 0, act ? row : 0, t, act, twx, rtw);
-    }
-  }
-  slab_cols<T, NX, NY, -1>(lds, twy);
+  slab_rows_forward<T, NX, NY>(lds, twx, rtw);
+  slab_cols_forward<T, NX, NY>(lds, twy);
   slab_store_lds<T, NX, NY>(dst, lds);
 }
 
@@ -222,17 +290,10 @@ __device__ __forceinline__ void slab_load_inverse(cplx<T>* lds, const cplx<T>* _
                                                   const cplx<T>* __restrict__ twx,
                                                   const cplx<T>* __restrict__ twy,
                                                   const cplx<T>* __restrict__ rtw) {
-  using S = SlabCfg<T, NX, NY>;
   slab_load_lds<T, NX, NY>(lds, src);
   __syncthreads();
-  slab_cols<T, NX, NY, +1>(lds, twy);
-  const int grp = threadIdx.x % S::GX, t = threadIdx.x / S::GX;  // row index fastest
-#pragma unroll 1
-  for (int r0 = 0; r0 < NY; r0 += S::GX) {
-    const int row = r0 + grp;
-    const bool act = t < S::TPPX && row < NY;
-    rows_c2r_lds<T, S::M, 1, S::P2>(lds, 0, act ? row : 0, t, act, twx, rtw);
-  }
+  slab_cols_inverse<T, NX, NY>(lds, twy);
+  slab_rows_inverse<T, NX, NY>(lds, twx, rtw);
 }
 
 // Square slab lengths compiled for the fused passes.
