@@ -27,11 +27,12 @@ struct TGreenGeom {
 };
 
 // Tile configuration of the green pass (see ColCfg): pencil-count variant and
-// whether each field gets its own threads during the transforms.  Measured at
-// 128^3 FP32 (one box, same run): 102 us with 14 pencils per workgroup and
-// all fields per thread, 65.9 us with one thread group per field, 108 and
-// 85.6 us with 8 pencils per workgroup.
-constexpr int kTGVar = 0;
+// whether each field gets its own threads during the transforms (which takes
+// it from 102 to 65.9 us per LS iteration at 128^3 FP32).  Half-width tiles
+// (8 pencils): at 128^3 the 1,040 tiles all fit on the chip at once (five
+// workgroups of 384 threads per CU), where 520 full-width tiles of 768
+// threads leave 8 for a second round (24.7 against 27.0 us).
+constexpr int kTGVar = 1;
 constexpr int kTGSpl = 1;
 template <typename T, int L, int NC>
 using TGCfg = ColCfg<T, L, NC, kTGVar, kTGSpl>;
