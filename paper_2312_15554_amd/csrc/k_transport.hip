@@ -71,7 +71,9 @@ __global__ __launch_bounds__((TGCfg<T, L, tg_fields<D, SL, FL>()>::NT)) void k_t
   const cplx<T>* tw =
       twiddles_to_lds<T, C::NT, Plan<L>::tw_total>(lds + tg_fields<D, SL, FL>() * PS, tw_g);
   const int P = gg.plane;
-  const int f0 = blockIdx.x * C::TX;
+  // neighbouring tiles share the cache lines at their edges (a tile row is
+  // half a line of FP32 complex): keep them on one XCD, whose L2 they share
+  const int f0 = xcd_tile(blockIdx.x, gridDim.x) * C::TX;
   // transform threads: (field, t, column) when each field has its own threads
   const int fc = kTGSpl ? threadIdx.x / (C::TPP * C::TX) : 0;
   const int tr = kTGSpl ? threadIdx.x % (C::TPP * C::TX) : threadIdx.x;
