@@ -239,6 +239,9 @@ def fno_section(args, log, cells):
     # (2) every 256^3 test cell, plain vs warm at eps = 1e-6
     tests = []
     test_cells = W.make_cells(256, args.fno_test, 20000, 16.0, 0.35, 0.50)
+    if test_cells:  # the 256^3 plan is tuned before any timed solve
+        acm_stokes_solve(torch.from_numpy(test_cells[0]).cuda(), (1.0, 0.0, 0.0), eps=1e-6, max_iter=400,
+                         want_q=False)
     for i, c in enumerate(test_cells):
         r = W.solve_plain_and_warm(net, norm, torch.from_numpy(c).cuda(), eps=1e-6)
         log(f"fno test cell {i}: {r}")
