@@ -172,6 +172,103 @@ __global__ __launch_bounds__(256) void k_fno_pointwise_bwd(const float* __restri
   }
 }
 
+// ------------------------------------------- pointwise layer on matrix cores
+// The 32-channel mix is a dense contraction, pre[o][x] = sum_i W[o][i] v[i][x]
+// over 32 voxels per wave: v_mfma_f32_32x32x2_f32 takes W (32 x 2, lane l
+// holding W[l % 32][2 s + l / 32] at step s) and v (2 x 32, lane l holding
+// v[2 s + l / 32][x0 + l % 32]) and accumulates the 32 x 32 tile over 16
+// steps in FP32, with the same operands (BF16-rounded weights, FP32
+// activations) as the vector kernel.  Lane l then holds rows
+// 8 (r / 4) + 4 (l / 32) + r % 4 of column l % 32 in its register r.
+typedef float mfma_f32x16 __attribute__((ext_vector_type(16)));
+constexpr int kMixTiles = 4;  // 32-voxel tiles per wave (the weights are loaded once)
+
+__device__ __forceinline__ int mix_row(int r, int half) { return 8 * (r / 4) + 4 * half + (r % 4); }
+
+__global__ __launch_bounds__(256) void k_fno_pointwise_mfma(const float* __restrict__ vin,
+                                                            const float* __restrict__ k,
+                                                            const uint16_t* __restrict__ W,
+                                                            const uint16_t* __restrict__ bias,
+                                                            float* __restrict__ pre,
+                                                            float* __restrict__ vout, int64_t nvox,
+                                                            int act) {
+  constexpr int C = 32;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 31, half = lane >> 5;
+  const int b = blockIdx.y;
+  float wa[16], br[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) wa[s] = bf2f(W[col * C + 2 * s + half]);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) br[r] = bf2f(bias[mix_row(r, half)]);
+  const int64_t base = (int64_t)b * C * nvox;
+  for (int tt = 0; tt < kMixTiles; ++tt) {
+    const int64_t x0 = (((int64_t)blockIdx.x * 4 + wave) * kMixTiles + tt) * 32;
+    if (x0 >= nvox) break;  // the same for the whole wave
+    const int64_t x = x0 + col;
+    const bool in = x < nvox;
+    float bv[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) bv[s] = in ? vin[base + (int64_t)(2 * s + half) * nvox + x] : 0.f;
+    mfma_f32x16 acc = {};
+#pragma unroll
+    for (int s = 0; s < 16; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wa[s], bv[s], acc, 0, 0, 0);
+    if (in) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t off = base + (int64_t)mix_row(r, half) * nvox + x;
+        const float v = acc[r] + br[r] + k[off];
+        if (pre) pre[off] = v;
+        vout[off] = act ? gelu_f(v) : v;
+      }
+    }
+  }
+}
+
+// dpre = dv * act'(pre);  dvdir = W^T dpre, the contraction on matrix cores
+// as above with W^T (lane l holding W[2 s + l / 32][l % 32] at step s) and
+// dpre (formed in the lane that feeds it to the step).
+__global__ __launch_bounds__(256) void k_fno_pointwise_bwd_mfma(const float* __restrict__ dv,
+                                                                const float* __restrict__ pre,
+                                                                const uint16_t* __restrict__ W,
+                                                                float* __restrict__ dpre,
+                                                                float* __restrict__ dvdir,
+                                                                int64_t nvox, int act) {
+  constexpr int C = 32;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 31, half = lane >> 5;
+  const int b = blockIdx.y;
+  float wa[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) wa[s] = bf2f(W[(2 * s + half) * C + col]);
+  const int64_t base = (int64_t)b * C * nvox;
+  for (int tt = 0; tt < kMixTiles; ++tt) {
+    const int64_t x0 = (((int64_t)blockIdx.x * 4 + wave) * kMixTiles + tt) * 32;
+    if (x0 >= nvox) break;
+    const int64_t x = x0 + col;
+    const bool in = x < nvox;
+    float dp[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int64_t off = base + (int64_t)(2 * s + half) * nvox + x;
+      float g = 0.f;
+      if (in) {
+        g = dv[off];
+        if (act) g *= gelu_grad_f(pre[off]);
+        dpre[off] = g;
+      }
+      dp[s] = g;
+    }
+    mfma_f32x16 acc = {};
+#pragma unroll
+    for (int s = 0; s < 16; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wa[s], dp[s], acc, 0, 0, 0);
+    if (in) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) dvdir[base + (int64_t)mix_row(r, half) * nvox + x] = acc[r];
+    }
+  }
+}
+
 // dv += other
 __global__ __launch_bounds__(256) void k_fno_add(float* __restrict__ a, const float* __restrict__ b,
                                                  int64_t n) {
@@ -418,6 +515,12 @@ hipError_t fno_dR(const void* Fm, const void* Xm, const float* mw, float* dR, in
 hipError_t fno_pointwise(int C, const float* vin, const float* k, const uint16_t* W,
                          const uint16_t* b, float* pre, float* vout, int64_t nvox, int B,
                          int act, hipStream_t s) {
+  if (C == 32) {  // matrix cores: 4 waves x kMixTiles tiles of 32 voxels per workgroup
+    const int64_t per = 4 * kMixTiles * 32;
+    hipLaunchKernelGGL(k_fno_pointwise_mfma, dim3((unsigned)((nvox + per - 1) / per), (unsigned)B),
+                       dim3(256), 0, s, vin, k, W, b, pre, vout, nvox, act);
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)((nvox + 255) / 256), (unsigned)B);
   switch (C) {
 #define CASE(CC)                                                                              \
@@ -435,6 +538,13 @@ hipError_t fno_pointwise(int C, const float* vin, const float* k, const uint16_t
 hipError_t fno_pointwise_bwd(int C, const float* dv, const float* pre, const uint16_t* W,
                              float* dpre, float* dvdir, int64_t nvox, int B, int act,
                              hipStream_t s) {
+  if (C == 32) {
+    const int64_t per = 4 * kMixTiles * 32;
+    hipLaunchKernelGGL(k_fno_pointwise_bwd_mfma,
+                       dim3((unsigned)((nvox + per - 1) / per), (unsigned)B), dim3(256), 0, s, dv,
+                       pre, W, dpre, dvdir, nvox, act);
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)((nvox + 255) / 256), (unsigned)B);
   switch (C) {
 #define CASE(CC)                                                                              \

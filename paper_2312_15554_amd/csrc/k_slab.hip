@@ -102,9 +102,10 @@ __attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
   }
 
   cplx<T>* slab = spec + field * nspec + (int64_t)z * NY * S::XH;
+  float4 stg[SlabCopy<T, NX, NY>::PT];
+  slab_load_regs<T, NX, NY>(stg, slab);  // in flight during the partial sums below
   const SlabTw<T> tws = slab_twiddles<T, NX, NY>(lds, twx_g, twy_g, rtw_g);
   const cplx<T>*twx = tws.x, *twy = tws.y, *rtw = tws.r;
-  slab_load_lds<T, NX, NY>(lds, slab);
   if constexpr (!FUSED) {
     if (threadIdx.x < kShare) {
       const int nb = gridDim.x * gridDim.y, b = blockIdx.y * gridDim.x + blockIdx.x;
@@ -120,6 +121,7 @@ __attribute__((amdgpu_waves_per_eu(FUSED ? SlabCfg<T, NX, NY>::WPE_ONE
       gsh[threadIdx.x * 3 + 2] = s2;
     }
   }
+  slab_regs_to_lds<T, NX, NY>(lds, stg);
   __syncthreads();
   slab_cols_inverse<T, NX, NY>(lds, twy);
   if constexpr (S::PF == 1) {

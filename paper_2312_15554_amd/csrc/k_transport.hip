@@ -405,7 +405,10 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, N, N>::WPE_ONE))) void k_transport
   const int64_t soff = (int64_t)z * N * S::XH;
   const SlabTw<T> tws = slab_twiddles<T, N, N>(lds, twx_g, twy_g, rtw_g);
   const cplx<T>*twx = tws.x, *twy = tws.y, *rtw = tws.r;
-  slab_load_inverse<T, N, N>(lds, spec + ax * nspec + soff, twx, twy, rtw);
+  slab_load_lds<T, N, N>(lds, spec + ax * nspec + soff);
+  __syncthreads();
+  slab_cols_inverse<T, N, N>(lds, twy);
+  slab_rows_inverse<T, N, N>(lds, twx, rtw);
 
   const T gc = (T)ctl->g[ax], B0c = (T)ctl->B0[ax];
   const T A0 = (T)ctl->A0, Pe = (T)ctl->Pe, eta = (T)ctl->eta, dif = (T)ctl->diff;

@@ -104,26 +104,40 @@ struct SlabCopy {
 // Load the half-spectrum slab `src` into LDS with 16-byte accesses, every
 // load of a thread issued before the first LDS write: the slab arrives in one
 // memory round trip rather than one per element (a loop that stores each
-// loaded value to LDS waits on every load in turn).
-template <typename T, int NX, int NY>
-__device__ __forceinline__ void slab_load_lds(cplx<T>* lds, const cplx<T>* __restrict__ src) {
+// loaded value to LDS waits on every load in turn).  In two halves, so that
+// a kernel can do other work while the loads are in flight:
+// slab_load_regs issues them (into b), slab_regs_to_lds writes them.
+template <typename T, int NX, int NY, int PT>
+__device__ __forceinline__ void slab_load_regs(float4 (&b)[PT], const cplx<T>* __restrict__ src) {
   using C = SlabCopy<T, NX, NY>;
+  static_assert(PT == C::PT, "register stage of the slab's size");
   constexpr int NT = SlabCfg<T, NX, NY>::NT;
   const gmem<float4>* s = as_global(reinterpret_cast<const float4*>(src));
-  float4* d = reinterpret_cast<float4*>(lds);
   // every load is unconditional (the tail re-reads the last vector), so
   // none waits inside a branch for the loads before it
-  float4 b[C::PT];
 #pragma unroll
   for (int j = 0; j < C::PT; ++j) {
     const int i = threadIdx.x + j * NT;
     b[j] = s[(C::EVEN || i < C::NV) ? i : C::NV - 1];
   }
+}
+template <typename T, int NX, int NY, int PT>
+__device__ __forceinline__ void slab_regs_to_lds(cplx<T>* lds, const float4 (&b)[PT]) {
+  using C = SlabCopy<T, NX, NY>;
+  static_assert(PT == C::PT, "register stage of the slab's size");
+  constexpr int NT = SlabCfg<T, NX, NY>::NT;
+  float4* d = reinterpret_cast<float4*>(lds);
 #pragma unroll
   for (int j = 0; j < C::PT; ++j) {
     const int i = threadIdx.x + j * NT;
     if (C::EVEN || i < C::NV) d[i] = b[j];
   }
+}
+template <typename T, int NX, int NY>
+__device__ __forceinline__ void slab_load_lds(cplx<T>* lds, const cplx<T>* __restrict__ src) {
+  float4 b[SlabCopy<T, NX, NY>::PT];
+  slab_load_regs<T, NX, NY>(b, src);
+  slab_regs_to_lds<T, NX, NY>(lds, b);
 }
 
 // The twiddle tables of a slab pass, copied into LDS after the slab.  Every
@@ -285,16 +299,7 @@ __device__ __forceinline__ void slab_forward_store(cplx<T>* lds, cplx<T>* __rest
 // to real space: inverse y transforms of the columns, then inverse x
 // transforms of the rows.  Row y of the result starts at real offset
 // y * 2 * P2.  Ends with a barrier.
-template <typename T, int NX, int NY>
-__device__ __forceinline__ void slab_load_inverse(cplx<T>* lds, const cplx<T>* __restrict__ src,
-                                                  const cplx<T>* __restrict__ twx,
-                                                  const cplx<T>* __restrict__ twy,
-                                                  const cplx<T>* __restrict__ rtw) {
-  slab_load_lds<T, NX, NY>(lds, src);
-  __syncthreads();
-  slab_cols_inverse<T, NX, NY>(lds, twy);
-  slab_rows_inverse<T, NX, NY>(lds, twx, rtw);
-}
+
 
 // Square slab lengths compiled for the fused passes.
 #define ACM_SLAB_LENGTHS(X) X(32) X(48) X(64) X(96) X(128)

@@ -37,8 +37,11 @@ def _flat_grad(net, g):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("n,C,m,L,B", [(8, 4, 2, 2, 2), (16, 8, 3, 3, 2)])
+@pytest.mark.parametrize("n,C,m,L,B", [(8, 4, 2, 2, 2), (16, 8, 3, 3, 2), (16, 32, 3, 2, 2)])
 def test_fno_forward_and_gradients_match_oracle(n, C, m, L, B):
+    """Forward pass and every parameter gradient against the FP64 oracle on
+    the same BF16 weights.  32 channels take the matrix-core kernels of the
+    pointwise mix (the width the warm start trains), fewer the vector ones."""
     require_gpu()
     from paper_2312_15554_amd.fno import FNO
     print(f"fno grad check n={n} C={C} m={m} L={L} B={B}", flush=True)
