@@ -507,6 +507,17 @@ def main():
     from paper_2312_15554_amd import inputs as I
     from paper_2312_15554_amd.api import acm_effective_props, acm_stokes_solve
 
+    if args.copy_probe_mib:
+        # a plain copy of known size: calibrates the HBM byte counters (before
+        # anything else, so that no worker pool runs under a profiler)
+        import torch
+        a = torch.ones(args.copy_probe_mib * (1 << 18), dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": a.numel() * 4, "launches": 10}))
+        return
     # the FNO training cells are built first, in a forked pool, while the
     # process has not touched the GPU yet
     fno_cells = None
@@ -520,15 +531,6 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
-    if args.copy_probe_mib:
-        # a plain copy of known size: calibrates the HBM byte counters
-        a = torch.ones(args.copy_probe_mib * (1 << 18), dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(10):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_each_way": a.numel() * 4, "launches": 10}))
-        return
     n, d = args.n, 3
     H_np = I.overlapping_spheres(n, 8.0 * n / 128.0, 0.40, seed=1)
     nsolid = int(H_np.sum())

@@ -383,9 +383,22 @@ __attribute__((amdgpu_waves_per_eu(SlabCfg<T, N, N>::WPE_ONE))) void k_transport
     const TransportState cur = ctl->st[par];
     double tot[2] = {0.0, 0.0};
     if (cur.pend) {
-      for (int j = threadIdx.x; j < ngreen; j += S::NT) {
-        tot[0] += partials[j * 2 + 0];
-        tot[1] += partials[j * 2 + 1];
+      // four partials per thread in flight at a time (one green tile each;
+      // 1,040 tiles at 128^3): the sum is one memory round trip, not three
+      constexpr int U = 4;
+      for (int j0 = threadIdx.x; j0 < ngreen; j0 += U * S::NT) {
+        double v[U][2];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+          const int j = j0 + k * S::NT;
+          v[k][0] = j < ngreen ? partials[j * 2 + 0] : 0.0;
+          v[k][1] = j < ngreen ? partials[j * 2 + 1] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+          tot[0] += v[k][0];
+          tot[1] += v[k][1];
+        }
       }
       block_sum<2>(tot, red);
     }
