@@ -59,56 +59,120 @@ __global__ __launch_bounds__(256) void k_fno_gather(const float2* __restrict__ s
 
 // Y[b][o][m] = sum_i R[m][o][i] X[b][i][m] (conj(R) and sum over o when
 // ADJ: Z[b][i][m] = sum_o conj(R[m][o][i]) X[b][o][m]); scattered into the
-// (cleared) full spectrum at the kept-mode offsets.
-template <bool ADJ>
+// (cleared) full spectrum at the kept-mode offsets.  A workgroup takes JT =
+// 256 / C consecutive modes: their weights (C x C complex BF16 pairs per mode,
+// contiguous) are staged in LDS with coalesced loads and a padded row, so that
+// thread (c, jj) reads row c of R[m] (or column c for the adjoint) without
+// bank conflicts and keeps it in registers while it runs through the batch;
+// the activations of a chunk of batch members are staged beside them.
+template <bool ADJ, int C>
 __global__ __launch_bounds__(256) void k_fno_mix(const float2* __restrict__ Xm,
                                                  const uint16_t* __restrict__ R,
                                                  float2* __restrict__ spec,
-                                                 const int* __restrict__ midx, int nm, int C,
+                                                 const int* __restrict__ midx, int nm, int B,
                                                  int64_t nspec) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int o = blockIdx.y;  // output channel
-  const int b = blockIdx.z;
-  if (j >= nm) return;
-  float ar = 0.f, ai = 0.f;
-  for (int i = 0; i < C; ++i) {
-    // R[m][o][i] complex (re, im) as bf16 pairs; adjoint uses R[m][i][o] conjugated
-    const int64_t ri = ADJ ? (((int64_t)j * C + i) * C + o) : (((int64_t)j * C + o) * C + i);
-    const float rr = bf2f(R[2 * ri]), rim = bf2f(R[2 * ri + 1]);
-    const float2 x = Xm[((int64_t)b * C + i) * nm + j];
-    if (!ADJ) {
-      ar += rr * x.x - rim * x.y;
-      ai += rr * x.y + rim * x.x;
-    } else {
-      ar += rr * x.x + rim * x.y;
-      ai += rr * x.y - rim * x.x;
+  constexpr int JT = 256 / C, RS = C + 1, BT = 8;
+  __shared__ uint32_t sR[JT * C * RS];
+  __shared__ float2 sX[BT * C * JT];
+  const int j0 = blockIdx.x * JT;
+  const int nj = min(JT, nm - j0);
+  const uint32_t* gR = reinterpret_cast<const uint32_t*>(R) + (int64_t)j0 * C * C;
+  for (int e = threadIdx.x; e < nj * C * C; e += 256) sR[(e / C) * RS + e % C] = gR[e];
+  const int c = threadIdx.x / JT, jj = threadIdx.x % JT;
+  const bool live = jj < nj;
+  const int64_t sidx = live ? midx[j0 + jj] : 0;
+  __syncthreads();
+  float rr[C], ri[C];
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    // real part in the low half of the pair, imaginary in the high half
+    const uint32_t w = ADJ ? sR[(jj * C + k) * RS + c] : sR[(jj * C + c) * RS + k];
+    rr[k] = __uint_as_float(w << 16);
+    ri[k] = __uint_as_float(w & 0xffff0000u);
+  }
+  for (int b0 = 0; b0 < B; b0 += BT) {
+    const int nb = min(BT, B - b0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nb * C * JT; e += 256) {
+      const int jx = e % JT, bi = e / JT;  // bi = (batch member in chunk) * C + channel
+      sX[e] = jx < nj ? Xm[((int64_t)b0 * C + bi) * nm + j0 + jx] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    if (!live) continue;
+    for (int bb = 0; bb < nb; ++bb) {
+      float ar = 0.f, ai = 0.f;
+#pragma unroll
+      for (int k = 0; k < C; ++k) {
+        const float2 x = sX[(bb * C + k) * JT + jj];
+        if (!ADJ) {
+          ar += rr[k] * x.x - ri[k] * x.y;
+          ai += rr[k] * x.y + ri[k] * x.x;
+        } else {
+          ar += rr[k] * x.x + ri[k] * x.y;
+          ai += rr[k] * x.y - ri[k] * x.x;
+        }
+      }
+      spec[((int64_t)(b0 + bb) * C + c) * nspec + sidx] = make_float2(ar, ai);
     }
   }
-  spec[((int64_t)b * C + o) * nspec + midx[j]] = make_float2(ar, ai);
 }
 
-// dR[m][o][i] = sum_b (w_m / N) F[b][o][m] conj(X[b][i][m])  (float pairs)
+// dR[m][o][i] = sum_b (w_m / N) F[b][o][m] conj(X[b][i][m])  (float pairs).
+// A workgroup takes JT = 256 / C consecutive modes, stages F and X of a chunk
+// of batch members in LDS (coalesced along the modes; the row padded by one so
+// that the threads of one mode read different banks) and writes the modes'
+// C x C gradients as one contiguous run.
+template <int C>
 __global__ __launch_bounds__(256) void k_fno_dR(const float2* __restrict__ Fm,
                                                 const float2* __restrict__ Xm,
                                                 const float* __restrict__ mw,
-                                                float* __restrict__ dR, int nm, int C, int B,
+                                                float* __restrict__ dR, int nm, int B,
                                                 float inv_n) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t total = (int64_t)nm * C * C;
-  if (t >= total) return;
-  const int i = (int)(t % C);
-  const int o = (int)((t / C) % C);
-  const int j = (int)(t / ((int64_t)C * C));
-  float ar = 0.f, ai = 0.f;
-  for (int b = 0; b < B; ++b) {
-    const float2 f = Fm[((int64_t)b * C + o) * nm + j];
-    const float2 x = Xm[((int64_t)b * C + i) * nm + j];
-    ar += f.x * x.x + f.y * x.y;
-    ai += f.y * x.x - f.x * x.y;
+  constexpr int JT = 256 / C, JS = JT + 1, BT = 8, PER = JT * C * C / 256;
+  __shared__ float2 sF[BT * C * JS], sX[BT * C * JS];
+  const int j0 = blockIdx.x * JT;
+  const int nj = min(JT, nm - j0);
+  float ar[PER], ai[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) ar[k] = ai[k] = 0.f;
+  for (int b0 = 0; b0 < B; b0 += BT) {
+    const int nb = min(BT, B - b0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nb * C * JT; e += 256) {
+      const int jx = e % JT, bi = e / JT;  // bi = (batch member in chunk) * C + channel
+      const int64_t g = ((int64_t)b0 * C + bi) * nm + j0 + jx;
+      float2 fv = make_float2(0.f, 0.f), xv = fv;
+      if (jx < nj) {
+        fv = Fm[g];
+        xv = Xm[g];
+      }
+      sF[bi * JS + jx] = fv;
+      sX[bi * JS + jx] = xv;
+    }
+    __syncthreads();
+    for (int bb = 0; bb < nb; ++bb) {
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int e = threadIdx.x + k * 256;
+        const int jj = e / (C * C), o = (e / C) % C, i = e % C;
+        const float2 f = sF[(bb * C + o) * JS + jj];
+        const float2 x = sX[(bb * C + i) * JS + jj];
+        ar[k] += f.x * x.x + f.y * x.y;
+        ai[k] += f.y * x.x - f.x * x.y;
+      }
+    }
   }
-  const float s = mw[j] * inv_n;
-  dR[2 * t] = ar * s;
-  dR[2 * t + 1] = ai * s;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = threadIdx.x + k * 256;
+    const int jj = e / (C * C);
+    if (jj < nj) {
+      const float sc = mw[j0 + jj] * inv_n;
+      const int64_t t = (int64_t)j0 * C * C + e;
+      dR[2 * t] = ar[k] * sc;
+      dR[2 * t + 1] = ai[k] * sc;
+    }
+  }
 }
 
 // --------------------------------------------------------- pointwise layer
@@ -419,14 +483,135 @@ __global__ __launch_bounds__(256) void k_fno_outer(const float* __restrict__ A,
   }
 }
 
-// out[e] = sum over blocks (in order) of part[blk][e]
-__global__ __launch_bounds__(256) void k_fno_sum_parts(const float* __restrict__ part, int nblk,
-                                                       int n, float* __restrict__ out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  double s = 0.0;
-  for (int k = 0; k < nblk; ++k) s += part[(int64_t)k * n + e];
-  out[e] = (float)s;
+// The same sums on the matrix cores.  G = A B^T over the B nvox voxels of the
+// batch is a dense contraction of two short matrices: a workgroup owns a group
+// of GP x GQ output blocks of 32 x 32 and walks 64-voxel tiles of the batch
+// (grid-stride, one batch member per tile since nvox is a multiple of 64).
+// Each tile's 32 (GP + GQ) rows of A and B are staged in LDS with coalesced
+// loads while the next tile's loads are in flight, and v_mfma_f32_32x32x2_f32
+// contracts them: with four blocks in the group each wave owns one block and
+// the whole tile; with fewer, the waves of a block split the tile's voxels and
+// their partial blocks are added in a fixed order at the end.  Since the
+// voxel index is only summed over, lane l takes voxel base + (l / 32) HALF + j
+// of row l % 32 at step j, so that it reads its operands as float4 runs.
+// Rows beyond P or Q are zero; BM selects B: 0 the matrix Bm, 1 the
+// indicator of the uint8 field Bu8 in every row, 2 ones.
+template <int GP, int GQ, int BM>
+__global__ __launch_bounds__(256) void k_fno_outer_mfma(const float* __restrict__ A,
+                                                        const float* __restrict__ Bm,
+                                                        const uint8_t* __restrict__ Bu8, int P,
+                                                        int Q, int64_t nvox, int64_t ntiles,
+                                                        float* __restrict__ part) {
+  constexpr int TK = kOuterTile, LS = TK + 4, TQ = TK / 4;
+  constexpr int R = 32 * (GP + GQ);
+  constexpr int NL = R * TQ / 256;  // float4 loads per thread and tile
+  constexpr int NBG = GP * GQ, KP = 4 / NBG, HALF = TK / KP / 2;
+  static_assert(R * TQ % 256 == 0 && 4 % NBG == 0, "outer tile shape");
+  extern __shared__ __align__(16) float sm[];
+  const int qgroups = (Q + 32 * GQ - 1) / (32 * GQ);
+  const int p0 = (int)(blockIdx.y / qgroups) * GP * 32, q0 = (int)(blockIdx.y % qgroups) * GQ * 32;
+  const gmem<const float>* gA = as_global(A);
+  const gmem<const float>* gB = as_global(Bm);
+  const gmem<const uint8_t>* gU = as_global(Bu8);
+
+  float4 buf[NL];
+  auto load = [&](int64_t tile) {
+    const int64_t t0 = tile * TK;
+    const int64_t b = t0 / nvox, x0 = t0 - b * nvox;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      const int e = threadIdx.x + j * 256;
+      const int row = e / TQ, c = 4 * (e % TQ);
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (row < 32 * GP) {
+        const int p = p0 + row;
+        if (p < P) v = *(const gmem<const float4>*)(gA + (b * P + p) * nvox + x0 + c);
+      } else {
+        const int q = q0 + row - 32 * GP;
+        if (q < Q) {
+          if constexpr (BM == 0) {
+            v = *(const gmem<const float4>*)(gB + (b * Q + q) * nvox + x0 + c);
+          } else if constexpr (BM == 1) {
+            const uchar4 m = *(const gmem<const uchar4>*)(gU + b * nvox + x0 + c);
+            v = make_float4(m.x ? 1.f : 0.f, m.y ? 1.f : 0.f, m.z ? 1.f : 0.f, m.w ? 1.f : 0.f);
+          } else {
+            v = make_float4(1.f, 1.f, 1.f, 1.f);
+          }
+        }
+      }
+      buf[j] = v;
+    }
+  };
+
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, r = l & 31, h = l >> 5;
+  const int bb = w % NBG, kp = w / NBG, bp = bb / GQ, bq = bb % GQ;
+  const float* pa = sm + (bp * 32 + r) * LS + kp * 2 * HALF + h * HALF;
+  const float* pb = sm + (32 * GP + bq * 32 + r) * LS + kp * 2 * HALF + h * HALF;
+  mfma_f32x16 acc = {};
+  int64_t tile = blockIdx.x;
+  if (tile < ntiles) load(tile);
+  for (; tile < ntiles; tile += gridDim.x) {
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      const int e = threadIdx.x + j * 256;
+      *reinterpret_cast<float4*>(sm + (e / TQ) * LS + 4 * (e % TQ)) = buf[j];
+    }
+    __syncthreads();
+    if (tile + gridDim.x < ntiles) load(tile + gridDim.x);
+#pragma unroll
+    for (int j = 0; j < HALF; j += 4) {
+      const float4 a = *reinterpret_cast<const float4*>(pa + j);
+      const float4 c = *reinterpret_cast<const float4*>(pb + j);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, c.x, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, c.y, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, c.z, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, c.w, acc, 0, 0, 0);
+    }
+  }
+  __syncthreads();
+  float* red = sm;  // 4 waves x 16 registers x 64 lanes
+#pragma unroll
+  for (int i = 0; i < 16; ++i) red[(w * 16 + i) * 64 + l] = acc[i];
+  __syncthreads();
+  if (w >= NBG) return;
+  const int q = q0 + bq * 32 + r;
+  float* dst = part + (int64_t)blockIdx.x * P * Q;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    float v = red[(w * 16 + i) * 64 + l];
+#pragma unroll
+    for (int k = 1; k < KP; ++k) v += red[((w + k * NBG) * 16 + i) * 64 + l];
+    const int p = p0 + bp * 32 + mix_row(i, h);
+    if (p < P && q < Q) dst[p * Q + q] = v;
+  }
+}
+
+// out[e] = sum over blocks of part[blk][e], in double: each of the 16 waves
+// of a workgroup sums a contiguous slice of the blocks for 64 entries, and the
+// slices are added in order, so the result does not depend on timing.
+constexpr int kSumWaves = 16;
+__global__ __launch_bounds__(64 * kSumWaves) void k_fno_sum_parts(const float* __restrict__ part,
+                                                                  int nblk, int n,
+                                                                  float* __restrict__ out) {
+  __shared__ double red[kSumWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane;
+  const int k0 = (int)((int64_t)nblk * w / kSumWaves);
+  const int k1 = (int)((int64_t)nblk * (w + 1) / kSumWaves);
+  double acc = 0.0;
+  if (e < n) {
+#pragma unroll 8
+    for (int k = k0; k < k1; ++k) acc += part[(int64_t)k * n + e];
+  }
+  red[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && e < n) {
+    double t = 0.0;
+#pragma unroll
+    for (int j = 0; j < kSumWaves; ++j) t += red[j][lane];
+    out[e] = (float)t;
+  }
 }
 
 // ------------------------------------------------------------------- Adam
@@ -490,27 +675,45 @@ hipError_t fno_gather(const void* spec, void* out, const int* midx, int nm, int6
   return hipGetLastError();
 }
 
+#define FNO_CHANNELS(X) X(4) X(8) X(16) X(32)
+
 hipError_t fno_mix(const void* Xm, const uint16_t* R, void* spec, const int* midx, int nm, int C,
                    int B, int64_t nspec, bool adjoint, hipStream_t s) {
-  dim3 grid((unsigned)((nm + 255) / 256), (unsigned)C, (unsigned)B);
-  if (adjoint)
-    hipLaunchKernelGGL(k_fno_mix<true>, grid, dim3(256), 0, s, (const float2*)Xm, R, (float2*)spec,
-                       midx, nm, C, nspec);
-  else
-    hipLaunchKernelGGL(k_fno_mix<false>, grid, dim3(256), 0, s, (const float2*)Xm, R,
-                       (float2*)spec, midx, nm, C, nspec);
-  return hipGetLastError();
+  switch (C) {
+#define CASE(CC)                                                                              \
+  case CC: {                                                                                  \
+    const dim3 grid((unsigned)((nm + 256 / CC - 1) / (256 / CC)));                            \
+    if (adjoint)                                                                              \
+      hipLaunchKernelGGL((k_fno_mix<true, CC>), grid, dim3(256), 0, s, (const float2*)Xm, R,  \
+                         (float2*)spec, midx, nm, B, nspec);                                  \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_fno_mix<false, CC>), grid, dim3(256), 0, s, (const float2*)Xm, R, \
+                         (float2*)spec, midx, nm, B, nspec);                                  \
+    return hipGetLastError();                                                                 \
+  }
+    FNO_CHANNELS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 hipError_t fno_dR(const void* Fm, const void* Xm, const float* mw, float* dR, int nm, int C,
                   int B, float inv_n, hipStream_t s) {
-  const int64_t total = (int64_t)nm * C * C;
-  hipLaunchKernelGGL(k_fno_dR, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                     (const float2*)Fm, (const float2*)Xm, mw, dR, nm, C, B, inv_n);
-  return hipGetLastError();
+  switch (C) {
+#define CASE(CC)                                                                             \
+  case CC:                                                                                   \
+    hipLaunchKernelGGL((k_fno_dR<CC>), dim3((unsigned)((nm + 256 / CC - 1) / (256 / CC))),   \
+                       dim3(256), 0, s, (const float2*)Fm, (const float2*)Xm, mw, dR,         \
+                       nm, B, inv_n);                                                        \
+    return hipGetLastError();
+    FNO_CHANNELS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
-#define FNO_CHANNELS(X) X(4) X(8) X(16) X(32)
 
 hipError_t fno_pointwise(int C, const float* vin, const float* k, const uint16_t* W,
                          const uint16_t* b, float* pre, float* vout, int64_t nvox, int B,
@@ -600,27 +803,54 @@ hipError_t fno_project_bwd(int C, const float* v, const float* dout, const uint1
   }
 }
 
-// G[p][q] = sum A[b][p][x] Bm[b][q][x]; `part` must hold nblk*P*Q floats.
+// G[p][q] = sum A[b][p][x] Bm[b][q][x]; `part` must hold
+// fno_outer_blocks(nvox, B) * P * Q floats.
+constexpr int kOuterMaxBlocks = 1024;
 int fno_outer_blocks(int64_t nvox, int B) {
-  const int64_t total = nvox * B;
-  int64_t nb = (total + 8191) / 8192;  // 8192 (voxel, b) pairs per block
-  return (int)std::max<int64_t>(1, std::min<int64_t>(nb, 4096));
+  const int64_t tiles = (nvox * B + kOuterTile - 1) / kOuterTile;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, kOuterMaxBlocks));
 }
 
 hipError_t fno_outer(const float* A, const float* Bm, const uint8_t* Bu8, int P, int Q,
                      int64_t nvox, int B, float* part, float* out, hipStream_t s) {
-  if (P * Q > 16 * 256) return hipErrorInvalidValue;
-  const int nb = fno_outer_blocks(nvox, B);
+  if (P < 1 || Q < 1 || P * Q > 16 * 256) return hipErrorInvalidValue;
   const int64_t total = nvox * B;
-  int64_t chunk = (total + nb - 1) / nb;
-  chunk = ((chunk + kOuterTile - 1) / kOuterTile) * kOuterTile;
-  const size_t lds = sizeof(float) * (size_t)(P + Q) * kOuterTile;
-  hipLaunchKernelGGL(k_fno_outer, dim3(nb), dim3(256), lds, s, A, Bm, Bu8, P, Q, nvox, B, chunk,
-                     part);
+  int nb;
+  const bool aligned = ((uintptr_t)A % 16 == 0) && ((uintptr_t)Bm % 16 == 0) &&
+                       ((uintptr_t)Bu8 % 4 == 0);
+  if (nvox % kOuterTile == 0 && aligned) {
+    const int PB = (P + 31) / 32, QB = (Q + 31) / 32;
+    const int GP = PB >= 4 ? 4 : (PB >= 2 ? 2 : 1);
+    const int GQ = std::min(QB >= 4 ? 4 : (QB >= 2 ? 2 : 1), 4 / GP);
+    const int64_t ntiles = total / kOuterTile;
+    nb = fno_outer_blocks(nvox, B);
+    const unsigned groups = (unsigned)(((PB + GP - 1) / GP) * ((QB + GQ - 1) / GQ));
+    const size_t lds = sizeof(float) * std::max<size_t>(32 * (GP + GQ) * (kOuterTile + 4), 4096);
+    const int bm = Bm ? 0 : (Bu8 ? 1 : 2);
+#define OUTER(GPP, GQQ, BMM)                                                              \
+  if (GP == GPP && GQ == GQQ && bm == BMM)                                                \
+    hipLaunchKernelGGL((k_fno_outer_mfma<GPP, GQQ, BMM>), dim3((unsigned)nb, groups),     \
+                       dim3(256), lds, s, A, Bm, Bu8, P, Q, nvox, ntiles, part);
+    OUTER(1, 1, 0) else OUTER(1, 2, 0) else OUTER(1, 4, 0) else OUTER(2, 1, 0)
+    else OUTER(2, 2, 0) else OUTER(4, 1, 0)
+    else OUTER(1, 1, 1) else OUTER(1, 2, 1) else OUTER(1, 4, 1) else OUTER(2, 1, 1)
+    else OUTER(2, 2, 1) else OUTER(4, 1, 1)
+    else OUTER(1, 1, 2) else OUTER(1, 2, 2) else OUTER(1, 4, 2) else OUTER(2, 1, 2)
+    else OUTER(2, 2, 2) else OUTER(4, 1, 2)
+#undef OUTER
+  } else {  // vector kernel: unaligned operands or a voxel count off the tile
+    const int64_t want = std::max<int64_t>(1, (total + 8191) / 8192);  // 8192 pairs per block
+    nb = (int)std::min<int64_t>(want, fno_outer_blocks(nvox, B));
+    int64_t chunk = (total + nb - 1) / nb;
+    chunk = ((chunk + kOuterTile - 1) / kOuterTile) * kOuterTile;
+    const size_t lds = sizeof(float) * (size_t)(P + Q) * kOuterTile;
+    hipLaunchKernelGGL(k_fno_outer, dim3(nb), dim3(256), lds, s, A, Bm, Bu8, P, Q, nvox, B, chunk,
+                       part);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fno_sum_parts, dim3((unsigned)((P * Q + 255) / 256)), dim3(256), 0, s, part,
-                     nb, P * Q, out);
+  hipLaunchKernelGGL(k_fno_sum_parts, dim3((unsigned)((P * Q + 63) / 64)), dim3(64 * kSumWaves), 0,
+                     s, part, nb, P * Q, out);
   return hipGetLastError();
 }
 

@@ -37,14 +37,18 @@ def _flat_grad(net, g):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("n,C,m,L,B", [(8, 4, 2, 2, 2), (16, 8, 3, 3, 2), (16, 32, 3, 2, 2)])
-def test_fno_forward_and_gradients_match_oracle(n, C, m, L, B):
+@pytest.mark.parametrize("n,C,m,L,B,shift", [(8, 4, 2, 2, 2, 0), (16, 8, 3, 3, 2, 0),
+                                             (16, 32, 3, 2, 2, 0), (8, 4, 2, 1, 3, 1)])
+def test_fno_forward_and_gradients_match_oracle(n, C, m, L, B, shift):
     """Forward pass and every parameter gradient against the FP64 oracle on
     the same BF16 weights.  32 channels take the matrix-core kernels of the
-    pointwise mix (the width the warm start trains), fewer the vector ones."""
+    pointwise mix (the width the warm start trains), fewer the vector ones.
+    The weight-gradient sums run on the matrix cores for 16-byte aligned
+    operands; `shift` = 1 hands dout over one float off that alignment, which
+    sends the sums over dout to the vector kernel."""
     require_gpu()
     from paper_2312_15554_amd.fno import FNO
-    print(f"fno grad check n={n} C={C} m={m} L={L} B={B}", flush=True)
+    print(f"fno grad check n={n} C={C} m={m} L={L} B={B} shift={shift}", flush=True)
     net = FNO(channels=C, hidden=6, modes=m, layers=L, seed=5)
     # larger spectral weights than the training initialisation so that the
     # spectral path carries a visible share of the output
@@ -61,7 +65,11 @@ def test_fno_forward_and_gradients_match_oracle(n, C, m, L, B):
     scale = np.abs(ref).max()
     assert np.abs(host(out) - ref).max() < 2e-5 * scale
     dout_n = I.random_field((B, 4, n, n, n), 77)
-    g = net.backward(H, dev(dout_n, torch.float32))
+    flat = torch.zeros(dout_n.size + shift, dtype=torch.float32, device="cuda")
+    flat[shift:] = dev(dout_n.reshape(-1), torch.float32)
+    dout = flat[shift:].view(dout_n.shape)
+    assert (dout.data_ptr() % 16 == 0) == (shift == 0)
+    g = net.backward(H, dout)
     gref = _flat_grad(net, F.backward(p, cache, dout_n))
     gg = host(g).astype(np.float64)
     for name, (o, size) in net.layout().items():
