@@ -306,6 +306,8 @@ acm_status acm_fft_c2r(const acm_grid* grid, int32_t precision, int32_t nfields,
  * complex as (re,im), W[C][C], b[C] | Q1[Cp][C] c1[Cp] Q2[4][Cp] c2[4],
  * nm = (2m)^2 m); kernels read the BF16 copy, Adam updates the FP32 master
  * and refreshes the BF16 copy.  Activations and accumulations are FP32.
+ * params_bf16 must be 4-byte aligned (the mode weights are read as (re, im)
+ * pairs); otherwise the call returns ACM_E_INVALID.
  * Grids must be cubic 3D with n in the supported set, channels in
  * {4, 8, 16, 32}, hidden * channels <= 4096, 2 * modes <= n.
  * H: uint8 [batch][n^3]; out, dout: float [batch][4][n^3] (device).

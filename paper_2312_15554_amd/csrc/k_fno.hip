@@ -77,7 +77,9 @@ __global__ __launch_bounds__(256) void k_fno_mix(const float2* __restrict__ Xm,
   const int j0 = blockIdx.x * JT;
   const int nj = min(JT, nm - j0);
   const uint32_t* gR = reinterpret_cast<const uint32_t*>(R) + (int64_t)j0 * C * C;
-  for (int e = threadIdx.x; e < nj * C * C; e += 256) sR[(e / C) * RS + e % C] = gR[e];
+  batched_copy<uint32_t, 256, JT * C * C>(
+      nj * C * C, [&](int e) { return gR[e]; },
+      [&](int e, const uint32_t& w) { sR[(e / C) * RS + e % C] = w; });
   const int c = threadIdx.x / JT, jj = threadIdx.x % JT;
   const bool live = jj < nj;
   const int64_t sidx = live ? midx[j0 + jj] : 0;
@@ -93,10 +95,16 @@ __global__ __launch_bounds__(256) void k_fno_mix(const float2* __restrict__ Xm,
   for (int b0 = 0; b0 < B; b0 += BT) {
     const int nb = min(BT, B - b0);
     __syncthreads();
-    for (int e = threadIdx.x; e < nb * C * JT; e += 256) {
-      const int jx = e % JT, bi = e / JT;  // bi = (batch member in chunk) * C + channel
-      sX[e] = jx < nj ? Xm[((int64_t)b0 * C + bi) * nm + j0 + jx] : make_float2(0.f, 0.f);
-    }
+    // e = ((batch member in chunk) * C + channel) * JT + mode in tile
+    batched_copy<float2, 256, BT * C * JT>(
+        nb * C * JT,
+        [&](int e) {
+          const int jx = e % JT, bi = e / JT;
+          float2 v = make_float2(0.f, 0.f);
+          if (jx < nj) v = Xm[((int64_t)b0 * C + bi) * nm + j0 + jx];
+          return v;
+        },
+        [&](int e, const float2& v) { sX[e] = v; });
     __syncthreads();
     if (!live) continue;
     for (int bb = 0; bb < nb; ++bb) {
@@ -130,8 +138,10 @@ __global__ __launch_bounds__(256) void k_fno_dR(const float2* __restrict__ Fm,
                                                 float inv_n) {
   constexpr int JT = 256 / C, JS = JT + 1, BT = 8, PER = JT * C * C / 256;
   __shared__ float2 sF[BT * C * JS], sX[BT * C * JS];
+  __shared__ float smw[JT];
   const int j0 = blockIdx.x * JT;
   const int nj = min(JT, nm - j0);
+  if (threadIdx.x < JT) smw[threadIdx.x] = threadIdx.x < nj ? mw[j0 + threadIdx.x] * inv_n : 0.f;
   float ar[PER], ai[PER];
 #pragma unroll
   for (int k = 0; k < PER; ++k) ar[k] = ai[k] = 0.f;
@@ -167,7 +177,7 @@ __global__ __launch_bounds__(256) void k_fno_dR(const float2* __restrict__ Fm,
     const int e = threadIdx.x + k * 256;
     const int jj = e / (C * C);
     if (jj < nj) {
-      const float sc = mw[j0 + jj] * inv_n;
+      const float sc = smw[jj];
       const int64_t t = (int64_t)j0 * C * C + e;
       dR[2 * t] = ar[k] * sc;
       dR[2 * t + 1] = ai[k] * sc;

@@ -1897,6 +1897,7 @@ acm_status acm_fno_forward(const acm_fno_shape* shape, const acm_grid* grid, int
                            void* stream) {
   g_err.clear();
   if (!params_bf16 || !H || !out || !workspace) return fail(ACM_E_INVALID, "null argument");
+  if ((uintptr_t)params_bf16 % 4 != 0) return fail(ACM_E_INVALID, "params_bf16 must be 4-byte aligned");
   FnoLayout f;
   CellPlan* pl = nullptr;
   acm_status r = fno_check(shape, grid, batch, &pl, &f);
@@ -1918,6 +1919,7 @@ acm_status acm_fno_backward(const acm_fno_shape* shape, const acm_grid* grid, in
                             float* grad, void* workspace, int64_t workspace_bytes, void* stream) {
   g_err.clear();
   if (!params_bf16 || !H || !dout || !grad || !workspace) return fail(ACM_E_INVALID, "null argument");
+  if ((uintptr_t)params_bf16 % 4 != 0) return fail(ACM_E_INVALID, "params_bf16 must be 4-byte aligned");
   FnoLayout f;
   CellPlan* pl = nullptr;
   acm_status r = fno_check(shape, grid, batch, &pl, &f);

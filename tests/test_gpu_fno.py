@@ -79,6 +79,32 @@ def test_fno_forward_and_gradients_match_oracle(n, C, m, L, B, shift):
 
 
 @pytest.mark.gpu
+def test_fno_rejects_misaligned_weights():
+    """The mode weights are read as (re, im) BF16 pairs, so a parameter array
+    off 4-byte alignment is refused before any work is queued; the aligned
+    array runs."""
+    require_gpu()
+    import ctypes as C
+    from paper_2312_15554_amd.api import _grid
+    from paper_2312_15554_amd.fno import FNO
+    n, B = 8, 1
+    net = FNO(channels=4, hidden=6, modes=2, layers=1, seed=2)
+    H = dev(I.random_mask((B, n, n, n), 4, 0.4))
+    out = torch.empty((B, 4, n, n, n), dtype=torch.float32, device="cuda")
+    ws = net.workspace(n, B, False)
+    gr = _grid((n, n, n))
+    shifted = torch.zeros(net.bf16.numel() + 1, dtype=net.bf16.dtype, device="cuda")
+    shifted[1:] = net.bf16
+    args = lambda p: (C.byref(net.shape), C.byref(gr), B, p, H.data_ptr(), out.data_ptr(),
+                      ws.data_ptr(), ws.numel(), 0, None)
+    assert net.lib.acm_fno_forward(*args(shifted.data_ptr() + 2)) == -1
+    assert b"aligned" in net.lib.acm_last_error()
+    assert net.lib.acm_fno_forward(*args(net.bf16.data_ptr())) == 0
+    torch.cuda.synchronize()
+    assert torch.isfinite(out).all()
+
+
+@pytest.mark.gpu
 def test_fno_adam_step_decreases_loss():
     require_gpu()
     from paper_2312_15554_amd.fno import FNO
