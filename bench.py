@@ -498,7 +498,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(independent cells or directions would shard one per GPU, see DESIGN.md).",
+              "(independent cells or flow directions would shard one per GPU, each GPU "
+              "running this single-GPU path on its share).",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np

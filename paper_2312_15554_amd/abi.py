@@ -101,8 +101,8 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(
-            f"{path} is not built: run __graft_entry__.build() (or python -m "
-            "paper_2312_15554_amd.build).  There is no CPU fallback.")
+            f"{path} is not built: run python -m paper_2312_15554_amd.build.  "
+            "There is no CPU fallback.")
     lib = C.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
