@@ -37,19 +37,23 @@ def _flat_grad(net, g):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("n,C,m,L,B,shift", [(8, 4, 2, 2, 2, 0), (16, 8, 3, 3, 2, 0),
-                                             (16, 32, 3, 2, 2, 0), (8, 4, 2, 1, 3, 1)])
-def test_fno_forward_and_gradients_match_oracle(n, C, m, L, B, shift):
+@pytest.mark.parametrize("n,C,m,L,B,shift,hidden", [
+    (8, 4, 2, 2, 2, 0, 6), (16, 8, 3, 3, 2, 0, 6), (16, 32, 3, 2, 2, 0, 6), (8, 4, 2, 1, 3, 1, 6),
+    (8, 8, 2, 1, 2, 0, 40), (8, 16, 2, 1, 2, 0, 200)])
+def test_fno_forward_and_gradients_match_oracle(n, C, m, L, B, shift, hidden):
     """Forward pass and every parameter gradient against the FP64 oracle on
     the same BF16 weights.  32 channels take the matrix-core kernels of the
     pointwise mix (the width the warm start trains), fewer the vector ones.
     The weight-gradient sums run on the matrix cores for 16-byte aligned
     operands; `shift` = 1 hands dout over one float off that alignment, which
-    sends the sums over dout to the vector kernel."""
+    sends the sums over dout to the vector kernel.  The projection widths 40
+    and 200 give those sums two 32-row blocks per workgroup (40 rows), and
+    more blocks than one workgroup owns (200 rows: two groups of four along
+    P for dQ1 and along Q for dQ2), each with a ragged last block."""
     require_gpu()
     from paper_2312_15554_amd.fno import FNO
-    print(f"fno grad check n={n} C={C} m={m} L={L} B={B} shift={shift}", flush=True)
-    net = FNO(channels=C, hidden=6, modes=m, layers=L, seed=5)
+    print(f"fno grad check n={n} C={C} m={m} L={L} B={B} shift={shift} hidden={hidden}", flush=True)
+    net = FNO(channels=C, hidden=hidden, modes=m, layers=L, seed=5)
     # larger spectral weights than the training initialisation so that the
     # spectral path carries a visible share of the output
     with torch.no_grad():
