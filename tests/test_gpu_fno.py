@@ -39,7 +39,7 @@ def _flat_grad(net, g):
 @pytest.mark.gpu
 @pytest.mark.parametrize("n,C,m,L,B,shift,hidden", [
     (8, 4, 2, 2, 2, 0, 6), (16, 8, 3, 3, 2, 0, 6), (16, 32, 3, 2, 2, 0, 6), (8, 4, 2, 1, 3, 1, 6),
-    (8, 8, 2, 1, 2, 0, 40), (8, 16, 2, 1, 2, 0, 200)])
+    (8, 8, 2, 1, 2, 0, 40), (8, 16, 2, 1, 2, 0, 200), (8, 8, 2, 2, 11, 0, 6)])
 def test_fno_forward_and_gradients_match_oracle(n, C, m, L, B, shift, hidden):
     """Forward pass and every parameter gradient against the FP64 oracle on
     the same BF16 weights.  32 channels take the matrix-core kernels of the
@@ -49,7 +49,9 @@ def test_fno_forward_and_gradients_match_oracle(n, C, m, L, B, shift, hidden):
     sends the sums over dout to the vector kernel.  The projection widths 40
     and 200 give those sums two 32-row blocks per workgroup (40 rows), and
     more blocks than one workgroup owns (200 rows: two groups of four along
-    P for dQ1 and along Q for dQ2), each with a ragged last block."""
+    P for dQ1 and along Q for dQ2), each with a ragged last block.  A batch
+    of 11 takes the mode mix, its adjoint and the spectral gradient through a
+    full chunk of eight cells and a ragged one of three."""
     require_gpu()
     from paper_2312_15554_amd.fno import FNO
     print(f"fno grad check n={n} C={C} m={m} L={L} B={B} shift={shift} hidden={hidden}", flush=True)
